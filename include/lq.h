@@ -1,0 +1,212 @@
+/*
+ * lq.h -- C ABI of the MI355X (gfx950) Wilson / Wilson-clover fermion-matrix
+ * library: the fermion matrix of eq. (1), Sec. 3 of Akahoshi et al.,
+ * "General purpose lattice QCD code set Bridge++ 2.0 for high performance
+ * computing" (arXiv:2111.04457), its even-odd Schur form, and the Krylov
+ * solvers that compute quark propagators with it (Sec. 2, Fig. 1).
+ *
+ * The calls follow the usage of the paper's Fig. 1: an operator object is
+ * created from fermion parameters (params_fopr), given a gauge field
+ * (set_config), applied in a mode (set_mode: D, Ddag, DdagD, ...), and
+ * inverted to a tolerance with a mixed-precision solver (invert(x, b, nconv,
+ * diff)).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  dims      (Lx, Ly, Lz, Lt), each even and >= 2.  V = Lx Ly Lz Lt.
+ *  lex site  x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2 (even = 0).
+ *  gauge     complex128 U[t][z][y][x][mu][a][b], mu = 0..3 for x, y, z, t;
+ *            (U psi)_a = sum_b U_ab psi_b.  Links must be SU(3) when 12-real
+ *            compression is used.
+ *  spinor    full field: complex128 [V][4 spin][3 colour] in lex order
+ *            (spin-colour index ic + 3*is, as in Fig. 1);
+ *            parity field: complex128 [V/2][4][3] in checkerboard order
+ *            cb = lex / 2 (integer division), holding the sites of one parity.
+ *            Several right-hand sides are stacked on a leading axis [nrhs].
+ *  gamma     chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+ *            gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1).
+ *  boundary  a hop x -> x+mu across the lattice edge is multiplied by the
+ *            phase bc[mu] (|bc| = 1); the backward hop by its conjugate
+ *            (the paper: a boundary condition imposed in each direction).
+ *  clover    F(x) = -c_sw kappa sum_{mu<nu} gamma_mu gamma_nu (x) Fhat_{mu nu}(x),
+ *            Fhat = (Q - Q^dag)/8 of the four counter-clockwise plaquettes Q
+ *            at x (colour trace removed unless clover_traceless = 0).  In
+ *            the chiral basis A = 1 + F is two 6x6 Hermitian blocks.
+ *  even-odd  D = [[A_ee, -kappa H_eo], [-kappa H_oe, A_oo]] with H the
+ *            hopping sum of eq. (1); Schur operator
+ *            M = A_ee - kappa^2 H_eo A_oo^-1 H_oe on even sites.
+ *
+ * Memory and streams
+ * ------------------
+ *  Every spinor / gauge pointer is a DEVICE pointer owned by the caller and
+ *  borrowed for the duration of the call.  The library owns the device
+ *  copies it makes (packed links and clover in every precision, solver
+ *  work vectors), allocated in lq_op_create / lq_field_create / on first
+ *  solve, and freed by the matching destroy.  `stream` is a hipStream_t
+ *  (NULL = the default stream); every call is ordered on it.  Calls that
+ *  return host results (solves, forces, norms) synchronize the stream.
+ *  An lq_op is not thread-safe: calls on one lq_op must not overlap.
+ *
+ * Errors
+ * ------
+ *  Every call returns an lq_status.  Negative values are errors (outputs
+ *  unspecified); LQ_NOT_CONVERGED (+1) means the solution, nconv and diff
+ *  were still filled.  Arguments are validated on the host before any
+ *  device work.  lq_last_error() returns a message for the calling thread's
+ *  last failure.
+ */
+#ifndef LQ_H
+#define LQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lq_op lq_op;
+typedef struct lq_field lq_field;
+
+typedef enum {
+    LQ_OK = 0,
+    LQ_NOT_CONVERGED = 1,
+    LQ_ERR_ARG = -1,
+    LQ_ERR_STATE = -2,
+    LQ_ERR_HIP = -3,
+    LQ_ERR_NOMEM = -4,
+    LQ_ERR_SINGULAR = -5,
+    LQ_ERR_NONFINITE = -6,
+    LQ_ERR_NODEVICE = -7
+} lq_status;
+
+/* Storage precision of packed fields.  LQ_F16 stores links as IEEE binary16
+ * and spinors as binary16 with one FP32 scale per site; arithmetic is FP32. */
+typedef enum { LQ_F64 = 0, LQ_F32 = 1, LQ_F16 = 2 } lq_prec;
+
+/* Operator kinds (the set_mode analogue of Fig. 1).
+ * Full-lattice kinds act on full fields, the others on parity fields. */
+typedef enum {
+    LQ_D = 0,             /* D of eq. (1)                          full */
+    LQ_DDAG = 1,          /* D^dag                                 full */
+    LQ_DDAGD = 2,         /* D^dag D                               full */
+    LQ_SCHUR = 3,         /* M = A_ee - kappa^2 H_eo A_oo^-1 H_oe   even -> even */
+    LQ_SCHUR_DAG = 4,     /* M^dag                                 even -> even */
+    LQ_SCHUR_NORMAL = 5,  /* M^dag M                               even -> even */
+    LQ_HOP_EO = 6,        /* H_eo (odd -> even)                    */
+    LQ_HOP_OE = 7,        /* H_oe (even -> odd)                    */
+    LQ_HOP_EO_DAG = 8,    /* (H_oe)^dag (odd -> even)              */
+    LQ_HOP_OE_DAG = 9,    /* (H_eo)^dag (even -> odd)              */
+    LQ_CLOVER_E = 10,     /* A_ee                                  even -> even */
+    LQ_CLOVER_O = 11,     /* A_oo                                  odd -> odd */
+    LQ_CLOVER_INV_O = 12  /* A_oo^-1                               odd -> odd */
+} lq_kind;
+
+typedef enum { LQ_CGNE = 0, LQ_BICGSTAB = 1 } lq_solver_kind;
+
+/* Fermion parameters (params_fopr of Fig. 1). */
+typedef struct {
+    int dims[4];          /* Lx, Ly, Lz, Lt: even, >= 2 */
+    double kappa;         /* hopping parameter, kappa = 1/(8 + 2 m0); finite */
+    double csw;           /* clover coefficient; 0 = Wilson (F = 0) */
+    double bc[4][2];      /* boundary phase per direction as (re, im), |phase| = 1 */
+    int clover_traceless; /* 1 (default): colour trace of Fhat removed */
+    int link_recon;       /* 18 or 12: reals per link in the FP32/FP16 copies */
+} lq_op_params;
+
+/* Solver parameters (params_solver of Fig. 1). */
+typedef struct {
+    int solver;           /* lq_solver_kind */
+    double tol;           /* target true relative residual |b - D x| / |b| (FP64) */
+    int max_iter;         /* cap on total inner Krylov iterations */
+    int inner;            /* lq_prec of the inner solve; LQ_F64 = plain FP64 solve */
+    double inner_tol;     /* residual reduction asked of each inner solve (mixed) */
+    int max_outer;        /* cap on FP64 defect-correction steps */
+    int check_every;      /* inner iterations between host convergence checks */
+    int even_odd;         /* 1: solve the Schur system (default); 0: full lattice (CGNE only) */
+} lq_solver_params;
+
+/* Per-system solve statistics (nconv and diff of Fig. 1's invert). */
+typedef struct {
+    int nconv;            /* total inner Krylov iterations */
+    int nouter;           /* FP64 defect-correction steps */
+    int restarts;         /* Krylov restarts after breakdown */
+    int converged;        /* 1 if diff <= tol */
+    double diff;          /* true residual |b - D x|_2 / |b|_2 in FP64 (not squared) */
+    double t_solve_ms;    /* wall time of the solve (all systems of the call together) */
+    double hop_bytes;     /* algorithmic bytes of the hopping-term applies of the call
+                             (lq_op_traffic per apply), all systems together */
+    int n_hop;            /* parity hopping-term applies of the call, all precisions */
+} lq_solve_stats;
+
+/* Defaults: lq_op_params with kappa = 0.125, csw = 0, periodic phases,
+ * traceless clover, 18-real links; lq_solver_params with BiCGStab,
+ * tol 1e-10, FP32 inner, inner_tol 1e-5, even-odd. */
+void lq_op_params_default(lq_op_params *p);
+void lq_solver_params_default(lq_solver_params *p);
+
+/* Version string of the library. */
+const char *lq_version(void);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char *lq_last_error(void);
+
+/* Create an operator for the parameters (validated on the host: even dims
+ * >= 2, finite kappa and csw, |bc| = 1, link_recon in {12, 18}); allocates
+ * the device copies.  LQ_ERR_NODEVICE if no gfx950 device is visible. */
+lq_status lq_op_create(const lq_op_params *p, lq_op **out);
+void lq_op_destroy(lq_op *op);
+
+/* Set the gauge field (set_config of Fig. 1).  U: device complex128 in the
+ * gauge layout.  Packs FP64, FP32 and FP16 copies (even/odd split, SoA),
+ * builds A = 1 + F and A_oo^-1 in FP64 and down-converts them.
+ * LQ_ERR_SINGULAR if a clover block is not invertible. */
+lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream);
+
+/* Change kappa, csw and the boundary phases; rebuilds the clover term from
+ * the stored links.  bc may be NULL to keep the phases. */
+lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[4][2], void *stream);
+
+/* out = K in for kind K with packed storage/arithmetic precision prec.
+ * in, out: device complex128 in the full or parity spinor layout of K,
+ * nrhs right-hand sides stacked; in != out.  Full-lattice kinds use FP64
+ * only at the boundary; prec selects the internal precision. */
+lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
+                      void *stream);
+
+/* Device-resident parity spinor fields in the library's packed layout
+ * (structure of arrays over checkerboard sites, nrhs stacked), for applying
+ * kinds >= LQ_SCHUR without packing at every call. */
+lq_status lq_field_create(lq_op *op, lq_prec prec, int nrhs, lq_field **out);
+void lq_field_destroy(lq_field *f);
+/* Import from / export to a device complex128 parity field [nrhs][V/2][4][3]. */
+lq_status lq_field_import(lq_field *f, const void *src, void *stream);
+lq_status lq_field_export(const lq_field *f, void *dst, void *stream);
+/* out = K in on packed fields of the same precision and nrhs (K >= LQ_SCHUR). */
+lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_field *in, void *stream);
+
+/* Workgroup size (64, 128 or 256 threads) of the hopping kernels of
+ * precision prec on this operator.  The result does not depend on it: every
+ * site is summed in the same order whatever the launch shape. */
+lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
+
+/* Algorithmic HBM bytes and flops of one parity hopping-term apply per
+ * output site and right-hand side for the given precision, with (clover = 1)
+ * or without the fused clover epilogue: compulsory traffic only (8 links,
+ * one input and one output spinor, clover block if used). */
+lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, double *bytes_per_site,
+                        double *flops_per_site);
+
+/* Solve op x = b for mode LQ_D, LQ_DDAG or LQ_DDAGD (invert of Fig. 1) for
+ * nrhs right-hand sides at once (multi-RHS kernels reuse every loaded link
+ * across the right-hand sides).  b, x: device complex128 full fields
+ * [nrhs][V][4][3]; x is the initial guess if use_x0, and is overwritten by
+ * the solution.  stats: host array of nrhs entries (may be NULL).
+ * Returns LQ_OK, LQ_NOT_CONVERGED (x and stats filled), or an error;
+ * LQ_ERR_NONFINITE if b or an intermediate residual is not finite. */
+lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
+                   int use_x0, lq_solve_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQ_H */

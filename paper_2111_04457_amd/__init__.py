@@ -1,0 +1,16 @@
+"""MI355X (gfx950) library for the Wilson / Wilson-clover fermion matrix of
+eq. (1) of the Bridge++ 2.0 paper (arXiv:2111.04457) and its Krylov solvers.
+
+The compute path is the HIP library liblq.so behind the C ABI of
+include/lq.h; this package only marshals torch tensors and streams to it.
+"""
+from ._lib import LQError, load  # noqa: F401
+
+__all__ = ["Operator", "Field", "SolverParams", "SolveStats", "apply_field", "LQError", "load"]
+
+
+def __getattr__(name):
+    if name in ("Operator", "Field", "SolverParams", "SolveStats", "apply_field"):
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

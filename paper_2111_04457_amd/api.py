@@ -1,0 +1,203 @@
+"""Python binding of the C ABI (include/lq.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch supplies device memory
+(complex128 CUDA tensors) and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _bc_array(bc):
+    if bc is None:
+        bc = (1, 1, 1, 1)
+    arr = ((ctypes.c_double * 2) * 4)()
+    for i, v in enumerate(bc):
+        v = complex(*v) if isinstance(v, (tuple, list)) else complex(v)
+        arr[i][0] = v.real
+        arr[i][1] = v.imag
+    return arr
+
+
+def _dev(t: torch.Tensor, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.device.type != "cuda":
+        raise TypeError("%s must be a complex128 CUDA tensor" % name)
+    if tuple(t.shape[-len(shape):]) != tuple(shape):
+        raise ValueError("%s has shape %s, expected [..., %s]" % (name, tuple(t.shape), shape))
+    return t.contiguous()
+
+
+@dataclass
+class SolverParams:
+    """params_solver of the paper's Fig. 1."""
+    solver: str = "bicgstab"     # "bicgstab" | "cgne"
+    tol: float = 1e-10           # true relative residual |b - D x| / |b|
+    max_iter: int = 100000
+    inner: str = "f32"           # "f64" (plain FP64 solve), "f32", "f16"
+    inner_tol: float = 1e-5
+    max_outer: int = 100
+    check_every: int = 8
+    even_odd: bool = True
+
+    def to_c(self) -> _lib.SolverParams:
+        p = _lib.SolverParams()
+        load().lq_solver_params_default(ctypes.byref(p))
+        p.solver = {"cgne": _lib.CGNE, "bicgstab": _lib.BICGSTAB}[self.solver]
+        p.tol = self.tol
+        p.max_iter = self.max_iter
+        p.inner = _lib.PREC[self.inner]
+        p.inner_tol = self.inner_tol
+        p.max_outer = self.max_outer
+        p.check_every = self.check_every
+        p.even_odd = int(bool(self.even_odd))
+        return p
+
+
+@dataclass
+class SolveStats:
+    nconv: int
+    nouter: int
+    restarts: int
+    converged: bool
+    diff: float
+    t_solve_ms: float
+    hop_bytes: float
+    n_hop: int
+
+
+class Operator:
+    """The fermion matrix of eq. (1) on one gauge field (params_fopr +
+    set_config of Fig. 1)."""
+
+    def __init__(self, dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18):
+        lib = load()
+        p = _lib.OpParams()
+        lib.lq_op_params_default(ctypes.byref(p))
+        for i in range(4):
+            p.dims[i] = int(dims[i])
+        p.kappa = float(kappa)
+        p.csw = float(csw)
+        p.bc = _bc_array(bc)
+        p.clover_traceless = int(bool(traceless))
+        p.link_recon = int(link_recon)
+        h = ctypes.c_void_p()
+        check(lib.lq_op_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.full_shape = tuple(self.dims[::-1]) + (4, 3)
+        self.parity_shape = (self.V // 2, 4, 3)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lq_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_gauge(self, U: torch.Tensor):
+        U = _dev(U, self.dims[::-1] + (4, 3, 3), "U")
+        check(load().lq_op_set_gauge(self._h, ctypes.c_void_p(U.data_ptr()), _stream()))
+
+    def set_params(self, kappa, csw, bc=None):
+        arr = None if bc is None else _bc_array(bc)
+        check(load().lq_op_set_params(self._h, float(kappa), float(csw),
+                                      None if arr is None else ctypes.byref(arr), _stream()))
+
+    def apply(self, kind: str, psi: torch.Tensor, prec: str = "f64") -> torch.Tensor:
+        """out = K psi for K in D, Ddag, DdagD (full fields) or the parity kinds."""
+        full = kind in _lib.FULL_KINDS
+        shape = self.full_shape if full else self.parity_shape
+        psi = _dev(psi, shape, "psi")
+        nrhs = psi.numel() // (12 * (self.V if full else self.V // 2))
+        out = torch.empty_like(psi)
+        check(load().lq_op_apply(self._h, _lib.KINDS[kind], _lib.PREC[prec], ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(psi.data_ptr()), nrhs, _stream()))
+        return out
+
+    def traffic(self, prec="f32", nrhs=1, clover=False):
+        b = ctypes.c_double()
+        f = ctypes.c_double()
+        check(load().lq_op_traffic(self._h, _lib.PREC[prec], int(nrhs), int(bool(clover)), ctypes.byref(b),
+                                   ctypes.byref(f)))
+        return b.value, f.value
+
+    def solve(self, b: torch.Tensor, mode: str = "D", params: SolverParams | None = None,
+              x0: torch.Tensor | None = None):
+        """x = mode^-1 b for mode D, Ddag or DdagD (invert of Fig. 1).
+        b: [nrhs?, Lt, Lz, Ly, Lx, 4, 3] complex128.  Returns (x, [SolveStats])."""
+        params = params or SolverParams()
+        b = _dev(b, self.full_shape, "b")
+        nrhs = b.numel() // (12 * self.V)
+        if x0 is not None:
+            x = _dev(x0, self.full_shape, "x0").clone()
+        else:
+            x = torch.zeros_like(b)
+        stats = (_lib.SolveStats * nrhs)()
+        cp = params.to_c()
+        st = load().lq_solve(self._h, ctypes.byref(cp), _lib.KINDS[mode], nrhs, ctypes.c_void_p(x.data_ptr()),
+                             ctypes.c_void_p(b.data_ptr()), int(x0 is not None), stats, _stream())
+        check(st, allow_not_converged=True)
+        out = [SolveStats(s.nconv, s.nouter, s.restarts, bool(s.converged), s.diff, s.t_solve_ms, s.hop_bytes, s.n_hop)
+               for s in stats]
+        return x, out
+
+
+class Field:
+    """A device-resident parity spinor field in the library's packed layout."""
+
+    def __init__(self, op: Operator, prec: str = "f32", nrhs: int = 1):
+        h = ctypes.c_void_p()
+        check(load().lq_field_create(op.handle, _lib.PREC[prec], int(nrhs), ctypes.byref(h)))
+        self._h = h
+        self.op = op
+        self.prec = prec
+        self.nrhs = nrhs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lq_field_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load(self, src: torch.Tensor):
+        src = _dev(src, self.op.parity_shape, "src")
+        if src.numel() != self.nrhs * 12 * (self.op.V // 2):
+            raise ValueError("src holds a different number of right-hand sides")
+        check(load().lq_field_import(self._h, ctypes.c_void_p(src.data_ptr()), _stream()))
+
+    def read(self) -> torch.Tensor:
+        out = torch.empty((self.nrhs,) + self.op.parity_shape, dtype=torch.complex128, device="cuda")
+        check(load().lq_field_export(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out if self.nrhs > 1 else out[0]
+
+
+def apply_field(op: Operator, kind: str, out: Field, inp: Field):
+    check(load().lq_op_apply_field(op.handle, _lib.KINDS[kind], out.handle, inp.handle, _stream()))

@@ -1,0 +1,345 @@
+// abi.hip -- the extern "C" entry points declared in include/lq.h.
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+using namespace lq;
+
+#define LQ_VERSION_STRING "lq-mi355x 0.1 (gfx950)"
+
+// Run body, turning Failure / std exceptions into a status + message.
+template <typename F>
+static lq_status guarded(F &&body)
+{
+    try {
+        set_error("");
+        return body();
+    } catch (const Failure &f) {
+        set_error(f.msg);
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return LQ_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return LQ_ERR_STATE;
+    }
+}
+
+static lq_status arg_error(const std::string &msg)
+{
+    set_error(msg);
+    return LQ_ERR_ARG;
+}
+
+static bool valid_prec(int p) { return p == LQ_F64 || p == LQ_F32 || p == LQ_F16; }
+
+static void select_device(lq_op *op) { LQ_HIP(hipSetDevice(op->device)); }
+
+extern "C" {
+
+void lq_op_params_default(lq_op_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    for (int i = 0; i < 4; ++i) {
+        p->dims[i] = 4;
+        p->bc[i][0] = 1.0;
+        p->bc[i][1] = 0.0;
+    }
+    p->kappa = 0.125;
+    p->csw = 0.0;
+    p->clover_traceless = 1;
+    p->link_recon = 18;
+}
+
+void lq_solver_params_default(lq_solver_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->solver = LQ_BICGSTAB;
+    p->tol = 1e-10;
+    p->max_iter = 100000;
+    p->inner = LQ_F32;
+    p->inner_tol = 1e-5;
+    p->max_outer = 100;
+    p->check_every = 8;
+    p->even_odd = 1;
+}
+
+const char *lq_version(void) { return LQ_VERSION_STRING; }
+
+const char *lq_last_error(void) { return get_error(); }
+
+lq_status lq_op_create(const lq_op_params *p, lq_op **out)
+{
+    if (!p || !out) return arg_error("lq_op_create: null argument");
+    *out = nullptr;
+    long vol = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (p->dims[i] < 2 || (p->dims[i] & 1))
+            return arg_error("lq_op_create: every dimension must be even and >= 2");
+        vol *= p->dims[i];
+    }
+    if (vol > (1L << 30)) return arg_error("lq_op_create: volume above 2^30 sites");
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->csw)) return arg_error("lq_op_create: kappa and csw must be finite");
+    for (int i = 0; i < 4; ++i) {
+        const double m = std::hypot(p->bc[i][0], p->bc[i][1]);
+        if (!(std::fabs(m - 1.0) < 1e-12)) return arg_error("lq_op_create: boundary phases must have modulus 1");
+    }
+    if (p->link_recon != 18 && p->link_recon != 12) return arg_error("lq_op_create: link_recon must be 12 or 18");
+    return guarded([&]() -> lq_status {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+            (void)hipGetLastError();
+            set_error("lq_op_create: no HIP device visible");
+            return LQ_ERR_NODEVICE;
+        }
+        int dev = 0;
+        LQ_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        LQ_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            set_error(std::string("lq_op_create: device is ") + prop.gcnArchName + ", this library is built for gfx950");
+            return LQ_ERR_NODEVICE;
+        }
+        lq_op *op = new lq_op();
+        op->prm = *p;
+        op->device = dev;
+        Geom &g = op->g;
+        for (int i = 0; i < 4; ++i) {
+            g.L[i] = p->dims[i];
+            g.bc_re[i] = p->bc[i][0];
+            g.bc_im[i] = p->bc[i][1];
+        }
+        g.lxh = p->dims[0] / 2;
+        g.vh = (int)(vol / 2);
+        op->has_clover = p->csw != 0.0;
+        try {
+            op->links[F64].ensure(8 * link_bytes(F64, 18, g.vh));
+            op->links[F32].ensure(8 * link_bytes(F32, p->link_recon, g.vh));
+            op->links[F16].ensure(8 * link_bytes(F16, p->link_recon, g.vh));
+            op->flag.ensure(sizeof(int));
+        } catch (...) {
+            delete op;
+            throw;
+        }
+        *out = op;
+        return LQ_OK;
+    });
+}
+
+void lq_op_destroy(lq_op *op)
+{
+    if (!op) return;
+    (void)hipSetDevice(op->device);
+    (void)hipDeviceSynchronize();
+    delete op;
+}
+
+static void build_clover(lq_op *op, hipStream_t s)
+{
+    const Geom &g = op->g;
+    if (!op->has_clover) return;
+    for (int p = 0; p < 3; ++p) {
+        op->clov[p].ensure(2 * clover_bytes(p, g.vh));
+        op->clovinv[p].ensure(2 * clover_bytes(p, g.vh));
+    }
+    LQ_HIP(launch_clover_build(g, op->links[F64].ptr, op->prm.csw, op->prm.kappa, op->prm.clover_traceless,
+                               op->clov[F64].ptr, s));
+    LQ_HIP(hipMemsetAsync(op->flag.ptr, 0, sizeof(int), s));
+    LQ_HIP(launch_clover_invert(g, op->clov[F64].ptr, op->clovinv[F64].ptr, reinterpret_cast<int *>(op->flag.ptr), s));
+    for (int p = F32; p <= F16; ++p) {
+        LQ_HIP(launch_convert_clover(g, op->clov[F64].ptr, p, op->clov[p].ptr, s));
+        LQ_HIP(launch_convert_clover(g, op->clovinv[F64].ptr, p, op->clovinv[p].ptr, s));
+    }
+    int flag = 0;
+    LQ_HIP(hipMemcpyAsync(&flag, op->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    LQ_HIP(hipStreamSynchronize(s));
+    if (flag) throw Failure{LQ_ERR_SINGULAR, "a clover block A = 1 + F is singular"};
+}
+
+lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream)
+{
+    if (!op || !U) return arg_error("lq_op_set_gauge: null argument");
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const Geom &g = op->g;
+        op->gauge_set = false;
+        LQ_HIP(launch_pack_links_f64(g, static_cast<const double *>(U), op->links[F64].ptr, s));
+        LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F32, op->prm.link_recon, op->links[F32].ptr, s));
+        LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F16, op->prm.link_recon, op->links[F16].ptr, s));
+        build_clover(op, s);
+        op->gauge_set = true;
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[4][2], void *stream)
+{
+    if (!op) return arg_error("lq_op_set_params: null operator");
+    if (!std::isfinite(kappa) || !std::isfinite(csw)) return arg_error("lq_op_set_params: kappa and csw must be finite");
+    if (bc)
+        for (int i = 0; i < 4; ++i)
+            if (!(std::fabs(std::hypot(bc[i][0], bc[i][1]) - 1.0) < 1e-12))
+                return arg_error("lq_op_set_params: boundary phases must have modulus 1");
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        op->prm.kappa = kappa;
+        op->prm.csw = csw;
+        op->has_clover = csw != 0.0;
+        if (bc)
+            for (int i = 0; i < 4; ++i) {
+                op->prm.bc[i][0] = op->g.bc_re[i] = bc[i][0];
+                op->prm.bc[i][1] = op->g.bc_im[i] = bc[i][1];
+            }
+        if (op->gauge_set) {
+            op->gauge_set = false;
+            build_clover(op, static_cast<hipStream_t>(stream));
+            op->gauge_set = true;
+        }
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs, void *stream)
+{
+    if (!op || !out || !in) return arg_error("lq_op_apply: null argument");
+    if (kind < LQ_D || kind > LQ_CLOVER_INV_O) return arg_error("lq_op_apply: unknown kind");
+    if (!valid_prec(prec)) return arg_error("lq_op_apply: unknown precision");
+    if (nrhs < 1) return arg_error("lq_op_apply: nrhs must be >= 1");
+    if (out == in) return arg_error("lq_op_apply: out and in must differ");
+    if (!op->gauge_set) {
+        set_error("lq_op_apply: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const Geom &g = op->g;
+        const bool full = kind_is_full(kind);
+        const long bytes = (full ? 2 : 1) * fb(prec, g) * nrhs;
+        op->tmp[2].ensure(bytes);
+        op->tmp[3].ensure(bytes);
+        const double *src = static_cast<const double *>(in);
+        double *dst = static_cast<double *>(out);
+        if (full) {
+            for (int p = 0; p < 2; ++p)
+                LQ_HIP(launch_pack_spinor(g, p, 0, src, full_parity_view(op->tmp[2].ptr, prec, g, nrhs, p), s));
+        } else {
+            LQ_HIP(launch_pack_spinor(g, 0, 1, src, parity_view(op->tmp[2].ptr, prec, g, nrhs), s));
+        }
+        apply_packed(op, kind, prec, op->tmp[3].ptr, op->tmp[2].ptr, nrhs, s);
+        if (full) {
+            for (int p = 0; p < 2; ++p)
+                LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(op->tmp[3].ptr, prec, g, nrhs, p), dst, s));
+        } else {
+            LQ_HIP(launch_unpack_spinor(g, 0, 1, parity_view(op->tmp[3].ptr, prec, g, nrhs), dst, s));
+        }
+        return LQ_OK;
+    });
+}
+
+lq_status lq_field_create(lq_op *op, lq_prec prec, int nrhs, lq_field **out)
+{
+    if (!op || !out) return arg_error("lq_field_create: null argument");
+    if (!valid_prec(prec)) return arg_error("lq_field_create: unknown precision");
+    if (nrhs < 1) return arg_error("lq_field_create: nrhs must be >= 1");
+    *out = nullptr;
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        lq_field *f = new lq_field();
+        f->op = op;
+        f->prec = prec;
+        f->nrhs = nrhs;
+        try {
+            f->data.ensure(fb(prec, op->g) * nrhs);
+            LQ_HIP(hipMemset(f->data.ptr, 0, fb(prec, op->g) * nrhs));
+        } catch (...) {
+            delete f;
+            throw;
+        }
+        *out = f;
+        return LQ_OK;
+    });
+}
+
+void lq_field_destroy(lq_field *f)
+{
+    if (!f) return;
+    (void)hipSetDevice(f->op->device);
+    (void)hipDeviceSynchronize();
+    delete f;
+}
+
+lq_status lq_field_import(lq_field *f, const void *src, void *stream)
+{
+    if (!f || !src) return arg_error("lq_field_import: null argument");
+    return guarded([&]() -> lq_status {
+        select_device(f->op);
+        LQ_HIP(launch_pack_spinor(f->op->g, 0, 1, static_cast<const double *>(src), f->view(),
+                                  static_cast<hipStream_t>(stream)));
+        return LQ_OK;
+    });
+}
+
+lq_status lq_field_export(const lq_field *f, void *dst, void *stream)
+{
+    if (!f || !dst) return arg_error("lq_field_export: null argument");
+    return guarded([&]() -> lq_status {
+        select_device(f->op);
+        LQ_HIP(launch_unpack_spinor(f->op->g, 0, 1, f->view(), static_cast<double *>(dst),
+                                    static_cast<hipStream_t>(stream)));
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_field *in, void *stream)
+{
+    if (!op || !out || !in) return arg_error("lq_op_apply_field: null argument");
+    if (kind < LQ_SCHUR || kind > LQ_CLOVER_INV_O) return arg_error("lq_op_apply_field: kind must act on parity fields");
+    if (out->op != op || in->op != op) return arg_error("lq_op_apply_field: fields belong to another operator");
+    if (out->prec != in->prec || out->nrhs != in->nrhs) return arg_error("lq_op_apply_field: precision or nrhs differ");
+    if (out == in) return arg_error("lq_op_apply_field: out and in must differ");
+    if (!op->gauge_set) {
+        set_error("lq_op_apply_field: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        apply_packed(op, kind, in->prec, out->data.ptr, in->data.ptr, in->nrhs, static_cast<hipStream_t>(stream));
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block)
+{
+    if (!op) return arg_error("lq_op_set_block: null operator");
+    if (!valid_prec(prec)) return arg_error("lq_op_set_block: unknown precision");
+    if (block != 64 && block != 128 && block != 256) return arg_error("lq_op_set_block: block must be 64, 128 or 256");
+    op->hop_block[prec] = block;
+    return LQ_OK;
+}
+
+lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, double *bytes_per_site,
+                        double *flops_per_site)
+{
+    if (!op || !bytes_per_site || !flops_per_site) return arg_error("lq_op_traffic: null argument");
+    if (!valid_prec(prec) || nrhs < 1) return arg_error("lq_op_traffic: bad precision or nrhs");
+    const double rs = prec == LQ_F64 ? 8 : prec == LQ_F32 ? 4 : 2;
+    const int nl = prec == LQ_F64 ? 18 : op->prm.link_recon;
+    const double spinor = 24 * rs + (prec == LQ_F16 ? 4 : 0);
+    double b = 8.0 * nl * rs / nrhs + 2.0 * spinor;
+    double f = 1320.0;
+    if (clover) {
+        b += 72.0 * rs / nrhs;
+        f += 504.0;
+    }
+    *bytes_per_site = b;
+    *flops_per_site = f;
+    return LQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// blas.h -- vector kernels of the Krylov solvers on packed spinor fields.
+//
+// Solver scalars live in device memory, NSC doubles per system, so an
+// iteration runs without host round trips: reduction kernels write
+// per-workgroup partial sums (FP64) and a finish kernel sums them in a fixed
+// order and performs the solver's scalar recurrence on the device.
+// A field holding `sps` slices per system (1 for a parity field, 2 for a
+// full field) is reduced over all slices of the system.
+#pragma once
+
+#include "fields.h"
+
+namespace lq {
+
+enum ScalarSlot {
+    SC_RHO_RE = 0, SC_RHO_IM, SC_ALPHA_RE, SC_ALPHA_IM, SC_OMEGA_RE, SC_OMEGA_IM, SC_BETA_RE, SC_BETA_IM,
+    SC_RR,       // current |r|^2 of the Krylov residual
+    SC_TARGET2,  // stop when SC_RR <= SC_TARGET2 (set relative, made absolute by FIN_INIT_*)
+    SC_DONE,     // 1: system converged (frozen)
+    SC_BREAK,    // 1: breakdown (frozen, restart requested)
+    SC_ITER,     // iterations performed
+    SC_NORM2,    // result of FIN_NORM
+    SC_SCALE,    // sqrt(SC_NORM2)
+    SC_INVSCALE, // 1 / sqrt(SC_NORM2) (0 if zero)
+    SC_ODONE,    // 1: outer residual already below target (inner solve skipped)
+    SC_OTARGET2, // target of FIN_NORM for SC_ODONE
+    SC_DOT_RE, SC_DOT_IM,
+    NSC = 24
+};
+
+enum FinishOp {
+    FIN_NORM = 0,       // K=1: SC_NORM2, SC_SCALE, SC_INVSCALE, SC_ODONE (vs SC_OTARGET2)
+    FIN_INIT_CG,        // K=1: |r|^2 -> rr, done if rr <= target2 or outer done
+    FIN_CG_ALPHA,       // K=1: |M p|^2 -> alpha = rr / |Mp|^2
+    FIN_CG_BETA,        // K=1: |r|^2 -> beta, rr, iter, done
+    FIN_INIT_BICG,      // K=1: |r|^2 -> rho = rr, alpha = omega = 1, done
+    FIN_BICG_ALPHA,     // K=2: <rhat, v> -> alpha = rho / <rhat, v>
+    FIN_BICG_OMEGA,     // K=3: <s, t>, |t|^2 -> omega = <t, s> / |t|^2
+    FIN_BICG_RHO,       // K=3: <rhat, r>, |r|^2 -> beta, rho, rr, iter, done
+    FIN_DOT             // K=2: SC_DOT
+};
+
+// Per-slice reductions written to partial[(slice * nblocks + block) * K + k].
+enum ReduceMode { RED_NORM = 1, RED_DOT = 2, RED_DOT_NORM = 3 };
+
+int blas_blocks(long n);
+
+// partials of <x, y> / |x|^2 over every slice (y unused for RED_NORM);
+// RED_DOT_NORM gives <x, y> and |y|^2.
+hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s);
+// finish: sums partials of nsys systems (sps slices each, nblocks per slice,
+// K values) and runs op on the scalars sc[sys * NSC + ...].
+hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,
+                         double eps, hipStream_t s);
+
+// Elementwise kernels (complex scalars read from sc of each slice's system,
+// system = slice / sps; systems with SC_DONE or SC_BREAK set are skipped
+// when skip_done is true).
+hipError_t launch_zero(FieldView x, hipStream_t s);
+// y = x converted to y's precision, times sc[SC_INVSCALE] if scaled
+hipError_t launch_copy(FieldView y, FieldView x, const double *sc, int sps, bool scaled, hipStream_t s);
+// x64 += sc[SC_SCALE] * e (scaled) or x64 += e
+hipError_t launch_accum(FieldView x64, FieldView e, const double *sc, int sps, bool scaled, hipStream_t s);
+// r = b - y and partial |r|^2
+hipError_t launch_xmy_norm(FieldView r, FieldView b, FieldView y, double *partial, hipStream_t s);
+// CG: x += alpha p; r -= alpha q; partial |r|^2
+hipError_t launch_cg_xr(FieldView x, FieldView r, FieldView p, FieldView q, const double *sc, int sps,
+                        double *partial, hipStream_t s);
+// CG: p = r + beta p
+hipError_t launch_cg_p(FieldView p, FieldView r, const double *sc, int sps, hipStream_t s);
+// BiCGStab: s = r - alpha v
+hipError_t launch_bicg_s(FieldView sv, FieldView r, FieldView v, const double *sc, int sps, hipStream_t s);
+// BiCGStab: x += alpha p + omega s; r = s - omega t; partials <rhat, r>, |r|^2
+hipError_t launch_bicg_xr(FieldView x, FieldView r, FieldView p, FieldView sv, FieldView t, FieldView rhat,
+                          const double *sc, int sps, double *partial, hipStream_t s);
+// BiCGStab: p = r + beta (p - omega v)
+hipError_t launch_bicg_p(FieldView p, FieldView r, FieldView v, const double *sc, int sps, hipStream_t s);
+// apply gamma_5 = diag(1, 1, -1, -1) in place
+hipError_t launch_gamma5(FieldView x, hipStream_t s);
+
+}  // namespace lq

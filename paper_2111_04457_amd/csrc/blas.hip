@@ -1,0 +1,520 @@
+// blas.hip -- vector kernels and device-side scalar recurrences of the
+// Krylov solvers.  Sums are accumulated in FP64 whatever the storage
+// precision; every reduction is summed in a fixed order.
+#include <cmath>
+
+#include "blas.h"
+
+namespace lq {
+
+constexpr int BT = 256;  // threads per workgroup of the vector kernels
+
+int blas_blocks(long n) { return (int)((n + BT - 1) / BT); }
+
+template <typename R> __device__ __forceinline__ cx<R> scal(const double *sc, int slot)
+{
+    return cx<R>{(R)sc[slot], (R)sc[slot + 1]};
+}
+
+__device__ __forceinline__ bool frozen(const double *sc) { return sc[SC_DONE] != 0.0 || sc[SC_BREAK] != 0.0; }
+
+// ------------------------------------------------------------ reductions --
+
+template <int P, int MODE>
+__global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, double *partial)
+{
+    using R = typename PT<P>::R;
+    const long i = (long)blockIdx.x * BT + threadIdx.x;
+    const int slice = blockIdx.y;
+    double a = 0, b = 0, c = 0;
+    if (i < x.n) {
+        const Spinor<R> xv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+        if constexpr (MODE == RED_NORM) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) a += (double)norm2(xv.c[k]);
+        } else {
+            const Spinor<R> yv = load_spinor<P>(y.base + slice * y.rs, i, y.n);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cx<R> t = cmulc(xv.c[k], yv.c[k]);
+                a += (double)t.re;
+                b += (double)t.im;
+                if constexpr (MODE == RED_DOT_NORM) c += (double)norm2(yv.c[k]);
+            }
+        }
+    }
+    __shared__ double lds[BT / 64];
+    constexpr int K = MODE == RED_NORM ? 1 : MODE == RED_DOT ? 2 : 3;
+    double *out = partial + ((long)slice * gridDim.x + blockIdx.x) * K;
+    const double sa = block_sum<BT>(a, lds);
+    if (threadIdx.x == 0) out[0] = sa;
+    if constexpr (K >= 2) {
+        const double sb = block_sum<BT>(b, lds);
+        if (threadIdx.x == 0) out[1] = sb;
+    }
+    if constexpr (K == 3) {
+        const double scc = block_sum<BT>(c, lds);
+        if (threadIdx.x == 0) out[2] = scc;
+    }
+}
+
+hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s)
+{
+    const dim3 grid(blas_blocks(x.n), x.nrhs);
+#define LQ_RED(P)                                                                                      \
+    if (mode == RED_NORM) reduce_kernel<P, RED_NORM><<<grid, BT, 0, s>>>(x, y, partial);              \
+    else if (mode == RED_DOT) reduce_kernel<P, RED_DOT><<<grid, BT, 0, s>>>(x, y, partial);           \
+    else reduce_kernel<P, RED_DOT_NORM><<<grid, BT, 0, s>>>(x, y, partial);
+    switch (x.prec) {
+    case F64: LQ_RED(F64) break;
+    case F32: LQ_RED(F32) break;
+    case F16: LQ_RED(F16) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LQ_RED
+    return hipGetLastError();
+}
+
+// One workgroup per system: sum K values over sps * nblocks partials in a
+// fixed order, then update the system's scalars.
+__global__ __launch_bounds__(BT) void finish_kernel(const double *partial, int sps, int nblocks, int K, int op,
+                                                   double *scal, double eps)
+{
+    const int sys = blockIdx.x;
+    const long cnt = (long)sps * nblocks;
+    const double *p = partial + (long)sys * cnt * K;
+    double v[3] = {0, 0, 0};
+    for (long j = threadIdx.x; j < cnt; j += BT)
+        for (int k = 0; k < K; ++k) v[k] += p[j * K + k];
+    __shared__ double lds[BT / 64];
+    double tot[3];
+    for (int k = 0; k < 3; ++k) tot[k] = block_sum<BT>(v[k], lds);
+    if (threadIdx.x != 0) return;
+    double *sc = scal + (long)sys * NSC;
+    const bool fz = frozen(sc);
+    switch (op) {
+    case FIN_NORM: {
+        const double n2 = tot[0];
+        sc[SC_NORM2] = n2;
+        sc[SC_SCALE] = sqrt(n2);
+        sc[SC_INVSCALE] = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
+        sc[SC_ODONE] = (n2 <= sc[SC_OTARGET2]) ? 1.0 : 0.0;
+        break;
+    }
+    case FIN_INIT_CG:
+    case FIN_INIT_BICG: {
+        const double rr = tot[0];
+        sc[SC_RR] = rr;
+        sc[SC_TARGET2] *= rr;  // relative -> absolute
+        sc[SC_ITER] = 0;
+        sc[SC_BREAK] = 0;
+        sc[SC_DONE] = (sc[SC_ODONE] != 0.0 || rr <= sc[SC_TARGET2] || !(rr > 0)) ? 1.0 : 0.0;
+        sc[SC_ALPHA_RE] = sc[SC_OMEGA_RE] = 1.0;
+        sc[SC_ALPHA_IM] = sc[SC_OMEGA_IM] = 0.0;
+        sc[SC_BETA_RE] = sc[SC_BETA_IM] = 0.0;
+        sc[SC_RHO_RE] = rr;
+        sc[SC_RHO_IM] = 0.0;
+        break;
+    }
+    case FIN_CG_ALPHA: {
+        const double den = tot[0];
+        if (fz || !(den > 0)) {
+            if (!fz) sc[SC_BREAK] = 1.0;
+            sc[SC_ALPHA_RE] = 0.0;
+        } else {
+            sc[SC_ALPHA_RE] = sc[SC_RR] / den;
+        }
+        sc[SC_ALPHA_IM] = 0.0;
+        break;
+    }
+    case FIN_CG_BETA: {
+        const double rr = tot[0];
+        if (fz) {
+            sc[SC_BETA_RE] = 0.0;
+        } else {
+            sc[SC_BETA_RE] = rr / sc[SC_RR];
+            sc[SC_RR] = rr;
+            sc[SC_ITER] += 1.0;
+            if (rr <= sc[SC_TARGET2]) sc[SC_DONE] = 1.0;
+            if (!(rr == rr) || rr > 1e300) sc[SC_BREAK] = 1.0;
+        }
+        sc[SC_BETA_IM] = 0.0;
+        break;
+    }
+    case FIN_BICG_ALPHA: {
+        const double dr = tot[0], di = tot[1];
+        const double d2 = dr * dr + di * di;
+        if (fz || !(d2 > 0) || !(d2 < 1e300)) {
+            if (!fz) sc[SC_BREAK] = 1.0;
+            sc[SC_ALPHA_RE] = sc[SC_ALPHA_IM] = 0.0;
+        } else {
+            const double rr_ = sc[SC_RHO_RE], ri = sc[SC_RHO_IM];
+            sc[SC_ALPHA_RE] = (rr_ * dr + ri * di) / d2;
+            sc[SC_ALPHA_IM] = (ri * dr - rr_ * di) / d2;
+        }
+        break;
+    }
+    case FIN_BICG_OMEGA: {
+        // tot = <s, t> (re, im), |t|^2 ; omega = <t, s> / |t|^2 = conj(<s, t>) / |t|^2
+        const double tt = tot[2];
+        if (fz || !(tt > 0)) {
+            sc[SC_OMEGA_RE] = sc[SC_OMEGA_IM] = 0.0;
+        } else {
+            sc[SC_OMEGA_RE] = tot[0] / tt;
+            sc[SC_OMEGA_IM] = -tot[1] / tt;
+        }
+        break;
+    }
+    case FIN_BICG_RHO: {
+        const double pr = tot[0], pi = tot[1], rr = tot[2];
+        if (fz) {
+            sc[SC_BETA_RE] = sc[SC_BETA_IM] = 0.0;
+            break;
+        }
+        sc[SC_RR] = rr;
+        sc[SC_ITER] += 1.0;
+        if (rr <= sc[SC_TARGET2]) {
+            sc[SC_DONE] = 1.0;
+            sc[SC_BETA_RE] = sc[SC_BETA_IM] = 0.0;
+            break;
+        }
+        const double om2 = sc[SC_OMEGA_RE] * sc[SC_OMEGA_RE] + sc[SC_OMEGA_IM] * sc[SC_OMEGA_IM];
+        const double rho2 = sc[SC_RHO_RE] * sc[SC_RHO_RE] + sc[SC_RHO_IM] * sc[SC_RHO_IM];
+        if (!(rr == rr) || !(om2 > 0) || !(rho2 > 0) || (pr * pr + pi * pi) < eps * eps * rr * rr) {
+            sc[SC_BREAK] = 1.0;
+            sc[SC_BETA_RE] = sc[SC_BETA_IM] = 0.0;
+            break;
+        }
+        // beta = (rho_new / rho) * (alpha / omega)
+        const double qr = (pr * sc[SC_RHO_RE] + pi * sc[SC_RHO_IM]) / rho2;
+        const double qi = (pi * sc[SC_RHO_RE] - pr * sc[SC_RHO_IM]) / rho2;
+        const double ar = (sc[SC_ALPHA_RE] * sc[SC_OMEGA_RE] + sc[SC_ALPHA_IM] * sc[SC_OMEGA_IM]) / om2;
+        const double ai = (sc[SC_ALPHA_IM] * sc[SC_OMEGA_RE] - sc[SC_ALPHA_RE] * sc[SC_OMEGA_IM]) / om2;
+        sc[SC_BETA_RE] = qr * ar - qi * ai;
+        sc[SC_BETA_IM] = qr * ai + qi * ar;
+        sc[SC_RHO_RE] = pr;
+        sc[SC_RHO_IM] = pi;
+        break;
+    }
+    case FIN_DOT:
+        sc[SC_DOT_RE] = tot[0];
+        sc[SC_DOT_IM] = tot[1];
+        break;
+    }
+}
+
+hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,
+                         double eps, hipStream_t s)
+{
+    finish_kernel<<<nsys, BT, 0, s>>>(partial, sps, nblocks, K, op, sc, eps);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- elementwise --
+
+#define LQ_SITE                                                 \
+    const long i = (long)blockIdx.x * BT + threadIdx.x;         \
+    const int slice = blockIdx.y;                               \
+    if (i >= x.n) return;
+
+template <int P> __global__ __launch_bounds__(BT) void zero_kernel(FieldView x)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    Spinor<R> z;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) z.c[k] = cx<R>{0, 0};
+    store_spinor<P>(x.base + slice * x.rs, i, x.n, z);
+}
+
+template <int PY, int PX>
+__global__ __launch_bounds__(BT) void copy_kernel(FieldView y, FieldView x, const double *sc, int sps, bool scaled)
+{
+    using RX = typename PT<PX>::R;
+    using RY = typename PT<PY>::R;
+    LQ_SITE
+    const Spinor<RX> v = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+    const double f = scaled ? sc[(slice / sps) * NSC + SC_INVSCALE] : 1.0;
+    Spinor<RY> o;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o.c[k] = cx<RY>{(RY)(f * (double)v.c[k].re), (RY)(f * (double)v.c[k].im)};
+    store_spinor<PY>(y.base + slice * y.rs, i, y.n, o);
+}
+
+template <int PE>
+__global__ __launch_bounds__(BT) void accum_kernel(FieldView x, FieldView e, const double *sc, int sps, bool scaled)
+{
+    using RE = typename PT<PE>::R;
+    LQ_SITE
+    const double *s = sc + (slice / sps) * NSC;
+    if (s[SC_ODONE] != 0.0) return;
+    const double f = scaled ? s[SC_SCALE] : 1.0;
+    Spinor<double> xv = load_spinor<F64>(x.base + slice * x.rs, i, x.n);
+    const Spinor<RE> ev = load_spinor<PE>(e.base + slice * e.rs, i, e.n);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        xv.c[k].re += f * (double)ev.c[k].re;
+        xv.c[k].im += f * (double)ev.c[k].im;
+    }
+    store_spinor<F64>(x.base + slice * x.rs, i, x.n, xv);
+}
+
+__global__ __launch_bounds__(BT) void xmy_norm_kernel(FieldView r, FieldView b, FieldView x /* y */,
+                                                     double *partial)
+{
+    const long i = (long)blockIdx.x * BT + threadIdx.x;
+    const int slice = blockIdx.y;
+    double a = 0;
+    if (i < r.n) {
+        const Spinor<double> bv = load_spinor<F64>(b.base + slice * b.rs, i, b.n);
+        const Spinor<double> yv = load_spinor<F64>(x.base + slice * x.rs, i, x.n);
+        Spinor<double> o;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o.c[k] = bv.c[k] - yv.c[k];
+            a += norm2(o.c[k]);
+        }
+        store_spinor<F64>(r.base + slice * r.rs, i, r.n, o);
+    }
+    __shared__ double lds[BT / 64];
+    const double t = block_sum<BT>(a, lds);
+    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+}
+
+template <int P, int PX>
+__global__ __launch_bounds__(BT) void cg_xr_kernel(FieldView x, FieldView r, FieldView p, FieldView q,
+                                                  const double *sc, int sps, double *partial)
+{
+    using R = typename PT<P>::R;
+    using RX = typename PT<PX>::R;
+    const long i = (long)blockIdx.x * BT + threadIdx.x;
+    const int slice = blockIdx.y;
+    const double *s = sc + (slice / sps) * NSC;
+    double a = 0;
+    if (i < r.n) {
+        Spinor<R> rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+        if (!frozen(s)) {
+            const R al = (R)s[SC_ALPHA_RE];
+            const Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+            const Spinor<R> qv = load_spinor<P>(q.base + slice * q.rs, i, q.n);
+            Spinor<RX> xv = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                xv.c[k].re += (RX)(al * pv.c[k].re);
+                xv.c[k].im += (RX)(al * pv.c[k].im);
+                rv.c[k] = rv.c[k] - al * qv.c[k];
+            }
+            store_spinor<PX>(x.base + slice * x.rs, i, x.n, xv);
+            store_spinor<P>(r.base + slice * r.rs, i, r.n, rv);
+            if constexpr (PT<P>::scaled) rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) a += (double)norm2(rv.c[k]);
+    }
+    __shared__ double lds[BT / 64];
+    const double t = block_sum<BT>(a, lds);
+    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+}
+
+template <int P>
+__global__ __launch_bounds__(BT) void cg_p_kernel(FieldView p, FieldView x /* r */, const double *sc, int sps)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    const double *s = sc + (slice / sps) * NSC;
+    if (s[SC_BREAK] != 0.0) return;
+    const R be = (R)s[SC_BETA_RE];
+    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+    Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + be * pv.c[k];
+    store_spinor<P>(p.base + slice * p.rs, i, p.n, pv);
+}
+
+template <int P>
+__global__ __launch_bounds__(BT) void bicg_s_kernel(FieldView sv, FieldView x /* r */, FieldView v, const double *sc,
+                                                   int sps)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    const double *s = sc + (slice / sps) * NSC;
+    if (frozen(s)) return;
+    const cx<R> al = scal<R>(s, SC_ALPHA_RE);
+    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+    const Spinor<R> vv = load_spinor<P>(v.base + slice * v.rs, i, v.n);
+    Spinor<R> o;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o.c[k] = rv.c[k] - al * vv.c[k];
+    store_spinor<P>(sv.base + slice * sv.rs, i, sv.n, o);
+}
+
+template <int P, int PX>
+__global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, FieldView p, FieldView sv, FieldView t,
+                                                    FieldView rhat, const double *sc, int sps, double *partial)
+{
+    using R = typename PT<P>::R;
+    using RX = typename PT<PX>::R;
+    const long i = (long)blockIdx.x * BT + threadIdx.x;
+    const int slice = blockIdx.y;
+    const double *s = sc + (slice / sps) * NSC;
+    double a = 0, b = 0, c = 0;
+    if (i < r.n) {
+        Spinor<R> rv;
+        if (!frozen(s)) {
+            const cx<R> al = scal<R>(s, SC_ALPHA_RE);
+            const cx<R> om = scal<R>(s, SC_OMEGA_RE);
+            const Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+            const Spinor<R> svv = load_spinor<P>(sv.base + slice * sv.rs, i, sv.n);
+            const Spinor<R> tv = load_spinor<P>(t.base + slice * t.rs, i, t.n);
+            Spinor<RX> xv = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cx<R> d = al * pv.c[k] + om * svv.c[k];
+                xv.c[k].re += (RX)d.re;
+                xv.c[k].im += (RX)d.im;
+                rv.c[k] = svv.c[k] - om * tv.c[k];
+            }
+            store_spinor<PX>(x.base + slice * x.rs, i, x.n, xv);
+            store_spinor<P>(r.base + slice * r.rs, i, r.n, rv);
+            if constexpr (PT<P>::scaled) rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+        } else {
+            rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+        }
+        const Spinor<R> hv = load_spinor<P>(rhat.base + slice * rhat.rs, i, rhat.n);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cx<R> d = cmulc(hv.c[k], rv.c[k]);
+            a += (double)d.re;
+            b += (double)d.im;
+            c += (double)norm2(rv.c[k]);
+        }
+    }
+    __shared__ double lds[BT / 64];
+    double *out = partial + ((long)slice * gridDim.x + blockIdx.x) * 3;
+    const double sa = block_sum<BT>(a, lds);
+    const double sb = block_sum<BT>(b, lds);
+    const double scc = block_sum<BT>(c, lds);
+    if (threadIdx.x == 0) {
+        out[0] = sa;
+        out[1] = sb;
+        out[2] = scc;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(BT) void bicg_p_kernel(FieldView p, FieldView x /* r */, FieldView v, const double *sc,
+                                                   int sps)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    const double *s = sc + (slice / sps) * NSC;
+    if (frozen(s)) return;
+    const cx<R> be = scal<R>(s, SC_BETA_RE);
+    const cx<R> om = scal<R>(s, SC_OMEGA_RE);
+    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+    const Spinor<R> vv = load_spinor<P>(v.base + slice * v.rs, i, v.n);
+    Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + be * (pv.c[k] - om * vv.c[k]);
+    store_spinor<P>(p.base + slice * p.rs, i, p.n, pv);
+}
+
+template <int P> __global__ __launch_bounds__(BT) void gamma5_kernel(FieldView x)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    Spinor<R> v = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+#pragma unroll
+    for (int k = 6; k < 12; ++k) v.c[k] = cx<R>{-v.c[k].re, -v.c[k].im};
+    store_spinor<P>(x.base + slice * x.rs, i, x.n, v);
+}
+
+#undef LQ_SITE
+
+static dim3 grid_of(const FieldView &x) { return dim3(blas_blocks(x.n), x.nrhs); }
+
+#define LQ_BY_PREC(prec, KER, ...)                                                    \
+    switch (prec) {                                                                   \
+    case F64: KER<F64><<<grid_of(x), BT, 0, s>>>(__VA_ARGS__); break;                 \
+    case F32: KER<F32><<<grid_of(x), BT, 0, s>>>(__VA_ARGS__); break;                 \
+    case F16: KER<F16><<<grid_of(x), BT, 0, s>>>(__VA_ARGS__); break;                 \
+    default: return hipErrorInvalidValue;                                             \
+    }                                                                                 \
+    return hipGetLastError();
+
+hipError_t launch_zero(FieldView x, hipStream_t s) { LQ_BY_PREC(x.prec, zero_kernel, x) }
+
+hipError_t launch_copy(FieldView y, FieldView x, const double *sc, int sps, bool scaled, hipStream_t s)
+{
+    const dim3 g = grid_of(x);
+#define LQ_CP(PY, PX)                                                           \
+    if (y.prec == PY && x.prec == PX) {                                         \
+        copy_kernel<PY, PX><<<g, BT, 0, s>>>(y, x, sc, sps, scaled);            \
+        return hipGetLastError();                                               \
+    }
+    LQ_CP(F64, F64) LQ_CP(F32, F64) LQ_CP(F16, F64) LQ_CP(F32, F32) LQ_CP(F16, F16) LQ_CP(F64, F32)
+    LQ_CP(F32, F16) LQ_CP(F16, F32)
+#undef LQ_CP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accum(FieldView x64, FieldView e, const double *sc, int sps, bool scaled, hipStream_t s)
+{
+    FieldView &x = x64;
+    LQ_BY_PREC(e.prec, accum_kernel, x64, e, sc, sps, scaled)
+}
+
+hipError_t launch_xmy_norm(FieldView r, FieldView b, FieldView y, double *partial, hipStream_t s)
+{
+    xmy_norm_kernel<<<grid_of(r), BT, 0, s>>>(r, b, y, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(FieldView x, FieldView r, FieldView p, FieldView q, const double *sc, int sps,
+                        double *partial, hipStream_t s)
+{
+    const dim3 g = grid_of(r);
+    if (r.prec == F64 && x.prec == F64) cg_xr_kernel<F64, F64><<<g, BT, 0, s>>>(x, r, p, q, sc, sps, partial);
+    else if (r.prec == F32 && x.prec == F32) cg_xr_kernel<F32, F32><<<g, BT, 0, s>>>(x, r, p, q, sc, sps, partial);
+    else if (r.prec == F16 && x.prec == F32) cg_xr_kernel<F16, F32><<<g, BT, 0, s>>>(x, r, p, q, sc, sps, partial);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_p(FieldView p, FieldView r, const double *sc, int sps, hipStream_t s)
+{
+    FieldView &x = r;
+    LQ_BY_PREC(p.prec, cg_p_kernel, p, r, sc, sps)
+}
+
+hipError_t launch_bicg_s(FieldView sv, FieldView r, FieldView v, const double *sc, int sps, hipStream_t s)
+{
+    FieldView &x = r;
+    LQ_BY_PREC(r.prec, bicg_s_kernel, sv, r, v, sc, sps)
+}
+
+hipError_t launch_bicg_xr(FieldView x, FieldView r, FieldView p, FieldView sv, FieldView t, FieldView rhat,
+                          const double *sc, int sps, double *partial, hipStream_t s)
+{
+    const dim3 g = grid_of(r);
+    if (r.prec == F64 && x.prec == F64)
+        bicg_xr_kernel<F64, F64><<<g, BT, 0, s>>>(x, r, p, sv, t, rhat, sc, sps, partial);
+    else if (r.prec == F32 && x.prec == F32)
+        bicg_xr_kernel<F32, F32><<<g, BT, 0, s>>>(x, r, p, sv, t, rhat, sc, sps, partial);
+    else if (r.prec == F16 && x.prec == F32)
+        bicg_xr_kernel<F16, F32><<<g, BT, 0, s>>>(x, r, p, sv, t, rhat, sc, sps, partial);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(FieldView p, FieldView r, FieldView v, const double *sc, int sps, hipStream_t s)
+{
+    FieldView &x = r;
+    LQ_BY_PREC(r.prec, bicg_p_kernel, p, r, v, sc, sps)
+}
+
+hipError_t launch_gamma5(FieldView x, hipStream_t s) { LQ_BY_PREC(x.prec, gamma5_kernel, x) }
+
+#undef LQ_BY_PREC
+
+}  // namespace lq

@@ -1,0 +1,54 @@
+// dslash.h -- the Wilson hopping term of eq. (1) (Sec. 3) on one parity,
+// with fused clover / axpy epilogues, for gfx950.
+//
+// For every output site x of parity p the kernel sums the eight neighbour
+// terms of eq. (1):
+//     (1 - gamma_mu) U_mu(x) psi(x+mu)  +  (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)
+// (signs of gamma swapped for the dagger).  In the chiral basis
+// gamma_mu = [[0, B], [B^dag, 0]] with B unitary, so (1 + s gamma_mu) psi is
+// fixed by the two upper spin components h = psi_up + s B psi_dn: the lower
+// ones are s B^dag h.  Each term is therefore one spin projection to h
+// (2 spins x 3 colours), two SU(3) mat-vecs on h, and a reconstruction.
+#pragma once
+
+#include "lq_common.h"
+
+namespace lq {
+
+// Epilogue applied to res = coef * (H in):
+//   XPAY:      res = (CLOV == 1 ? C y : y) + res
+//   CLOV == 2: res = C res
+// where C is the packed clover block field of the output parity (A or A^-1).
+struct HopArgs {
+    Geom g;
+    int p_out;           // output parity
+    int nrhs;
+    const char *in;      // input field (parity 1 - p_out) base, rhs 0
+    long in_n;           // plane stride of the input (sites)
+    long in_rs;          // bytes between right-hand sides
+    char *out;
+    long out_n;
+    long out_rs;
+    const char *y;       // axpy operand at output sites (same layout as out)
+    long y_n;
+    long y_rs;
+    const char *links;   // packed links [parity][mu] (vh sites each)
+    const char *clov;    // packed clover blocks of the output parity (vh sites)
+    double coef;
+    double *partial;     // per-block partial sums (reduction epilogue) or null
+    const char *w;       // second operand of a fused dot product, or null
+    long w_n;
+    long w_rs;
+};
+
+// Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;
+// dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result;
+// xpay: add y; red: 0 none, 1 |out|^2, 2 <w, out> per right-hand side.
+// block: threads per workgroup (a multiple of 64).
+hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int block,
+                      hipStream_t s);
+
+// Number of workgroups launch_hop uses for a lattice of vh sites.
+inline int hop_blocks(int vh, int block) { return (vh + block - 1) / block; }
+
+}  // namespace lq

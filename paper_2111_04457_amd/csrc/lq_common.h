@@ -1,0 +1,230 @@
+// lq_common.h -- device-side building blocks shared by the HIP kernels:
+// geometry of the checkerboarded lattice, precision traits, complex
+// arithmetic, and loads/stores of the structure-of-arrays field layout.
+//
+// Field layout in HBM ("planes"): a field of R reals per site and storage
+// type T over n sites is stored as  floor(R*sizeof(T)/16)  planes of 16-byte
+// elements, followed by at most one narrower tail plane (8 or 4 bytes) for
+// the remainder, each plane holding one element per site:
+//     plane k element of site s at  base + k*16*n + 16*s
+//     tail element of site s    at  base + K16*16*n + TAIL*s
+// so a wavefront of 64 consecutive sites reads 64 consecutive 16-byte
+// elements (1 KiB) per load instruction.  FP16 spinors carry one more plane
+// of FP32 per-site scales.  Several right-hand sides are stacked whole.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lq {
+
+// ------------------------------------------------------------ precision --
+
+enum Prec { F64 = 0, F32 = 1, F16 = 2 };
+
+template <int P> struct PT;
+template <> struct PT<F64> { using S = double;   using R = double; static constexpr bool scaled = false; };
+template <> struct PT<F32> { using S = float;    using R = float;  static constexpr bool scaled = false; };
+template <> struct PT<F16> { using S = _Float16; using R = float;  static constexpr bool scaled = true; };
+
+// bytes of one site of a field of `reals` reals in storage precision p
+__host__ __device__ constexpr long site_bytes(int p, int reals)
+{
+    return (long)reals * (p == F64 ? 8 : p == F32 ? 4 : 2) + (p == F16 && reals == 24 ? 4 : 0);
+}
+
+// ------------------------------------------------------------- complex ---
+
+template <typename R> struct cx {
+    R re, im;
+};
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// multiply by +i / -i
+template <typename R> __device__ __forceinline__ cx<R> ti(cx<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ cx<R> tmi(cx<R> a) { return {a.im, -a.re}; }
+template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// --------------------------------------------------------------- planes --
+
+template <typename T, int N> struct Planes {
+    static constexpr int BYTES = N * (int)sizeof(T);
+    static constexpr int K16 = BYTES / 16;
+    static constexpr int TAIL = BYTES % 16;
+    static constexpr int PER16 = 16 / (int)sizeof(T);
+    static_assert(TAIL == 0 || TAIL == 8 || TAIL == 4, "unsupported tail");
+    // bytes of the whole field over n sites
+    __host__ __device__ static constexpr long field_bytes(long n) { return (long)BYTES * n; }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void load_planes(const char *__restrict__ base, long s, long n, T *__restrict__ out)
+{
+    using PL = Planes<T, N>;
+#pragma unroll
+    for (int k = 0; k < PL::K16; ++k) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(base + ((long)k * n + s) * 16);
+        __builtin_memcpy(out + k * PL::PER16, &q, 16);
+    }
+    if constexpr (PL::TAIL == 8) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(base + (long)PL::K16 * 16 * n + s * 8);
+        __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 8);
+    } else if constexpr (PL::TAIL == 4) {
+        const uint32_t q = *reinterpret_cast<const uint32_t *>(base + (long)PL::K16 * 16 * n + s * 4);
+        __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 4);
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_planes(char *__restrict__ base, long s, long n, const T *__restrict__ in)
+{
+    using PL = Planes<T, N>;
+#pragma unroll
+    for (int k = 0; k < PL::K16; ++k) {
+        uint4 q;
+        __builtin_memcpy(&q, in + k * PL::PER16, 16);
+        *reinterpret_cast<uint4 *>(base + ((long)k * n + s) * 16) = q;
+    }
+    if constexpr (PL::TAIL == 8) {
+        uint2 q;
+        __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 8);
+        *reinterpret_cast<uint2 *>(base + (long)PL::K16 * 16 * n + s * 8) = q;
+    } else if constexpr (PL::TAIL == 4) {
+        uint32_t q;
+        __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 4);
+        *reinterpret_cast<uint32_t *>(base + (long)PL::K16 * 16 * n + s * 4) = q;
+    }
+}
+
+// A spinor (12 complex = 24 reals) in compute precision R.
+template <typename R> struct Spinor {
+    cx<R> c[12];  // index spin*3 + colour
+};
+
+// Bytes of a packed spinor field over n sites (FP16: plus the scale plane).
+__host__ __device__ constexpr long spinor_field_bytes(int p, long n)
+{
+    return p == F64 ? 192 * n : p == F32 ? 96 * n : 52 * n;
+}
+
+template <int P>
+__device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__restrict__ base, long s, long n)
+{
+    using S = typename PT<P>::S;
+    using R = typename PT<P>::R;
+    S raw[24];
+    load_planes<S, 24>(base, s, n, raw);
+    Spinor<R> o;
+    if constexpr (PT<P>::scaled) {
+        const float sc = *reinterpret_cast<const float *>(base + 48 * n + 4 * s);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i] * sc, (R)raw[2 * i + 1] * sc};
+    } else {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i], (R)raw[2 * i + 1]};
+    }
+    return o;
+}
+
+template <int P>
+__device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, long n,
+                                             const Spinor<typename PT<P>::R> &v)
+{
+    using S = typename PT<P>::S;
+    using R = typename PT<P>::R;
+    S raw[24];
+    if constexpr (PT<P>::scaled) {
+        R m = 0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) m = fmaxf(m, fmaxf(fabsf(v.c[i].re), fabsf(v.c[i].im)));
+        const R inv = m > 0 ? (R)1 / m : (R)0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            raw[2 * i] = (S)(v.c[i].re * inv);
+            raw[2 * i + 1] = (S)(v.c[i].im * inv);
+        }
+        *reinterpret_cast<float *>(base + 48 * n + 4 * s) = m;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            raw[2 * i] = (S)v.c[i].re;
+            raw[2 * i + 1] = (S)v.c[i].im;
+        }
+    }
+    store_planes<S, 24>(base, s, n, raw);
+}
+
+// ------------------------------------------------------------- geometry --
+
+// Lattice geometry of one checkerboarded lattice, passed by value.
+struct Geom {
+    int L[4];     // Lx, Ly, Lz, Lt
+    int lxh;      // Lx / 2
+    int vh;       // sites per parity
+    double bc_re[4], bc_im[4];  // boundary phase per direction
+};
+
+// Coordinates of checkerboard site cb of parity p.
+__device__ __forceinline__ void cb_coords(const Geom &g, int p, int cb, int c[4])
+{
+    int j = cb % g.lxh;
+    int r = cb / g.lxh;
+    c[1] = r % g.L[1];
+    r /= g.L[1];
+    c[2] = r % g.L[2];
+    c[3] = r / g.L[2];
+    c[0] = 2 * j + ((c[1] + c[2] + c[3] + p) & 1);
+}
+
+// Checkerboard index of the site with coordinates c.
+__device__ __forceinline__ int cb_index(const Geom &g, const int c[4])
+{
+    return (c[0] >> 1) + g.lxh * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+}  // namespace lq
+
+namespace lq {
+
+// ------------------------------------------------------------ reductions --
+
+// Sum over the 64 lanes of a wavefront (butterfly: same order every run).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a workgroup of NT threads; the result is valid in thread 0.
+// Waves are combined through LDS in a fixed order, so the value does not
+// depend on scheduling.  Every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) r += lds[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+}  // namespace lq

@@ -1,0 +1,117 @@
+// runtime.h -- host-side runtime of the library: device buffers, the
+// operator object (packed links and clover in every precision), operator
+// applies on packed fields, and error reporting for the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lq.h"
+#include "dslash.h"
+#include "fields.h"
+
+namespace lq {
+
+// Thread-local message of the last failure, returned by lq_last_error().
+void set_error(const std::string &msg);
+const char *get_error();
+
+// An error carried out of the runtime to the ABI, with its status code.
+struct Failure {
+    lq_status code;
+    std::string msg;
+};
+
+#define LQ_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw ::lq::Failure{LQ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};    \
+    } while (0)
+
+// Owned device allocation.
+struct Buf {
+    char *ptr = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    ~Buf() { release(); }
+    void release();
+    // make sure at least n bytes are allocated (contents are not kept)
+    void ensure(size_t n);
+};
+
+}  // namespace lq
+
+struct lq_op {
+    lq_op_params prm;
+    lq::Geom g;
+    int device = 0;
+    bool gauge_set = false;
+    bool has_clover = false;
+    int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
+    lq::Buf links[3];                    // packed links per precision ([parity][mu])
+    lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
+    lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
+    lq::Buf flag;                        // device int: singular clover block
+    lq::Buf tmp[6];                      // scratch fields for composite applies
+    lq::Buf partial;                     // reduction partial sums
+    lq::Buf solver_ws;                   // solver work vectors
+    lq::Buf solver_sc;                   // solver scalars (device)
+    double *host_sc = nullptr;           // pinned host mirror of the solver scalars
+    size_t host_sc_n = 0;
+    ~lq_op() { if (host_sc) (void)hipHostFree(host_sc); }
+    int nl(int prec) const { return prec == lq::F64 ? 18 : prm.link_recon; }
+};
+
+struct lq_field {
+    lq_op *op;
+    int prec;
+    int nrhs;
+    lq::Buf data;
+    lq::FieldView view() const
+    {
+        return lq::FieldView{data.ptr, prec, (long)op->g.vh, lq::spinor_field_bytes(prec, op->g.vh), nrhs};
+    }
+};
+
+namespace lq {
+
+inline long fb(int prec, const Geom &g) { return spinor_field_bytes(prec, g.vh); }
+
+// A parity field view on buffer memory (nrhs slices, contiguous).
+inline FieldView parity_view(char *base, int prec, const Geom &g, int nrhs)
+{
+    return FieldView{base, prec, (long)g.vh, fb(prec, g), nrhs};
+}
+// Parity p of a full packed field laid out [rhs][parity][planes].
+inline FieldView full_parity_view(char *base, int prec, const Geom &g, int nrhs, int p)
+{
+    return FieldView{base + p * fb(prec, g), prec, (long)g.vh, 2 * fb(prec, g), nrhs};
+}
+
+// Hopping term on packed fields: out = epilogue(coef * H_{p_out,1-p_out} in).
+// clov_mode: 0 none, 1 clover on y, 2 clover on the result; inv selects A^-1.
+// red: 0 none, 1 per-rhs |out|^2, 2 per-rhs <w, out> partials into op->partial.
+void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, bool dag, int clov_mode,
+         bool inv, const FieldView *y, double coef, int red, const FieldView *w, hipStream_t s);
+
+// Apply kind on packed fields of precision prec.  Full kinds take full
+// packed fields ([rhs][parity][planes]); the others parity fields.
+void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s);
+
+// Clover of parity p (inverse if inv) applied site-locally.
+void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s);
+
+bool kind_is_full(lq_kind k);
+
+// Schur operator M (or M^dag) on packed even fields; t: odd scratch field.
+void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, bool dag,
+           hipStream_t s);
+// Full-lattice D (or D^dag) on full packed fields of nrhs systems.
+void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool dag, hipStream_t s);
+
+}  // namespace lq

@@ -1,0 +1,146 @@
+// runtime.hip -- operator applies on packed fields.
+#include "runtime.h"
+
+namespace lq {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *get_error() { return g_last_error.c_str(); }
+
+void Buf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void Buf::ensure(size_t n)
+{
+    if (n <= bytes && ptr) return;
+    release();
+    if (n == 0) n = 256;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Failure{LQ_ERR_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
+    }
+    ptr = static_cast<char *>(p);
+    bytes = n;
+}
+
+bool kind_is_full(lq_kind k) { return k == LQ_D || k == LQ_DDAG || k == LQ_DDAGD; }
+
+void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, bool dag, int clov_mode,
+         bool inv, const FieldView *y, double coef, int red, const FieldView *w, hipStream_t s)
+{
+    const Geom &g = op->g;
+    HopArgs a{};
+    a.g = g;
+    a.p_out = p_out;
+    a.nrhs = in.nrhs;
+    a.in = in.base;
+    a.in_n = in.n;
+    a.in_rs = in.rs;
+    a.out = out.base;
+    a.out_n = out.n;
+    a.out_rs = out.rs;
+    if (y) {
+        a.y = y->base;
+        a.y_n = y->n;
+        a.y_rs = y->rs;
+    }
+    if (w) {
+        a.w = w->base;
+        a.w_n = w->n;
+        a.w_rs = w->rs;
+    }
+    a.links = op->links[prec].ptr;
+    if (clov_mode && !op->has_clover) clov_mode = 0;
+    if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
+    a.coef = coef;
+    const int block = op->hop_block[prec];
+    if (red) {
+        op->partial.ensure((size_t)hop_blocks(g.vh, block) * in.nrhs * 2 * sizeof(double));
+        a.partial = reinterpret_cast<double *>(op->partial.ptr);
+    }
+    LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, block, s));
+}
+
+void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s)
+{
+    if (!op->has_clover) {
+        if (out.base != in.base)
+            for (int r = 0; r < in.nrhs; ++r)
+                LQ_HIP(hipMemcpyAsync(out.base + r * out.rs, in.base + r * in.rs, fb(prec, op->g),
+                                      hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const char *c = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p * clover_bytes(prec, op->g.vh);
+    LQ_HIP(launch_clover_apply(op->g, c, out, in, s));
+}
+
+// Schur operator M = A_ee - kappa^2 H_eo A_oo^-1 H_oe (dag: M^dag) on packed
+// even fields; t is an odd scratch field.
+void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, bool dag,
+                  hipStream_t s)
+{
+    const double k = op->prm.kappa;
+    hop(op, prec, t, in, 1, dag, 2, true, nullptr, 1.0, 0, nullptr, s);
+    hop(op, prec, out, t, 0, dag, 1, false, &in, -k * k, 0, nullptr, s);
+}
+
+// Full-lattice D (or D^dag): out_p = A_pp in_p - kappa H_{p,1-p} in_{1-p}.
+void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool dag, hipStream_t s)
+{
+    const Geom &g = op->g;
+    for (int p = 0; p < 2; ++p) {
+        const FieldView o = full_parity_view(out, prec, g, nrhs, p);
+        const FieldView x_in = full_parity_view(const_cast<char *>(in), prec, g, nrhs, 1 - p);
+        const FieldView y = full_parity_view(const_cast<char *>(in), prec, g, nrhs, p);
+        hop(op, prec, o, x_in, p, dag, 1, false, &y, -op->prm.kappa, 0, nullptr, s);
+    }
+}
+
+void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s)
+{
+    const Geom &g = op->g;
+    const FieldView o = parity_view(out, prec, g, nrhs);
+    const FieldView i = parity_view(const_cast<char *>(in), prec, g, nrhs);
+    switch (kind) {
+    case LQ_D: dirac_full(op, prec, out, in, nrhs, false, s); break;
+    case LQ_DDAG: dirac_full(op, prec, out, in, nrhs, true, s); break;
+    case LQ_DDAGD: {
+        op->tmp[0].ensure(2 * fb(prec, g) * nrhs);
+        dirac_full(op, prec, op->tmp[0].ptr, in, nrhs, false, s);
+        dirac_full(op, prec, out, op->tmp[0].ptr, nrhs, true, s);
+        break;
+    }
+    case LQ_SCHUR:
+    case LQ_SCHUR_DAG: {
+        op->tmp[0].ensure(fb(prec, g) * nrhs);
+        schur(op, prec, o, i, parity_view(op->tmp[0].ptr, prec, g, nrhs), kind == LQ_SCHUR_DAG, s);
+        break;
+    }
+    case LQ_SCHUR_NORMAL: {
+        op->tmp[0].ensure(fb(prec, g) * nrhs);
+        op->tmp[1].ensure(fb(prec, g) * nrhs);
+        const FieldView t = parity_view(op->tmp[0].ptr, prec, g, nrhs);
+        const FieldView m = parity_view(op->tmp[1].ptr, prec, g, nrhs);
+        schur(op, prec, m, i, t, false, s);
+        schur(op, prec, o, m, t, true, s);
+        break;
+    }
+    case LQ_HOP_EO: hop(op, prec, o, i, 0, false, 0, false, nullptr, 1.0, 0, nullptr, s); break;
+    case LQ_HOP_OE: hop(op, prec, o, i, 1, false, 0, false, nullptr, 1.0, 0, nullptr, s); break;
+    case LQ_HOP_EO_DAG: hop(op, prec, o, i, 0, true, 0, false, nullptr, 1.0, 0, nullptr, s); break;
+    case LQ_HOP_OE_DAG: hop(op, prec, o, i, 1, true, 0, false, nullptr, 1.0, 0, nullptr, s); break;
+    case LQ_CLOVER_E: clover_apply(op, prec, 0, false, o, i, s); break;
+    case LQ_CLOVER_O: clover_apply(op, prec, 1, false, o, i, s); break;
+    case LQ_CLOVER_INV_O: clover_apply(op, prec, 1, true, o, i, s); break;
+    default: throw Failure{LQ_ERR_ARG, "unknown operator kind"};
+    }
+}
+
+}  // namespace lq

@@ -1,0 +1,131 @@
+// stencil.h -- per-site pieces of the hopping term of eq. (1) (Sec. 3) and
+// of the clover term, shared by the operator, force and batch kernels.
+#pragma once
+
+#include "lq_common.h"
+
+namespace lq {
+
+// h = psi_up + s B psi_dn, B the upper-right 2x2 block of gamma_mu in the
+// chiral basis: B = -i sigma_1, -i sigma_2, -i sigma_3, 1 for mu = x, y, z, t.
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void project(const Spinor<R> &p, cx<R> h[6])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<R> b0, b1;  // (B psi_dn)_0, (B psi_dn)_1
+        const cx<R> d2 = p.c[6 + a], d3 = p.c[9 + a];
+        if constexpr (MU == 0) { b0 = tmi(d3); b1 = tmi(d2); }
+        else if constexpr (MU == 1) { b0 = mk(-d3.re, -d3.im); b1 = d2; }
+        else if constexpr (MU == 2) { b0 = tmi(d2); b1 = ti(d3); }
+        else { b0 = d2; b1 = d3; }
+        if constexpr (SG > 0) {
+            h[a] = p.c[a] + b0;
+            h[3 + a] = p.c[3 + a] + b1;
+        } else {
+            h[a] = p.c[a] - b0;
+            h[3 + a] = p.c[3 + a] - b1;
+        }
+    }
+}
+
+// acc += (u, s B^dag u) with u the colour-multiplied half spinor.
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void reconstruct(cx<R> acc[12], const cx<R> u[6])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<R> u0 = u[a], u1 = u[3 + a];
+        cx<R> l0, l1;  // (B^dag u)_0, (B^dag u)_1
+        if constexpr (MU == 0) { l0 = ti(u1); l1 = ti(u0); }
+        else if constexpr (MU == 1) { l0 = u1; l1 = mk(-u0.re, -u0.im); }
+        else if constexpr (MU == 2) { l0 = ti(u0); l1 = tmi(u1); }
+        else { l0 = u0; l1 = u1; }
+        acc[a] = acc[a] + u0;
+        acc[3 + a] = acc[3 + a] + u1;
+        if constexpr (SG > 0) {
+            acc[6 + a] = acc[6 + a] + l0;
+            acc[9 + a] = acc[9 + a] + l1;
+        } else {
+            acc[6 + a] = acc[6 + a] - l0;
+            acc[9 + a] = acc[9 + a] - l1;
+        }
+    }
+}
+
+// Load link (parity p, direction mu, site cb) as 9 complex numbers.
+template <int P, int NL>
+__device__ __forceinline__ void load_link(const char *__restrict__ links, int vh, int p, int mu, int cb,
+                                          cx<typename PT<P>::R> u[9])
+{
+    using S = typename PT<P>::S;
+    using R = typename PT<P>::R;
+    const char *base = links + (long)(p * 4 + mu) * Planes<S, NL>::field_bytes(vh);
+    S raw[NL];
+    load_planes<S, NL>(base, cb, vh, raw);
+#pragma unroll
+    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)raw[2 * i], (R)raw[2 * i + 1]};
+    if constexpr (NL == 12) {
+        // third row of an SU(3) matrix: conj(row0 x row1)
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
+// out = U h (dag = false) or U^dag h, for the two spin rows of h.
+template <bool DAGU, typename R>
+__device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[6], cx<R> o[6])
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> acc;
+            if constexpr (!DAGU) {
+                acc = u[a * 3 + 0] * h[s * 3 + 0];
+                acc = acc + u[a * 3 + 1] * h[s * 3 + 1];
+                acc = acc + u[a * 3 + 2] * h[s * 3 + 2];
+            } else {
+                acc = cmulc(u[0 * 3 + a], h[s * 3 + 0]);
+                acc = acc + cmulc(u[1 * 3 + a], h[s * 3 + 1]);
+                acc = acc + cmulc(u[2 * 3 + a], h[s * 3 + 2]);
+            }
+            o[s * 3 + a] = acc;
+        }
+}
+
+// y = C x with C two packed 6x6 Hermitian blocks: per block 6 real diagonal
+// entries then the 15 strictly-lower entries (row-major) as complex pairs.
+template <int P>
+__device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh, int cb,
+                                           Spinor<typename PT<P>::R> &v)
+{
+    using S = typename PT<P>::S;
+    using R = typename PT<P>::R;
+    S raw[72];
+    load_planes<S, 72>(clov, cb, vh, raw);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const S *c = raw + 36 * b;
+        cx<R> x[6], y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = v.c[6 * b + i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) y[i] = (R)c[i] * x[i];
+        int k = 6;
+#pragma unroll
+        for (int i = 1; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < i; ++j) {
+                const cx<R> l = cx<R>{(R)c[k], (R)c[k + 1]};
+                k += 2;
+                y[i] = y[i] + l * x[j];
+                y[j] = y[j] + cmulc(l, x[i]);
+            }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v.c[6 * b + i] = y[i];
+    }
+}
+
+}  // namespace lq

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/lq.h declares, and rejects bad arguments on the
+host before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lq.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2111_04457_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2111_04457_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for name in syms:
+        assert hasattr(lib, name), name
+    from paper_2111_04457_amd import _lib
+    assert set(syms) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_defaults(lib):
+    from paper_2111_04457_amd import _lib
+    assert b"gfx950" in lib.lq_version()
+    p = _lib.OpParams()
+    lib.lq_op_params_default(ctypes.byref(p))
+    assert list(p.dims) == [4, 4, 4, 4] and p.link_recon == 18 and p.clover_traceless == 1
+    s = _lib.SolverParams()
+    lib.lq_solver_params_default(ctypes.byref(s))
+    assert s.solver == _lib.BICGSTAB and s.tol == 1e-10 and s.even_odd == 1
+
+
+def _params(**kw):
+    from paper_2111_04457_amd import _lib
+    lib = _lib.load()
+    p = _lib.OpParams()
+    lib.lq_op_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "dims":
+            for i in range(4):
+                p.dims[i] = v[i]
+        elif k == "bc":
+            for i in range(4):
+                p.bc[i][0], p.bc[i][1] = v[i].real, v[i].imag
+        else:
+            setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(dims=(4, 4, 3, 4)), b"even"),
+    (dict(dims=(0, 4, 4, 4)), b"even"),
+    (dict(kappa=float("nan")), b"finite"),
+    (dict(csw=float("inf")), b"finite"),
+    (dict(bc=(1, 1, 1, 0.5)), b"modulus"),
+    (dict(link_recon=8), b"link_recon"),
+])
+def test_create_rejects_bad_arguments_on_host(lib, kw, frag):
+    p = _params(**kw)
+    h = ctypes.c_void_p()
+    st = lib.lq_op_create(ctypes.byref(p), ctypes.byref(h))
+    assert st == -1
+    assert frag in lib.lq_last_error()
+    assert not h.value
+
+
+def test_null_arguments(lib):
+    from paper_2111_04457_amd import _lib
+    h = ctypes.c_void_p()
+    assert lib.lq_op_create(None, ctypes.byref(h)) == -1
+    assert lib.lq_op_set_gauge(None, None, None) == -1
+    assert lib.lq_op_apply(None, 0, 0, None, None, 1, None) == -1
+    sp = _lib.SolverParams()
+    lib.lq_solver_params_default(ctypes.byref(sp))
+    assert lib.lq_solve(None, ctypes.byref(sp), 0, 1, None, None, 0, None, None) == -1
+    lib.lq_op_destroy(None)
+    lib.lq_field_destroy(None)
+
+
+def test_no_device_reported_without_gpu(lib):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = _params(dims=(4, 4, 4, 4))
+    h = ctypes.c_void_p()
+    assert lib.lq_op_create(ctypes.byref(p), ctypes.byref(h)) == -7
+    assert lib.lq_last_error()
+
+
+def test_traffic_model_matches_compulsory_bytes():
+    """Algorithmic bytes per output site: 8 links + spinor in + spinor out
+    (+ clover block) as stated with the hopping term of eq. (1)."""
+    per = {"f64": 8, "f32": 4, "f16": 2}
+    for prec, rs in per.items():
+        spin = 24 * rs + (4 if prec == "f16" else 0)
+        assert 8 * 18 * rs + 2 * spin == {"f64": 1536, "f32": 768, "f16": 392}[prec]
+    assert math.isclose(8 * 12 * 2 + 2 * (48 + 4), 296)
