@@ -1,0 +1,241 @@
+"""Benchmark of the mixed-precision even-odd clover propagator solve.
+
+One step = one complete solve D x = b to a true FP64 residual of 1e-10 on
+the 32^3 x 64 Wilson-clover lattice (links exp(i 0.5 H), kappa 0.1355,
+c_sw 1.7, antiperiodic in time): FP16-stored links and spinors with FP32
+arithmetic in the inner BiCGStab, FP64 defect correction outside, even-odd
+prepare / reconstruct and the final full-lattice residual included.
+
+Printed: one JSON line.  `value` is the whole-step dslash throughput: the
+algorithmic bytes of every hopping-term apply the solve performed (links,
+spinor in/out, clover block, per apply) divided by the step time.  The
+`roofline` entry times the dslash kernel alone (FP16, 12-real links) with
+HIP events on the stream it runs on; `cpu_baseline` times the FP64 oracle's
+hopping term on the host cores.  Inputs are generated on the host and
+copied to HBM before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lq_common.h", "stencil.h", "dslash_impl.h", "dslash.h"):
+        with open(os.path.join(ROOT, "paper_2111_04457_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_dslash_f16_32x32x32x64.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != _kernel_source_hash() or vals.get("kernel") != kernel_tag:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="clover_32x32x32x64")
+    ap.add_argument("--inner", default="f16", choices=["f16", "f32", "f64"])
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cgne"])
+    ap.add_argument("--recon", type=int, default=12, choices=[12, 18])
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32-inner reference solves")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2111_04457_amd as lq
+    from lattice_inputs import ANTIPERIODIC_T, WORKLOADS, workload_gauge, workload_source
+
+    from paper_2111_04457_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+
+    w = WORKLOADS[args.workload]
+    dims = w["dims"]
+    V = int(np.prod(dims))
+    t_gen = time.time()
+    U = workload_gauge(args.workload)
+    b = workload_source(args.workload)
+    print("bench: inputs %s generated in %.1f s" % (args.workload, time.time() - t_gen), file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    U_d = torch.from_numpy(U).cuda()
+    b_d = torch.from_numpy(b).cuda()
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=args.recon)
+    op.set_gauge(U_d)
+    del U_d
+    torch.cuda.synchronize()
+
+    inner_tol = {"f16": 1e-2, "f32": 1e-5, "f64": 1e-5}[args.inner]
+    prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10)
+
+    for _ in range(args.warmup):
+        op.solve(b_d, "D", prm)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hop_bytes = 0.0
+    stats = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    x_d = None
+    for _ in range(args.steps):
+        x_d, st = op.solve(b_d, "D", prm)
+        hop_bytes += st[0].hop_bytes
+        stats.append(st[0])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = hop_bytes / wall / 1e9
+    print("bench: %d steps, %.1f ms/step, iters %d outer %d diff %.2e" %
+          (args.steps, ms_per_step, stats[-1].nconv, stats[-1].nouter, stats[-1].diff), file=sys.stderr, flush=True)
+
+    # time to solution of the reference solves on the same GPU
+    tts = {"mixed_%s_ms" % args.inner: ms_per_step, "mixed_%s_iters" % args.inner: stats[-1].nconv,
+           "mixed_%s_outer" % args.inner: stats[-1].nouter, "mixed_%s_diff" % args.inner: stats[-1].diff}
+    if not args.no_compare:
+        refs = {}
+        for inner in ("f64", "f32"):
+            if inner == args.inner:
+                continue
+            p2 = lq.SolverParams(solver=args.solver, tol=args.tol, inner=inner,
+                                 inner_tol={"f32": 1e-5, "f64": 1e-5}[inner], check_every=10)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            xr, sr = op.solve(b_d, "D", p2)
+            torch.cuda.synchronize()
+            tts["%s_ms" % ("fp64" if inner == "f64" else "mixed_f32")] = 1e3 * (time.perf_counter() - ta)
+            tts["%s_iters" % ("fp64" if inner == "f64" else "mixed_f32")] = sr[0].nconv
+            tts["%s_diff" % ("fp64" if inner == "f64" else "mixed_f32")] = sr[0].diff
+            refs[inner] = xr
+        if "f64" in refs:
+            x64 = refs["f64"]
+            tts["err_vs_fp64_solution"] = float(torch.linalg.vector_norm(x_d - x64) / torch.linalg.vector_norm(x64))
+            tts["speedup_vs_fp64"] = tts["fp64_ms"] / ms_per_step
+        print("bench: reference solves %s" % json.dumps(tts), file=sys.stderr, flush=True)
+
+    # dslash kernel alone: hopping term even -> odd on resident packed fields
+    kern = {}
+    roof = None
+    for prec in ("f16", "f32", "f64"):
+        fin = lq.Field(op, prec)
+        fout = lq.Field(op, prec)
+        fin.load(b_d.reshape(-1, 4, 3)[: V // 2].contiguous())
+        for _ in range(3):
+            lq.apply_field(op, "hop_oe", fout, fin)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            lq.apply_field(op, "hop_oe", fout, fin)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.kernel_reps
+        bps, fps = op.traffic(prec, 1, clover=False)
+        gbs = bps * (V // 2) / (ms * 1e-3) / 1e9
+        kern["dslash_%s_us" % prec] = 1e3 * ms
+        kern["dslash_%s_GBs" % prec] = gbs
+        kern["dslash_%s_TFLOPs" % prec] = fps * (V // 2) / (ms * 1e-3) / 1e12
+        if prec == args.inner or (prec == "f16" and roof is None):
+            tag = "hop_kernel<%s,%d,dag=0,clov=0,xpay=0,red=0,256>" % (prec, 18 if prec == "f64" else args.recon)
+            traffic = _traffic_from_profile(tag) if prec == "f16" else None
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "traffic": traffic, "kernel": tag, "bytes_per_launch": bps * (V // 2),
+                    "avg_launch_us": 1e3 * ms}
+        fin.close()
+        fout.close()
+    # device copy probe (1 GiB read + 1 GiB write)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        c.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kern["copy_probe_GBs"] = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    print("bench: kernels %s" % json.dumps(kern), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ncores = len(os.sched_getaffinity(0))
+        oracle.set_num_threads(ncores)
+        reps = 3
+        ta = time.perf_counter()
+        for _ in range(reps):
+            oracle.hop(dims, U, ANTIPERIODIC_T, b)
+        tc = (time.perf_counter() - ta) / reps
+        # the oracle applies H on both parities: V output sites, FP64 bytes per site
+        cpu = {"value": 1536.0 * V / tc / 1e9, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d full-lattice FP64 hopping-term applies of the oracle on %s (%d sites each), %.2f s each"
+                         % (reps, args.workload, V, tc)}
+
+    op.close()
+    line = {
+        "metric": "dslash GB/s (% HBM peak); time to 1e-10 residual, mixed vs FP64 solve",
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f16": "f16-storage/f32", "f32": "f32", "f64": "f64"}[args.inner] + "+f64-outer",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "kappa": w["kappa"], "csw": w["csw"],
+                   "links": "exp(i*%.1f*H)" % w["eps"], "solver": args.solver, "inner": args.inner,
+                   "link_recon": args.recon, "tol": args.tol, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "time_to_solution": tts,
+        "kernels": kern,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

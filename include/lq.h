@@ -189,6 +189,15 @@ lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_fie
  * site is summed in the same order whatever the launch shape. */
 lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
 
+/* Other execution options (none changes a result bit):
+ *   "xcd_remap" 0|1  XCD-aware order of the hopping kernel's workgroups (default 1),
+ *                    all precisions; "xcd_remap_f64" / "_f32" / "_f16" per precision;
+ *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1).
+ * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16".
+ * LQ_ERR_ARG for an unknown name or value. */
+lq_status lq_op_set_option(lq_op *op, const char *name, int value);
+lq_status lq_op_get_option(const lq_op *op, const char *name, int *value);
+
 /* Algorithmic HBM bytes and flops of one parity hopping-term apply per
  * output site and right-hand side for the given precision, with (clover = 1)
  * or without the fused clover epilogue: compulsory traffic only (8 links,
@@ -205,6 +214,36 @@ lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, dou
  * LQ_ERR_NONFINITE if b or an intermediate residual is not finite. */
 lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
                    int use_x0, lq_solve_stats *stats, void *stream);
+
+/* Autotuner: for each storage precision, times the Schur operator (the two
+ * fused hopping kernels of every solver iteration, nrhs right-hand sides)
+ * over workgroup sizes {64, 128, 256} and both workgroup orders with HIP
+ * events, requires every candidate's output to be bitwise equal to the
+ * first's, and keeps the fastest on the operator.  Results are cached in
+ * the JSON file cache_path (or $LQ_TUNE_CACHE; NULL and unset: no cache),
+ * keyed by kernel, precision, lattice, link format, nrhs and architecture;
+ * cached entries are applied without timing.  report (may be NULL) receives
+ * a JSON summary, truncated to report_len bytes.  Uses (and overwrites) the
+ * operator's scratch fields; synchronizes the stream. */
+lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, size_t report_len, void *stream);
+
+/* Pseudofermion action and force (molecular-dynamics force of the gauge-field
+ * generation the paper's Sec. 2 describes, whose solves are the bottleneck):
+ *   variant 0 (even-odd):  S = phi^dag (M^dag M)^-1 phi,  M = 1 - kappa^2 H_eo H_oe,
+ *                          phi a device complex128 parity field [V/2][4][3] on even sites;
+ *   variant 1 (full):      S = phi^dag (D^dag D)^-1 phi,  phi a full field [V][4][3].
+ * The solve runs with sp (FP64 defect correction around sp->inner); the force
+ * kernel computes in force_prec (LQ_F64 or LQ_F32).  Outputs (device
+ * complex128, each may be NULL):
+ *   dSdU  [V][4][3][3]  the gradient of S with respect to the link entries,
+ *                       dS = Re sum conj(dSdU) dU, i.e. M^dag for the matrix M
+ *                       with dS = sum Re tr(M dU) (the torch convention);
+ *   G     [V][4][3][3]  the su(3) force -TA(U M), so that dS/de along
+ *                       U -> exp(e X) U equals sum Re tr(G^dag X);
+ *   X_out               X = (M^dag M)^-1 phi (layout of phi).
+ * *S receives the action.  Wilson operator only (csw = 0, else LQ_ERR_ARG). */
+lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
+                      void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

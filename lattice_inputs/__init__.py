@@ -43,16 +43,55 @@ def haar_su3(rng: np.random.Generator, n: int) -> np.ndarray:
     return q
 
 
-def exp_iH_su3(rng: np.random.Generator, n: int, eps: float) -> np.ndarray:
-    """n matrices U = exp(i*eps*H), H traceless Hermitian built from a complex
-    matrix with unit-variance Gaussian real and imaginary parts."""
+def random_traceless_hermitian(rng: np.random.Generator, n: int) -> np.ndarray:
+    """H = (A + A^dag)/2 minus its trace, A with unit-variance Gaussian real
+    and imaginary parts."""
     a = rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
     h = 0.5 * (a + np.conj(np.swapaxes(a, -1, -2)))
     tr = np.trace(h, axis1=-2, axis2=-1).real / 3.0
-    h = h - tr[:, None, None] * np.eye(3)[None]
-    w, v = np.linalg.eigh(h)
-    ph = np.exp(1j * eps * w)
-    return (v * ph[:, None, :]) @ np.conj(np.swapaxes(v, -1, -2))
+    return h - tr[:, None, None] * np.eye(3)[None]
+
+
+def expi_traceless_hermitian(q: np.ndarray) -> np.ndarray:
+    """exp(i Q) for traceless Hermitian 3x3 Q, in closed form (Morningstar and
+    Peardon, Phys. Rev. D 69 (2004) 054501, Sec. III): exp(iQ) = f0 + f1 Q +
+    f2 Q^2 with f_j from c0 = det Q and c1 = tr(Q^2)/2; negative c0 is
+    mapped to positive by f_j(-c0) = (-1)^j conj(f_j(c0))."""
+    q2 = q @ q
+    c0 = np.linalg.det(q).real
+    c1 = 0.5 * np.trace(q2, axis1=-2, axis2=-1).real
+    neg = c0 < 0
+    c0a = np.abs(c0)
+    c1 = np.maximum(c1, 1e-300)
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    theta = np.arccos(np.clip(c0a / c0max, -1.0, 1.0))
+    u = np.sqrt(c1 / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1) * np.sin(theta / 3.0)
+    xi0 = np.where(np.abs(w) > 0.05, np.sin(w) / np.where(w == 0, 1, w),
+                   1 - w ** 2 / 6 * (1 - w ** 2 / 20 * (1 - w ** 2 / 42)))
+    e2iu = np.exp(2j * u)
+    emiu = np.exp(-1j * u)
+    cw = np.cos(w)
+    h0 = (u * u - w * w) * e2iu + emiu * (8 * u * u * cw + 2j * u * (3 * u * u + w * w) * xi0)
+    h1 = 2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u * u - w * w) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9 * u * u - w * w
+    f0, f1, f2 = h0 / den, h1 / den, h2 / den
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    eye = np.eye(3)[None]
+    return f0[:, None, None] * eye + f1[:, None, None] * q + f2[:, None, None] * q2
+
+
+def exp_iH_su3(rng: np.random.Generator, n: int, eps: float, chunk: int = 1 << 20) -> np.ndarray:
+    """n matrices U = exp(i*eps*H), H traceless Hermitian built from a complex
+    matrix with unit-variance Gaussian real and imaginary parts."""
+    out = np.empty((n, 3, 3), dtype=np.complex128)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        out[s:s + m] = expi_traceless_hermitian(eps * random_traceless_hermitian(rng, m))
+    return out
 
 
 def gauge_haar(dims, seed: int) -> np.ndarray:

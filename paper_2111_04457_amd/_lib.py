@@ -62,8 +62,13 @@ SIGNATURES = {
     "lq_field_export": (I, [P, P, P]),
     "lq_op_apply_field": (I, [P, I, P, P, P]),
     "lq_op_set_block": (I, [P, I, I]),
+    "lq_op_set_option": (I, [P, ctypes.c_char_p, I]),
+    "lq_op_get_option": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
     "lq_op_traffic": (I, [P, I, I, I, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "lq_solve": (I, [P, ctypes.POINTER(SolverParams), I, I, P, P, I, ctypes.POINTER(SolveStats), P]),
+    "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
+    "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
+                        ctypes.POINTER(SolveStats), P]),
 }
 
 _LIB = None

@@ -140,6 +140,24 @@ class Operator:
                                    ctypes.byref(f)))
         return b.value, f.value
 
+    def set_option(self, name: str, value: int):
+        check(load().lq_op_set_option(self._h, name.encode(), int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int()
+        check(load().lq_op_get_option(self._h, name.encode(), ctypes.byref(v)))
+        return v.value
+
+    def set_block(self, prec: str, block: int):
+        check(load().lq_op_set_block(self._h, _lib.PREC[prec], int(block)))
+
+    def tune(self, nrhs: int = 1, cache: str | None = None) -> dict:
+        """Autotune the hopping kernels (lq_tune); returns the JSON report."""
+        import json
+        buf = ctypes.create_string_buffer(4096)
+        check(load().lq_tune(self._h, int(nrhs), cache.encode() if cache else None, buf, len(buf), _stream()))
+        return json.loads(buf.value.decode())
+
     def solve(self, b: torch.Tensor, mode: str = "D", params: SolverParams | None = None,
               x0: torch.Tensor | None = None):
         """x = mode^-1 b for mode D, Ddag or DdagD (invert of Fig. 1).
@@ -201,3 +219,52 @@ class Field:
 
 def apply_field(op: Operator, kind: str, out: Field, inp: Field):
     check(load().lq_op_apply_field(op.handle, _lib.KINDS[kind], out.handle, inp.handle, _stream()))
+
+
+def pf_force(op: Operator, phi: torch.Tensor, params: SolverParams | None = None, variant: str = "eo",
+             force_prec: str = "f64", want_x: bool = False):
+    """Pseudofermion action and force on the operator's gauge field.
+    variant "eo": S = phi^dag (M^dag M)^-1 phi with phi on even sites [V/2, 4, 3];
+    "full": S = phi^dag (D^dag D)^-1 phi with phi a full field.
+    Returns (S, grad_U, G, X, stats): grad_U the torch-convention gradient
+    dS/dU, G = -TA(U M) the su(3) force, X = (A)^-1 phi if want_x."""
+    params = params or SolverParams(tol=1e-12, inner="f64", solver="cgne")
+    shape = op.parity_shape if variant == "eo" else op.full_shape
+    phi = _dev(phi, shape, "phi")
+    gshape = tuple(op.dims[::-1]) + (4, 3, 3)
+    grad = torch.empty(gshape, dtype=torch.complex128, device="cuda")
+    G = torch.empty_like(grad)
+    X = torch.empty_like(phi) if want_x else None
+    S = ctypes.c_double()
+    st = _lib.SolveStats()
+    cp = params.to_c()
+    rc = load().lq_pf_force(op.handle, ctypes.byref(cp), 0 if variant == "eo" else 1, _lib.PREC[force_prec],
+                            ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                            ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(X.data_ptr()) if X is not None else None,
+                            ctypes.byref(S), ctypes.byref(st), _stream())
+    check(rc, allow_not_converged=True)
+    stats = SolveStats(st.nconv, st.nouter, st.restarts, bool(st.converged), st.diff, st.t_solve_ms, st.hop_bytes,
+                       st.n_hop)
+    return S.value, grad, G, X, stats
+
+
+class PseudofermionAction(torch.autograd.Function):
+    """S(U, phi) = phi^dag (M^dag M)^-1 phi (Wilson, even-odd) or
+    phi^dag (D^dag D)^-1 phi (variant "full") as a differentiable function.
+
+    The forward pass loads U into the operator and runs one solve and the
+    hand-written force kernel (lq_pf_force), which yields S, dS/dU and
+    X = (M^dag M)^-1 phi together; backward scales them by the incoming
+    gradient: dS/dU as computed, dS/dphi = 2 X (S is real)."""
+
+    @staticmethod
+    def forward(ctx, U, phi, op, params=None, variant="eo", force_prec="f64"):
+        op.set_gauge(U)
+        S, grad_U, _, X, _ = pf_force(op, phi, params, variant, force_prec, want_x=True)
+        ctx.save_for_backward(grad_U, X)
+        return torch.tensor(S, dtype=torch.float64, device=U.device)
+
+    @staticmethod
+    def backward(ctx, gS):
+        grad_U, X = ctx.saved_tensors
+        return gS * grad_U, 2.0 * gS * X, None, None, None, None

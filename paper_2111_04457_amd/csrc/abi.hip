@@ -121,6 +121,9 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
             op->links[F32].ensure(8 * link_bytes(F32, p->link_recon, g.vh));
             op->links[F16].ensure(8 * link_bytes(F16, p->link_recon, g.vh));
             op->flag.ensure(sizeof(int));
+            LQ_HIP(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
+            LQ_HIP(hipEventCreateWithFlags(&op->ev_in, hipEventDisableTiming));
+            LQ_HIP(hipEventCreateWithFlags(&op->ev_out, hipEventDisableTiming));
         } catch (...) {
             delete op;
             throw;
@@ -168,6 +171,7 @@ lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream)
         hipStream_t s = static_cast<hipStream_t>(stream);
         const Geom &g = op->g;
         op->gauge_set = false;
+        op->clear_graphs();
         LQ_HIP(launch_pack_links_f64(g, static_cast<const double *>(U), op->links[F64].ptr, s));
         LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F32, op->prm.link_recon, op->links[F32].ptr, s));
         LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F16, op->prm.link_recon, op->links[F16].ptr, s));
@@ -187,6 +191,7 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
                 return arg_error("lq_op_set_params: boundary phases must have modulus 1");
     return guarded([&]() -> lq_status {
         select_device(op);
+        op->clear_graphs();
         op->prm.kappa = kappa;
         op->prm.csw = csw;
         op->has_clover = csw != 0.0;
@@ -320,6 +325,36 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block)
     if (!valid_prec(prec)) return arg_error("lq_op_set_block: unknown precision");
     if (block != 64 && block != 128 && block != 256) return arg_error("lq_op_set_block: block must be 64, 128 or 256");
     op->hop_block[prec] = block;
+    op->clear_graphs();
+    return LQ_OK;
+}
+
+lq_status lq_op_set_option(lq_op *op, const char *name, int value)
+{
+    if (!op || !name) return arg_error("lq_op_set_option: null argument");
+    const std::string n(name);
+    if (n == "xcd_remap" && (value == 0 || value == 1)) op->xcd_remap[0] = op->xcd_remap[1] = op->xcd_remap[2] = value;
+    else if (n == "xcd_remap_f64" && (value == 0 || value == 1)) op->xcd_remap[F64] = value;
+    else if (n == "xcd_remap_f32" && (value == 0 || value == 1)) op->xcd_remap[F32] = value;
+    else if (n == "xcd_remap_f16" && (value == 0 || value == 1)) op->xcd_remap[F16] = value;
+    else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
+    else return arg_error("lq_op_set_option: unknown option or value: " + n);
+    op->clear_graphs();
+    return LQ_OK;
+}
+
+lq_status lq_op_get_option(const lq_op *op, const char *name, int *value)
+{
+    if (!op || !name || !value) return arg_error("lq_op_get_option: null argument");
+    const std::string n(name);
+    if (n == "xcd_remap" || n == "xcd_remap_f16") *value = op->xcd_remap[F16];
+    else if (n == "xcd_remap_f64") *value = op->xcd_remap[F64];
+    else if (n == "xcd_remap_f32") *value = op->xcd_remap[F32];
+    else if (n == "graphs") *value = op->use_graphs;
+    else if (n == "hop_block_f64") *value = op->hop_block[F64];
+    else if (n == "hop_block_f32") *value = op->hop_block[F32];
+    else if (n == "hop_block_f16") *value = op->hop_block[F16];
+    else return arg_error("lq_op_get_option: unknown option: " + n);
     return LQ_OK;
 }
 

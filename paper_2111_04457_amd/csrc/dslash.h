@@ -39,6 +39,7 @@ struct HopArgs {
     const char *w;       // second operand of a fused dot product, or null
     long w_n;
     long w_rs;
+    int xcd_remap;       // 1: XCD-aware tile order (result independent of it)
 };
 
 // Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;

@@ -58,8 +58,18 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT>
 __global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
 {
     using R = typename PT<P>::R;
-    const int cb = blockIdx.x * NT + threadIdx.x;
-    const int rhs = blockIdx.y;
+    // Workgroups are dispatched to the 8 XCDs round-robin; give each XCD a
+    // contiguous range of (site block, rhs) tiles so that neighbour spinors
+    // and, with several right-hand sides, the shared links of a site block
+    // are re-read from that XCD's L2.  rhs varies fastest within the range.
+    const int nbs = (a.g.vh + NT - 1) / NT;
+    const int total = nbs * a.nrhs;
+    const int full = a.xcd_remap ? (total / 8) * 8 : 0;
+    const int id = blockIdx.x;
+    const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
+    const int sblk = t / a.nrhs;
+    const int rhs = t - sblk * a.nrhs;
+    const int cb = sblk * NT + threadIdx.x;
     const bool valid = cb < a.g.vh;
     double red0 = 0.0, red1 = 0.0;
     if (valid) {
@@ -105,12 +115,12 @@ __global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
         __shared__ double lds[NT / 64];
         const double s0 = block_sum<NT>(red0, lds);
         if constexpr (RED == 1) {
-            if (threadIdx.x == 0) a.partial[(long)rhs * gridDim.x + blockIdx.x] = s0;
+            if (threadIdx.x == 0) a.partial[(long)rhs * nbs + sblk] = s0;
         } else {
             const double s1 = block_sum<NT>(red1, lds);
             if (threadIdx.x == 0) {
-                a.partial[2 * ((long)rhs * gridDim.x + blockIdx.x)] = s0;
-                a.partial[2 * ((long)rhs * gridDim.x + blockIdx.x) + 1] = s1;
+                a.partial[2 * ((long)rhs * nbs + sblk)] = s0;
+                a.partial[2 * ((long)rhs * nbs + sblk) + 1] = s1;
             }
         }
     }
@@ -119,7 +129,7 @@ __global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
 static hipError_t launch_nt(const HopArgs &a, int block, hipStream_t s)
 {
-    const dim3 grid(hop_blocks(a.g.vh, block), a.nrhs);
+    const dim3 grid(hop_blocks(a.g.vh, block) * a.nrhs);
     switch (block) {
     case 64: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 64><<<grid, 64, 0, s>>>(a); break;
     case 128: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 128><<<grid, 128, 0, s>>>(a); break;

@@ -1,0 +1,293 @@
+// force.hip -- pseudofermion force: the derivative of
+//   S = phi^dag (A)^-1 phi,  A = M^dag M (even-odd Wilson, M = 1 - kappa^2 H_eo H_oe)
+//                            or A = D^dag D (full lattice, D = 1 - kappa H)
+// with respect to every link, from the hopping term of eq. (1) (Sec. 3).
+//
+// With X = A^-1 phi: even-odd: Y = M X, Z = H_oe X, W = (H_eo)^dag Y and
+//   dS = 2 kappa^2 Re[ Y^dag dH_eo Z + W^dag dH_oe X ];
+// full lattice: Y = D X and dS = 2 kappa Re[ Y^dag dH X ].
+// For a pair Re[a^dag dH b] the link U_mu(x) receives, as the matrix M with
+// dS = sum Re tr(M dU), the forward term  ph sum_s [(1-g)b(x+mu)]_s a(x)_s^dag
+// plus the conjugate transpose of  conj(ph) sum_s [(1+g)b(x)]_s a(x+mu)_s^dag.
+// In the chiral basis (1 + s gamma_mu)/2 is a rank-2 projector, so each sum
+// is an outer product of the two projected half spinors:
+//   sum_s [(1+sg) b]_s a_s^dag = sum_{j=0,1} h^b_j (h^a_j)^dag,  h = up + s B dn.
+// The kernel writes the gradient M^dag (dS = Re sum conj(M^dag) dU) and the
+// su(3) force G = -TA(U M), where
+// TA(B) = (B - B^dag)/2 - tr(B - B^dag)/6.
+#include <chrono>
+#include <cmath>
+
+#include "solver.h"
+#include "stencil.h"
+
+namespace lq {
+
+struct ForceArgs {
+    Geom g;
+    const char *links;  // packed links of the force precision ([parity][mu])
+    // per output parity p: a, c on parity p; b, d on parity 1 - p
+    FieldView a[2], b[2], c[2], d[2];
+    double coef;
+    double *M;  // complex128 [V][4][3][3] (lex) or null
+    double *G;
+};
+
+template <int P, int NL, int MU>
+__device__ __forceinline__ void force_dir(const ForceArgs &f, int p, int cb, const int c[4], double *Mo, double *Go,
+                                          long lex)
+{
+    using R = typename PT<P>::R;
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    const bool wrap = d[MU] == f.g.L[MU] - 1;
+    d[MU] = wrap ? 0 : d[MU] + 1;
+    const int nb = cb_index(f.g, d);
+    const Spinor<R> av = load_spinor<P>(f.a[p].base, cb, f.a[p].n);
+    const Spinor<R> cv = load_spinor<P>(f.c[p].base, cb, f.c[p].n);
+    const Spinor<R> bv = load_spinor<P>(f.b[p].base, nb, f.b[p].n);
+    const Spinor<R> dv = load_spinor<P>(f.d[p].base, nb, f.d[p].n);
+    cx<R> ha[6], hb[6], hc[6], hd[6];
+    project<MU, -1>(av, ha);
+    project<MU, -1>(bv, hb);
+    project<MU, +1>(cv, hc);
+    project<MU, +1>(dv, hd);
+    cx<R> m[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cx<R> acc = cx<R>{0, 0};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                acc = acc + cmulc(ha[s * 3 + k], hb[s * 3 + i]);
+                acc = acc + cmulc(hc[s * 3 + k], hd[s * 3 + i]);
+            }
+            m[i * 3 + k] = acc;
+        }
+    cx<R> ph = cx<R>{(R)f.coef, 0};
+    if (wrap) ph = cx<R>{(R)(f.coef * f.g.bc_re[MU]), (R)(f.coef * f.g.bc_im[MU])};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] = ph * m[i];
+    if (Mo) {
+        // the gradient in the convention dS = Re sum conj(grad) dU: grad = M^dag
+        double *o = Mo + (lex * 4 + MU) * 18;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                o[2 * (i * 3 + k)] = (double)m[k * 3 + i].re;
+                o[2 * (i * 3 + k) + 1] = -(double)m[k * 3 + i].im;
+            }
+    }
+    if (Go) {
+        cx<R> u[9];
+        load_link<P, NL>(f.links, f.g.vh, p, MU, cb, u);
+        cx<R> bm[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                bm[i * 3 + k] = u[i * 3 + 0] * m[0 * 3 + k] + u[i * 3 + 1] * m[1 * 3 + k] + u[i * 3 + 2] * m[2 * 3 + k];
+        // G = -TA(B) = (B^dag - B)/2 + tr(B - B^dag)/6
+        const R tri = (bm[0].im + bm[4].im + bm[8].im) / (R)3;  // tr(B - B^dag)/6 = i Im tr(B)/3
+        double *o = Go + (lex * 4 + MU) * 18;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const cx<R> bik = bm[i * 3 + k], bki = bm[k * 3 + i];
+                R re = (R)0.5 * (bki.re - bik.re);
+                R im = (R)0.5 * (-bki.im - bik.im);
+                if (i == k) im += tri;
+                o[(i * 3 + k) * 2] = (double)re;
+                o[(i * 3 + k) * 2 + 1] = (double)im;
+            }
+    }
+}
+
+template <int P, int NL>
+__global__ __launch_bounds__(128) void force_kernel(ForceArgs f)
+{
+    const int cb = blockIdx.x * 128 + threadIdx.x;
+    const int p = blockIdx.y;
+    if (cb >= f.g.vh) return;
+    int c[4];
+    cb_coords(f.g, p, cb, c);
+    const long lex = c[0] + (long)f.g.L[0] * (c[1] + (long)f.g.L[1] * (c[2] + (long)f.g.L[2] * c[3]));
+    force_dir<P, NL, 0>(f, p, cb, c, f.M, f.G, lex);
+    force_dir<P, NL, 1>(f, p, cb, c, f.M, f.G, lex);
+    force_dir<P, NL, 2>(f, p, cb, c, f.M, f.G, lex);
+    force_dir<P, NL, 3>(f, p, cb, c, f.M, f.G, lex);
+}
+
+static hipError_t launch_force(const ForceArgs &f, int prec, int nl, hipStream_t s)
+{
+    const dim3 grid((f.g.vh + 127) / 128, 2);
+    if (prec == F64) force_kernel<F64, 18><<<grid, 128, 0, s>>>(f);
+    else if (prec == F32 && nl == 18) force_kernel<F32, 18><<<grid, 128, 0, s>>>(f);
+    else if (prec == F32 && nl == 12) force_kernel<F32, 12><<<grid, 128, 0, s>>>(f);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec,
+                                 const void *phi, void *dSdU, void *G, void *X_out, double *S,
+                                 lq_solve_stats *stats, void *stream)
+{
+    if (!op || !sp || !phi) {
+        set_error("lq_pf_force: null argument");
+        return LQ_ERR_ARG;
+    }
+    if (variant != 0 && variant != 1) {
+        set_error("lq_pf_force: variant must be 0 (even-odd) or 1 (full lattice)");
+        return LQ_ERR_ARG;
+    }
+    if (force_prec != LQ_F64 && force_prec != LQ_F32) {
+        set_error("lq_pf_force: force precision must be LQ_F64 or LQ_F32");
+        return LQ_ERR_ARG;
+    }
+    if (op->prm.csw != 0.0) {
+        set_error("lq_pf_force: the force is implemented for the Wilson operator (csw = 0)");
+        return LQ_ERR_ARG;
+    }
+    std::string why;
+    if (!lq::valid_solver_params(sp, why) && why != "the full-lattice solve is CGNE only") {
+        set_error("lq_pf_force: invalid solver parameters: " + why);
+        return LQ_ERR_ARG;
+    }
+    if (!op->gauge_set) {
+        set_error("lq_pf_force: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    try {
+        set_error("");
+        LQ_HIP(hipSetDevice(op->device));
+        hipStream_t us = static_cast<hipStream_t>(stream);
+        LQ_HIP(hipEventRecord(op->ev_in, us));
+        LQ_HIP(hipStreamWaitEvent(op->stream, op->ev_in, 0));
+        hipStream_t s = op->stream;
+        const Geom &g = op->g;
+        const bool eo = variant == 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        SolveCtx c;
+        make_ctx(c, op, 1, eo, sp->inner, s);
+        // phi packed into the solve space (FP64)
+        FieldView phiv = c.aux64;
+        if (eo) LQ_HIP(launch_pack_spinor(g, 0, 1, static_cast<const double *>(phi), phiv, s));
+        else
+            for (int p = 0; p < 2; ++p)
+                LQ_HIP(launch_pack_spinor(g, p, 0, static_cast<const double *>(phi),
+                                          FieldView{phiv.base + p * fb(F64, g), F64, (long)g.vh, 2 * fb(F64, g), 1},
+                                          s));
+        const std::vector<double> pn2 = norms2(c, phiv, c.sps);
+        if (!std::isfinite(pn2[0])) throw Failure{LQ_ERR_NONFINITE, "phi is not finite"};
+        // X = (M^dag M)^-1 phi
+        LQ_HIP(launch_zero(c.x64, s));
+        lq_solver_params sp2 = *sp;
+        const std::vector<double> target2{sp->tol * sp->tol * pn2[0]};
+        const OuterStats os = defect_correction(c, sp2, true, phiv, target2);
+        // final normal-system residual
+        c.apply(c.t64, c.x64, false);
+        c.apply(c.y64, c.t64, true);
+        LQ_HIP(launch_xmy_norm(c.r64, phiv, c.y64, c.partial, s));
+        LQ_HIP(launch_finish(c.partial, 1, c.sps, blas_blocks(g.vh), 1, FIN_NORM, c.sc, 0, s));
+        c.pull();
+        const double diff = pn2[0] > 0 ? std::sqrt(c.hsc[SC_NORM2] / pn2[0]) : 0.0;
+        // S = Re <phi, X>
+        LQ_HIP(launch_reduce(phiv, c.x64, RED_DOT, c.partial, s));
+        LQ_HIP(launch_finish(c.partial, 1, c.sps, blas_blocks(g.vh), 2, FIN_DOT, c.sc, 0, s));
+        c.pull();
+        const double Sval = c.hsc[SC_DOT_RE];
+
+        // Y, Z, W (FP64), in the odd scratch and solve vectors
+        const int fp = force_prec;
+        ForceArgs f{};
+        f.g = g;
+        f.links = op->links[fp].ptr;
+        f.M = static_cast<double *>(dSdU);
+        f.G = static_cast<double *>(G);
+        op->tmp[2].ensure(4 * (size_t)fb(F64, g) * 2);
+        op->tmp[3].ensure(4 * (size_t)fb(fp, g) * 2);
+        if (eo) {
+            const FieldView X = c.x64;
+            const FieldView Y = c.y64;
+            const FieldView Z = parity_view(op->tmp[2].ptr, F64, g, 1);
+            const FieldView W = parity_view(op->tmp[2].ptr + fb(F64, g), F64, g, 1);
+            c.apply(Y, X, false);
+            hop(op, F64, Z, X, 1, false, 0, false, nullptr, 1.0, 0, nullptr, s);
+            hop(op, F64, W, Y, 1, true, 0, false, nullptr, 1.0, 0, nullptr, s);
+            FieldView Xf = X, Yf = Y, Zf = Z, Wf = W;
+            if (fp != F64) {
+                char *b = op->tmp[3].ptr;
+                Xf = parity_view(b, fp, g, 1);
+                Yf = parity_view(b + fb(fp, g), fp, g, 1);
+                Zf = parity_view(b + 2 * fb(fp, g), fp, g, 1);
+                Wf = parity_view(b + 3 * fb(fp, g), fp, g, 1);
+                LQ_HIP(launch_copy(Xf, X, c.sc, 1, false, s));
+                LQ_HIP(launch_copy(Yf, Y, c.sc, 1, false, s));
+                LQ_HIP(launch_copy(Zf, Z, c.sc, 1, false, s));
+                LQ_HIP(launch_copy(Wf, W, c.sc, 1, false, s));
+            }
+            // even x: P(Y(x), Z(x+mu)) + Q^dag(X(x), W(x+mu)); odd x: Q^dag(Z(x), Y(x+mu)) + P(W(x), X(x+mu))
+            f.a[0] = Yf; f.b[0] = Zf; f.c[0] = Xf; f.d[0] = Wf;
+            f.a[1] = Wf; f.b[1] = Xf; f.c[1] = Zf; f.d[1] = Yf;
+            f.coef = 2.0 * op->prm.kappa * op->prm.kappa;
+        } else {
+            const FieldView X = c.x64;  // full: [parity] slices
+            const FieldView Y = c.y64;
+            c.apply(Y, X, false);
+            FieldView Xs = X, Ys = Y;
+            if (fp != F64) {
+                char *b = op->tmp[3].ptr;
+                Xs = FieldView{b, fp, (long)g.vh, fb(fp, g), 2};
+                Ys = FieldView{b + 2 * fb(fp, g), fp, (long)g.vh, fb(fp, g), 2};
+                LQ_HIP(launch_copy(Xs, X, c.sc, 2, false, s));
+                LQ_HIP(launch_copy(Ys, Y, c.sc, 2, false, s));
+            }
+            for (int p = 0; p < 2; ++p) {
+                const FieldView Xp{Xs.base + p * Xs.rs, fp, (long)g.vh, Xs.rs, 1};
+                const FieldView Xq{Xs.base + (1 - p) * Xs.rs, fp, (long)g.vh, Xs.rs, 1};
+                const FieldView Yp{Ys.base + p * Ys.rs, fp, (long)g.vh, Ys.rs, 1};
+                const FieldView Yq{Ys.base + (1 - p) * Ys.rs, fp, (long)g.vh, Ys.rs, 1};
+                f.a[p] = Yp; f.b[p] = Xq; f.c[p] = Xp; f.d[p] = Yq;
+            }
+            f.coef = 2.0 * op->prm.kappa;
+        }
+        if (dSdU || G) LQ_HIP(launch_force(f, fp, op->nl(fp), s));
+        if (X_out) {
+            if (eo) LQ_HIP(launch_unpack_spinor(g, 0, 1, c.x64, static_cast<double *>(X_out), s));
+            else
+                for (int p = 0; p < 2; ++p)
+                    LQ_HIP(launch_unpack_spinor(
+                        g, p, 0, FieldView{c.x64.base + p * fb(F64, g), F64, (long)g.vh, 2 * fb(F64, g), 1},
+                        static_cast<double *>(X_out), s));
+        }
+        LQ_HIP(hipEventRecord(op->ev_out, s));
+        LQ_HIP(hipStreamWaitEvent(us, op->ev_out, 0));
+        LQ_HIP(hipStreamSynchronize(s));
+        if (S) *S = Sval;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        const bool conv = diff <= sp->tol;
+        if (stats) {
+            stats->nconv = os.iters[0];
+            stats->nouter = os.outer[0];
+            stats->restarts = os.restarts[0];
+            stats->converged = conv;
+            stats->diff = diff;
+            stats->t_solve_ms = ms;
+            stats->hop_bytes = c.hop_bytes;
+            stats->n_hop = (int)c.n_hop;
+        }
+        return conv ? LQ_OK : LQ_NOT_CONVERGED;
+    } catch (const Failure &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return LQ_ERR_STATE;
+    }
+}

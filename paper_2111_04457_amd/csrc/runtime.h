@@ -53,6 +53,7 @@ struct lq_op {
     bool gauge_set = false;
     bool has_clover = false;
     int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
+    int xcd_remap[3] = {1, 1, 1};        // XCD-aware tile order of the hop kernel per precision
     lq::Buf links[3];                    // packed links per precision ([parity][mu])
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
@@ -63,7 +64,34 @@ struct lq_op {
     lq::Buf solver_sc;                   // solver scalars (device)
     double *host_sc = nullptr;           // pinned host mirror of the solver scalars
     size_t host_sc_n = 0;
-    ~lq_op() { if (host_sc) (void)hipHostFree(host_sc); }
+    int use_graphs = 1;                  // capture inner-iteration chunks in hipGraphs
+    hipStream_t stream = nullptr;        // internal stream of solves (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // captured inner-iteration chunks, keyed by everything the kernels read
+    struct GraphEntry {
+        std::vector<long> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        long n_hop = 0;
+        double hop_bytes = 0;
+    };
+    std::vector<GraphEntry> graphs;
+    void clear_graphs()
+    {
+        for (auto &e : graphs) {
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            if (e.graph) (void)hipGraphDestroy(e.graph);
+        }
+        graphs.clear();
+    }
+    ~lq_op()
+    {
+        clear_graphs();
+        if (host_sc) (void)hipHostFree(host_sc);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
     int nl(int prec) const { return prec == lq::F64 ? 18 : prm.link_recon; }
 };
 

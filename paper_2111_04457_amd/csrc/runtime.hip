@@ -60,6 +60,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     if (clov_mode && !op->has_clover) clov_mode = 0;
     if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
     a.coef = coef;
+    a.xcd_remap = op->xcd_remap[prec];
     const int block = op->hop_block[prec];
     if (red) {
         op->partial.ensure((size_t)hop_blocks(g.vh, block) * in.nrhs * 2 * sizeof(double));

@@ -1,0 +1,110 @@
+// solver.h -- FP64 defect correction around device-resident Krylov inner
+// solvers, shared by the propagator solve and the pseudofermion force.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "blas.h"
+#include "runtime.h"
+
+namespace lq {
+
+// Solver context: nsys systems on the solve space (even sites for the
+// even-odd Schur system, or the full lattice), workspace and scalars.
+struct SolveCtx {
+    lq_op *op = nullptr;
+    hipStream_t s = nullptr;
+    int nsys = 1;
+    bool eo = true;   // even-odd Schur system (else full lattice)
+    int sps = 1;      // slices per system of a solve-space vector
+    int pin = F64;    // inner storage precision
+    int px = F64;     // inner solution precision
+    double *sc = nullptr;       // device scalars [nsys][NSC]
+    double *hsc = nullptr;      // pinned host mirror
+    double *partial = nullptr;  // reduction partials
+    char *odd_tmp[3] = {nullptr, nullptr, nullptr};
+    long n_hop = 0;
+    double hop_bytes = 0;
+    // FP64 vectors of the solve space
+    FieldView x64, r64, y64, t64, aux64;
+    // inner vectors
+    FieldView ix, ir, ip, iv, is, it, irhat, iw, irin;
+
+    FieldView space(char *base, int p) const;
+    size_t space_bytes(int p) const;
+    void count_hops(int prec, int n);
+    // out = M in (dag: M^dag), in the precision of the views
+    void apply(const FieldView &out, const FieldView &in, bool dag);
+    void reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin);
+    void finish(int K, int op_fin, long n);
+    void pull();
+    void push();
+    // Run `chunk` iterations of body(); with graphs enabled the chunk is
+    // captured once into a hipGraph (keyed by kind, chunk and every buffer
+    // and setting the kernels read) and replayed.
+    template <typename Body> void run_chunk(int kind, int chunk, Body body);
+};
+
+template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body)
+{
+    if (!op->use_graphs) {
+        for (int k = 0; k < chunk; ++k) body();
+        return;
+    }
+    const std::vector<long> key = {kind, chunk, nsys, eo ? 1 : 0, pin, px, (long)op->solver_ws.ptr,
+                                   (long)op->solver_ws.bytes, (long)partial, (long)sc,
+                                   (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
+                                   (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2], (long)(void *)s};
+    lq_op::GraphEntry *e = nullptr;
+    for (auto &g : op->graphs)
+        if (g.key == key) e = &g;
+    if (!e) {
+        lq_op::GraphEntry ne;
+        ne.key = key;
+        const long n0 = n_hop;
+        const double b0 = hop_bytes;
+        LQ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int k = 0; k < chunk; ++k) body();
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        LQ_HIP(hipStreamEndCapture(s, &ne.graph));
+        LQ_HIP(hipGraphInstantiate(&ne.exec, ne.graph, nullptr, nullptr, 0));
+        ne.n_hop = n_hop - n0;
+        ne.hop_bytes = hop_bytes - b0;
+        n_hop = n0;
+        hop_bytes = b0;
+        op->graphs.push_back(ne);
+        e = &op->graphs.back();
+    }
+    LQ_HIP(hipGraphLaunch(e->exec, s));
+    n_hop += e->n_hop;
+    hop_bytes += e->hop_bytes;
+}
+
+// Allocate the workspace of a solve of nsys systems with inner precision
+// `inner` on the even-odd (eo) or full-lattice space.
+void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t s);
+
+struct OuterStats {
+    std::vector<int> iters, outer, restarts;
+};
+
+// Solve A x = rhs on the solve space to |rhs - A x|^2 <= target2[i] for
+// each system, A = M (normal = false; BiCGStab on M or CG on M^dag M) or
+// A = M^dag M (normal = true; CG).  x (c.x64) holds the initial guess.
+OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool normal, const FieldView &rhs,
+                             const std::vector<double> &target2);
+
+// Host-side validation of solver parameters; why holds the reason.
+bool valid_solver_params(const lq_solver_params *sp, std::string &why);
+
+// |v|^2 per system of a field with sps slices per system.
+std::vector<double> norms2(SolveCtx &c, const FieldView &v, int sps);
+
+}  // namespace lq

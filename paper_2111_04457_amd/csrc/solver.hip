@@ -4,22 +4,22 @@
 // propagator solve of the paper's Fig. 1 (a double-precision outer
 // template over a single-precision inner field type), solving D x = b.
 //
-// Outer loop (FP64): r = b_hat - M x; stop when |r| <= tol |b|; else
-// r_in = r / |r| in the inner precision, inner solve M e = r_in to a relative
-// residual max(inner_tol, tol |b| / (2 |r|)), x += |r| e.  Even-odd: M is the
-// Schur operator, b_hat = b_e + kappa H_eo A_oo^-1 b_o, and at the end
-// x_o = A_oo^-1 (b_o + kappa H_oe x_e); the reported diff is the true
-// residual |b - D x| / |b| of the full lattice in FP64.
+// Outer loop (FP64): r = rhs - A x; stop when |r|^2 <= target; else
+// r_in = r / |r| in the inner precision, inner solve to a relative residual
+// max(inner_tol, sqrt(target) / (2 |r|)), x += |r| e.  For D x = b on the
+// even-odd system: A is the Schur operator M, rhs = b_e + kappa H_eo
+// A_oo^-1 b_o, the odd half is x_o = A_oo^-1 (b_o + kappa H_oe x_e) and the
+// reported diff is the true residual |b - D x| / |b| of the full lattice in
+// FP64 (|b - D x| equals the Schur residual in exact arithmetic).
 //
 // Inner iterations keep every scalar on the device; the host reads the
 // scalars back every check_every iterations to stop the loop.
+#include "solver.h"
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
-
-#include "blas.h"
-#include "runtime.h"
 
 namespace lq {
 
@@ -37,178 +37,154 @@ struct Arena {
     }
 };
 
-struct Ctx {
-    lq_op *op;
-    hipStream_t s;
-    int nsys;
-    bool eo;          // even-odd Schur system (else full lattice)
-    int sps;          // slices per system of a solve-space vector
-    int pin, px;      // inner storage precision, inner solution precision
-    double *sc;       // device scalars [nsys][NSC]
-    double *hsc;      // pinned host mirror
-    double *partial;  // reduction partials
-    char *odd_tmp[3]; // odd scratch per precision (even-odd) / full scratch (full lattice)
-    long n_hop = 0;
-    double hop_bytes = 0;
-    const Geom &g() const { return op->g; }
-
-    // a vector of the solve space (even parity, or full lattice) in precision p
-    FieldView space(char *base, int p) const
-    {
-        return FieldView{base, p, (long)op->g.vh, fb(p, op->g), nsys * sps};
-    }
-    size_t space_bytes(int p) const { return (size_t)fb(p, op->g) * nsys * sps; }
-
-    void count_hops(int prec, int n)
-    {
-        double b, f;
-        lq_op_traffic(op, (lq_prec)prec, 1, op->has_clover ? 1 : 0, &b, &f);
-        n_hop += n;
-        hop_bytes += (double)n * b * op->g.vh * nsys;
-    }
-
-    // out = M in (dag: M^dag) in precision of the views
-    void apply(const FieldView &out, const FieldView &in, bool dag)
-    {
-        const int p = in.prec;
-        if (eo) {
-            schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, dag, s);
-        } else {
-            dirac_full(op, p, out.base, in.base, nsys, dag, s);
-        }
-        count_hops(p, 2);
-    }
-
-    void reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin)
-    {
-        LQ_HIP(launch_reduce(x, y, mode, partial, s));
-        const int K = mode == RED_NORM ? 1 : mode == RED_DOT ? 2 : 3;
-        LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(x.n), K, op_fin, sc, 1e-30, s));
-    }
-    void finish(int K, int op_fin, long n)
-    {
-        LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(n), K, op_fin, sc, 1e-30, s));
-    }
-
-    void pull()
-    {
-        LQ_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * NSC * nsys, hipMemcpyDeviceToHost, s));
-        LQ_HIP(hipStreamSynchronize(s));
-    }
-    void push()
-    {
-        LQ_HIP(hipMemcpyAsync(sc, hsc, sizeof(double) * NSC * nsys, hipMemcpyHostToDevice, s));
-    }
-};
-
-struct InnerVecs {
-    FieldView x, r, p, v, sv, t, rhat, w;
-};
-
-// Inner BiCGStab on M e = rin from e = 0.  Returns when every system is
-// done or broken down, or after max_iter iterations.
-int inner_bicgstab(Ctx &c, const InnerVecs &V, const FieldView &rin, int max_iter, int check_every)
+bool all_frozen(const SolveCtx &c)
 {
-    LQ_HIP(launch_zero(V.x, c.s));
-    LQ_HIP(launch_copy(V.r, rin, c.sc, c.sps, false, c.s));
-    LQ_HIP(launch_copy(V.rhat, rin, c.sc, c.sps, false, c.s));
-    LQ_HIP(launch_copy(V.p, rin, c.sc, c.sps, false, c.s));
-    c.reduce_finish(V.r, V.r, RED_NORM, FIN_INIT_BICG);
+    for (int i = 0; i < c.nsys; ++i) {
+        const double *h = c.hsc + i * NSC;
+        if (h[SC_DONE] == 0.0 && h[SC_BREAK] == 0.0) return false;
+    }
+    return true;
+}
+
+// Inner BiCGStab on M e = rin from e = 0 (SC_TARGET2 relative to |rin|).
+int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
+{
+    LQ_HIP(launch_zero(c.ix, c.s));
+    LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    LQ_HIP(launch_copy(c.irhat, c.irin, c.sc, c.sps, false, c.s));
+    LQ_HIP(launch_copy(c.ip, c.irin, c.sc, c.sps, false, c.s));
+    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_BICG);
     int it = 0;
     while (it < max_iter) {
         const int chunk = std::min(check_every, max_iter - it);
-        for (int k = 0; k < chunk; ++k) {
-            c.apply(V.v, V.p, false);
-            c.reduce_finish(V.rhat, V.v, RED_DOT, FIN_BICG_ALPHA);
-            LQ_HIP(launch_bicg_s(V.sv, V.r, V.v, c.sc, c.sps, c.s));
-            c.apply(V.t, V.sv, false);
-            c.reduce_finish(V.sv, V.t, RED_DOT_NORM, FIN_BICG_OMEGA);
-            LQ_HIP(launch_bicg_xr(V.x, V.r, V.p, V.sv, V.t, V.rhat, c.sc, c.sps, c.partial, c.s));
-            c.finish(3, FIN_BICG_RHO, V.r.n);
-            LQ_HIP(launch_bicg_p(V.p, V.r, V.v, c.sc, c.sps, c.s));
-        }
+        c.run_chunk(1, chunk, [&]() {
+            c.apply(c.iv, c.ip, false);
+            c.reduce_finish(c.irhat, c.iv, RED_DOT, FIN_BICG_ALPHA);
+            LQ_HIP(launch_bicg_s(c.is, c.ir, c.iv, c.sc, c.sps, c.s));
+            c.apply(c.it, c.is, false);
+            c.reduce_finish(c.is, c.it, RED_DOT_NORM, FIN_BICG_OMEGA);
+            LQ_HIP(launch_bicg_xr(c.ix, c.ir, c.ip, c.is, c.it, c.irhat, c.sc, c.sps, c.partial, c.s));
+            c.finish(3, FIN_BICG_RHO, c.ir.n);
+            LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));
+        });
         it += chunk;
         c.pull();
-        bool all = true;
-        for (int i = 0; i < c.nsys; ++i) {
-            const double *h = c.hsc + i * NSC;
-            if (h[SC_DONE] == 0.0 && h[SC_BREAK] == 0.0) all = false;
-        }
-        if (all) break;
+        if (all_frozen(c)) break;
     }
     return it;
 }
 
-// Inner CG on M^dag M e = M^dag rin from e = 0.
-int inner_cgne(Ctx &c, const InnerVecs &V, const FieldView &rin, int max_iter, int check_every)
+// Inner CG from e = 0 on M^dag M e = M^dag rin (normal_rhs = false) or on
+// M^dag M e = rin (normal_rhs = true); SC_TARGET2 relative to the initial
+// residual.
+int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, int check_every)
 {
-    LQ_HIP(launch_zero(V.x, c.s));
-    c.apply(V.r, rin, true);
-    LQ_HIP(launch_copy(V.p, V.r, c.sc, c.sps, false, c.s));
-    c.reduce_finish(V.r, V.r, RED_NORM, FIN_INIT_CG);
+    LQ_HIP(launch_zero(c.ix, c.s));
+    if (normal_rhs) LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    else c.apply(c.ir, c.irin, true);
+    LQ_HIP(launch_copy(c.ip, c.ir, c.sc, c.sps, false, c.s));
+    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_CG);
     int it = 0;
     while (it < max_iter) {
         const int chunk = std::min(check_every, max_iter - it);
-        for (int k = 0; k < chunk; ++k) {
-            c.apply(V.w, V.p, false);
-            c.reduce_finish(V.w, V.w, RED_NORM, FIN_CG_ALPHA);
-            c.apply(V.v, V.w, true);
-            LQ_HIP(launch_cg_xr(V.x, V.r, V.p, V.v, c.sc, c.sps, c.partial, c.s));
-            c.finish(1, FIN_CG_BETA, V.r.n);
-            LQ_HIP(launch_cg_p(V.p, V.r, c.sc, c.sps, c.s));
-        }
+        c.run_chunk(2, chunk, [&]() {
+            c.apply(c.iw, c.ip, false);
+            c.reduce_finish(c.iw, c.iw, RED_NORM, FIN_CG_ALPHA);
+            c.apply(c.iv, c.iw, true);
+            LQ_HIP(launch_cg_xr(c.ix, c.ir, c.ip, c.iv, c.sc, c.sps, c.partial, c.s));
+            c.finish(1, FIN_CG_BETA, c.ir.n);
+            LQ_HIP(launch_cg_p(c.ip, c.ir, c.sc, c.sps, c.s));
+        });
         it += chunk;
         c.pull();
-        bool all = true;
-        for (int i = 0; i < c.nsys; ++i) {
-            const double *h = c.hsc + i * NSC;
-            if (h[SC_DONE] == 0.0 && h[SC_BREAK] == 0.0) all = false;
-        }
-        if (all) break;
+        if (all_frozen(c)) break;
     }
     return it;
 }
 
 }  // namespace
 
-// Solve D x = b for nsys systems; b64, x64: full packed FP64 fields.
-// stats[i] filled for each system.  Returns LQ_OK or LQ_NOT_CONVERGED.
-lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x64, const char *b64, bool use_x0,
-                       lq_solve_stats *stats, hipStream_t s)
+FieldView SolveCtx::space(char *base, int p) const
+{
+    return FieldView{base, p, (long)op->g.vh, fb(p, op->g), nsys * sps};
+}
+
+size_t SolveCtx::space_bytes(int p) const { return (size_t)fb(p, op->g) * nsys * sps; }
+
+void SolveCtx::count_hops(int prec, int n)
+{
+    double b, f;
+    lq_op_traffic(op, (lq_prec)prec, 1, op->has_clover ? 1 : 0, &b, &f);
+    n_hop += n;
+    hop_bytes += (double)n * b * op->g.vh * nsys;
+}
+
+void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
+{
+    const int p = in.prec;
+    if (eo) schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, dag, s);
+    else dirac_full(op, p, out.base, in.base, nsys, dag, s);
+    count_hops(p, 2);
+}
+
+void SolveCtx::reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin)
+{
+    LQ_HIP(launch_reduce(x, y, mode, partial, s));
+    const int K = mode == RED_NORM ? 1 : mode == RED_DOT ? 2 : 3;
+    LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(x.n), K, op_fin, sc, 1e-30, s));
+}
+
+void SolveCtx::finish(int K, int op_fin, long n)
+{
+    LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(n), K, op_fin, sc, 1e-30, s));
+}
+
+void SolveCtx::pull()
+{
+    LQ_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * NSC * nsys, hipMemcpyDeviceToHost, s));
+    LQ_HIP(hipStreamSynchronize(s));
+}
+
+void SolveCtx::push() { LQ_HIP(hipMemcpyAsync(sc, hsc, sizeof(double) * NSC * nsys, hipMemcpyHostToDevice, s)); }
+
+void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t s)
 {
     const Geom &g = op->g;
-    Ctx c{op, s, nsys};
-    c.eo = sp.even_odd != 0;
-    c.sps = c.eo ? 1 : 2;
-    c.pin = sp.inner;
-    c.px = sp.inner == F64 ? F64 : F32;
-
-    // workspace
-    Arena A;
+    c.op = op;
+    c.s = s;
+    c.nsys = nsys;
+    c.eo = eo;
+    c.sps = eo ? 1 : 2;
+    c.pin = inner;
+    c.px = inner == F64 ? F64 : F32;
     const size_t f64b = c.space_bytes(F64), finb = c.space_bytes(c.pin), fxb = c.space_bytes(c.px);
-    const size_t odd = (size_t)fb(F64, g) * nsys * (c.eo ? 1 : 2);
-    const size_t need = 6 * f64b + 8 * finb + fxb + 3 * (odd + 256) + 2 * (size_t)fb(F64, g) * nsys + 64 * 256;
+    const size_t odd = (size_t)fb(F64, g) * nsys;
+    const size_t need = 5 * (f64b + 256) + 9 * (finb + 256) + (fxb + 256) + 3 * (odd + 256);
     op->solver_ws.ensure(need);
+    Arena A;
     A.base = op->solver_ws.ptr;
-    char *bh = A.take(f64b), *xs = A.take(f64b), *r64 = A.take(f64b), *y64 = A.take(f64b);
-    char *full_r = A.take(2 * (size_t)fb(F64, g) * nsys), *full_y = A.take(2 * (size_t)fb(F64, g) * nsys);
+    c.x64 = c.space(A.take(f64b), F64);
+    c.r64 = c.space(A.take(f64b), F64);
+    c.y64 = c.space(A.take(f64b), F64);
+    c.t64 = c.space(A.take(f64b), F64);
+    c.aux64 = c.space(A.take(f64b), F64);
     for (int p = 0; p < 3; ++p) c.odd_tmp[p] = A.take(odd);
-    InnerVecs V;
-    V.x = c.space(A.take(fxb), c.px);
-    V.r = c.space(A.take(finb), c.pin);
-    V.p = c.space(A.take(finb), c.pin);
-    V.v = c.space(A.take(finb), c.pin);
-    V.sv = c.space(A.take(finb), c.pin);
-    V.t = c.space(A.take(finb), c.pin);
-    V.rhat = c.space(A.take(finb), c.pin);
-    V.w = c.space(A.take(finb), c.pin);
-    const FieldView rin = c.space(A.take(finb), c.pin);
+    c.ix = c.space(A.take(fxb), c.px);
+    c.ir = c.space(A.take(finb), c.pin);
+    c.ip = c.space(A.take(finb), c.pin);
+    c.iv = c.space(A.take(finb), c.pin);
+    c.is = c.space(A.take(finb), c.pin);
+    c.it = c.space(A.take(finb), c.pin);
+    c.irhat = c.space(A.take(finb), c.pin);
+    c.iw = c.space(A.take(finb), c.pin);
+    c.irin = c.space(A.take(finb), c.pin);
 
     op->solver_sc.ensure(sizeof(double) * NSC * nsys);
     c.sc = reinterpret_cast<double *>(op->solver_sc.ptr);
     if (op->host_sc_n < (size_t)NSC * nsys) {
         if (op->host_sc) LQ_HIP(hipHostFree(op->host_sc));
         op->host_sc = nullptr;
+        op->host_sc_n = 0;
         LQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&op->host_sc), sizeof(double) * NSC * nsys, 0));
         op->host_sc_n = (size_t)NSC * nsys;
     }
@@ -218,52 +194,40 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
     c.partial = reinterpret_cast<double *>(op->partial.ptr);
     std::memset(c.hsc, 0, sizeof(double) * NSC * nsys);
     c.push();
+}
 
-    const auto t0 = std::chrono::steady_clock::now();
+std::vector<double> norms2(SolveCtx &c, const FieldView &v, int sps)
+{
+    LQ_HIP(launch_reduce(v, v, RED_NORM, c.partial, c.s));
+    LQ_HIP(launch_finish(c.partial, c.nsys, sps, blas_blocks(v.n), 1, FIN_NORM, c.sc, 0, c.s));
+    c.pull();
+    std::vector<double> out(c.nsys);
+    for (int i = 0; i < c.nsys; ++i) out[i] = c.hsc[i * NSC + SC_NORM2];
+    return out;
+}
 
-    // |b|^2 of the full lattice, per system
-    const FieldView bfull{const_cast<char *>(b64), F64, (long)g.vh, fb(F64, g), 2 * nsys};
-    {
-        LQ_HIP(launch_reduce(bfull, bfull, RED_NORM, c.partial, s));
-        LQ_HIP(launch_finish(c.partial, nsys, 2, blas_blocks(g.vh), 1, FIN_NORM, c.sc, 0, s));
-        c.pull();
-    }
-    std::vector<double> bn2(nsys);
-    for (int i = 0; i < nsys; ++i) bn2[i] = c.hsc[i * NSC + SC_NORM2];
-    for (int i = 0; i < nsys; ++i)
-        if (!std::isfinite(bn2[i])) throw Failure{LQ_ERR_NONFINITE, "right-hand side is not finite"};
-
-    // right-hand side of the solved system and the initial guess
-    const FieldView bhv = c.space(bh, F64);
-    const FieldView xv = c.space(xs, F64);
-    const FieldView r64v = c.space(r64, F64);
-    const FieldView y64v = c.space(y64, F64);
-    if (c.eo) {
-        const FieldView be = full_parity_view(const_cast<char *>(b64), F64, g, nsys, 0);
-        const FieldView bo = full_parity_view(const_cast<char *>(b64), F64, g, nsys, 1);
-        const FieldView t = FieldView{c.odd_tmp[F64], F64, (long)g.vh, fb(F64, g), nsys};
-        clover_apply(op, F64, 1, true, t, bo, s);
-        hop(op, F64, bhv, t, 0, false, 0, false, &be, op->prm.kappa, 0, nullptr, s);
-        c.count_hops(F64, 1);
-        if (use_x0) LQ_HIP(launch_copy(xv, full_parity_view(x64, F64, g, nsys, 0), c.sc, 1, false, s));
-        else LQ_HIP(launch_zero(xv, s));
-    } else {
-        LQ_HIP(launch_copy(bhv, bfull, c.sc, 2, false, s));
-        if (use_x0) LQ_HIP(launch_copy(xv, FieldView{x64, F64, (long)g.vh, fb(F64, g), 2 * nsys}, c.sc, 2, false, s));
-        else LQ_HIP(launch_zero(xv, s));
-    }
-
-    std::vector<int> iters(nsys, 0), outer(nsys, 0), restarts(nsys, 0);
+OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool normal, const FieldView &rhs,
+                             const std::vector<double> &target2)
+{
+    const int nsys = c.nsys;
+    OuterStats os;
+    os.iters.assign(nsys, 0);
+    os.outer.assign(nsys, 0);
+    os.restarts.assign(nsys, 0);
     int total_inner = 0;
-    bool ok = false;
     for (int step = 0; step <= sp.max_outer; ++step) {
-        // r = b_hat - M x, |r|^2
+        // r = rhs - A x, |r|^2 (FIN_NORM also flags systems below target)
         c.pull();
-        for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = sp.tol * sp.tol * bn2[i];
+        for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
         c.push();
-        c.apply(y64v, xv, false);
-        LQ_HIP(launch_xmy_norm(r64v, bhv, y64v, c.partial, s));
-        c.finish(1, FIN_NORM, g.vh);
+        if (normal) {
+            c.apply(c.t64, c.x64, false);
+            c.apply(c.y64, c.t64, true);
+        } else {
+            c.apply(c.y64, c.x64, false);
+        }
+        LQ_HIP(launch_xmy_norm(c.r64, rhs, c.y64, c.partial, c.s));
+        c.finish(1, FIN_NORM, c.r64.n);
         c.pull();
         bool all = true;
         for (int i = 0; i < nsys; ++i) {
@@ -271,57 +235,96 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
             if (!std::isfinite(n2)) throw Failure{LQ_ERR_NONFINITE, "residual is not finite"};
             if (c.hsc[i * NSC + SC_ODONE] == 0.0) all = false;
         }
-        if (all) {
-            ok = true;
-            break;
-        }
-        if (step == sp.max_outer || total_inner >= sp.max_iter) break;
+        if (all || step == sp.max_outer || total_inner >= sp.max_iter) break;
         // relative target of this inner solve, per system
         for (int i = 0; i < nsys; ++i) {
             double *h = c.hsc + i * NSC;
             const double rn = std::sqrt(h[SC_NORM2]);
-            double rel = 0.5 * sp.tol * std::sqrt(bn2[i]) / (rn > 0 ? rn : 1.0);
+            double rel = 0.5 * std::sqrt(target2[i]) / (rn > 0 ? rn : 1.0);
             if (c.pin != F64) rel = std::max(rel, sp.inner_tol);
             rel = std::min(rel, 0.5);
-            h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT converts it
-            if (h[SC_ODONE] == 0.0) outer[i]++;
+            h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT_* makes it absolute
+            if (h[SC_ODONE] == 0.0) os.outer[i]++;
         }
-        // SC_TARGET2 is relative to the initial inner residual (FIN_INIT
-        // scales it): |rin| for BiCGStab, |M^dag rin| for CGNE.
         c.push();
-        LQ_HIP(launch_copy(rin, r64v, c.sc, c.sps, true, s));
-        const int budget = sp.max_iter - total_inner;
-        int it = 0;
-        if (sp.solver == LQ_CGNE) {
-            it = inner_cgne(c, V, rin, budget, std::max(1, sp.check_every));
-        } else {
-            it = inner_bicgstab(c, V, rin, budget, std::max(1, sp.check_every));
-        }
+        LQ_HIP(launch_copy(c.irin, c.r64, c.sc, c.sps, true, c.s));
+        // a stagnating inner solve hands back to the outer loop after
+        // kInnerCap iterations (a restart from the current FP64 iterate)
+        constexpr int kInnerCap = 1000;
+        const int budget = std::min(sp.max_iter - total_inner, kInnerCap);
+        const int every = std::max(1, sp.check_every);
+        int it;
+        if (normal) it = inner_cg(c, true, budget, every);
+        else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, every);
+        else it = inner_bicgstab(c, budget, every);
         total_inner += it;
         for (int i = 0; i < nsys; ++i) {
             const double *h = c.hsc + i * NSC;
             if (h[SC_ODONE] == 0.0) {
-                iters[i] += (int)h[SC_ITER];
-                if (h[SC_BREAK] != 0.0) restarts[i]++;
+                os.iters[i] += (int)h[SC_ITER];
+                if (h[SC_BREAK] != 0.0) os.restarts[i]++;
             }
         }
         // x += |r| e
-        LQ_HIP(launch_accum(xv, V.x, c.sc, c.sps, true, s));
+        LQ_HIP(launch_accum(c.x64, c.ix, c.sc, c.sps, true, c.s));
     }
+    return os;
+}
+
+// Solve D x = b for nsys systems; b64, x64: full packed FP64 fields
+// ([rhs][parity]).  stats[i] filled for each system.
+lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x64, const char *b64, bool use_x0,
+                       lq_solve_stats *stats, hipStream_t s)
+{
+    const Geom &g = op->g;
+    SolveCtx c;
+    make_ctx(c, op, nsys, sp.even_odd != 0, sp.inner, s);
+    const auto t0 = std::chrono::steady_clock::now();
+
+    const FieldView bfull{const_cast<char *>(b64), F64, (long)g.vh, fb(F64, g), 2 * nsys};
+    const FieldView xfull{x64, F64, (long)g.vh, fb(F64, g), 2 * nsys};
+    const std::vector<double> bn2 = norms2(c, bfull, 2);
+    for (int i = 0; i < nsys; ++i)
+        if (!std::isfinite(bn2[i])) throw Failure{LQ_ERR_NONFINITE, "right-hand side is not finite"};
+
+    // right-hand side of the solved system and the initial guess
+    FieldView rhs = c.aux64;
+    if (c.eo) {
+        const FieldView be = full_parity_view(const_cast<char *>(b64), F64, g, nsys, 0);
+        const FieldView bo = full_parity_view(const_cast<char *>(b64), F64, g, nsys, 1);
+        const FieldView t = FieldView{c.odd_tmp[F64], F64, (long)g.vh, fb(F64, g), nsys};
+        clover_apply(op, F64, 1, true, t, bo, s);
+        hop(op, F64, rhs, t, 0, false, 0, false, &be, op->prm.kappa, 0, nullptr, s);
+        c.count_hops(F64, 1);
+        if (use_x0) LQ_HIP(launch_copy(c.x64, full_parity_view(x64, F64, g, nsys, 0), c.sc, 1, false, s));
+        else LQ_HIP(launch_zero(c.x64, s));
+    } else {
+        rhs = bfull;
+        if (use_x0) LQ_HIP(launch_copy(c.x64, xfull, c.sc, 2, false, s));
+        else LQ_HIP(launch_zero(c.x64, s));
+    }
+    std::vector<double> target2(nsys);
+    for (int i = 0; i < nsys; ++i) target2[i] = sp.tol * sp.tol * bn2[i];
+    const OuterStats os = defect_correction(c, sp, false, rhs, target2);
 
     // full solution and true residual
     if (c.eo) {
-        LQ_HIP(launch_copy(full_parity_view(x64, F64, g, nsys, 0), xv, c.sc, 1, false, s));
+        LQ_HIP(launch_copy(full_parity_view(x64, F64, g, nsys, 0), c.x64, c.sc, 1, false, s));
         const FieldView bo = full_parity_view(const_cast<char *>(b64), F64, g, nsys, 1);
-        hop(op, F64, full_parity_view(x64, F64, g, nsys, 1), xv, 1, false, 2, true, &bo, op->prm.kappa, 0, nullptr, s);
+        hop(op, F64, full_parity_view(x64, F64, g, nsys, 1), c.x64, 1, false, 2, true, &bo, op->prm.kappa, 0, nullptr,
+            s);
         c.count_hops(F64, 1);
     } else {
-        LQ_HIP(launch_copy(FieldView{x64, F64, (long)g.vh, fb(F64, g), 2 * nsys}, xv, c.sc, 2, false, s));
+        LQ_HIP(launch_copy(xfull, c.x64, c.sc, 2, false, s));
     }
-    dirac_full(op, F64, full_y, x64, nsys, false, s);
+    // the full-lattice residual uses the (now free) FP64 solve vectors as
+    // scratch: two of them hold one full field when eo
+    op->tmp[0].ensure(2 * (size_t)fb(F64, g) * nsys);
+    op->tmp[1].ensure(2 * (size_t)fb(F64, g) * nsys);
+    dirac_full(op, F64, op->tmp[0].ptr, x64, nsys, false, s);
     c.count_hops(F64, 2);
-    const FieldView fr{full_r, F64, (long)g.vh, fb(F64, g), 2 * nsys};
-    const FieldView fy{full_y, F64, (long)g.vh, fb(F64, g), 2 * nsys};
+    const FieldView fy{op->tmp[0].ptr, F64, (long)g.vh, fb(F64, g), 2 * nsys};
+    const FieldView fr{op->tmp[1].ptr, F64, (long)g.vh, fb(F64, g), 2 * nsys};
     LQ_HIP(launch_xmy_norm(fr, bfull, fy, c.partial, s));
     LQ_HIP(launch_finish(c.partial, nsys, 2, blas_blocks(g.vh), 1, FIN_NORM, c.sc, 0, s));
     c.pull();
@@ -335,9 +338,9 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
         all_conv = all_conv && conv;
         if (stats) {
             lq_solve_stats &st = stats[i];
-            st.nconv = iters[i];
-            st.nouter = outer[i];
-            st.restarts = restarts[i];
+            st.nconv = os.iters[i];
+            st.nouter = os.outer[i];
+            st.restarts = os.restarts[i];
             st.converged = conv ? 1 : 0;
             st.diff = diff;
             st.t_solve_ms = ms;
@@ -345,8 +348,28 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
             st.n_hop = (int)c.n_hop;
         }
     }
-    (void)ok;
     return all_conv ? LQ_OK : LQ_NOT_CONVERGED;
+}
+
+bool valid_solver_params(const lq_solver_params *sp, std::string &why)
+{
+    if (sp->max_iter < 0 || sp->max_outer < 0 || !(sp->tol > 0) || !(sp->inner_tol > 0) || !(sp->inner_tol < 1)) {
+        why = "tol, inner_tol, max_iter or max_outer out of range";
+        return false;
+    }
+    if (sp->solver != LQ_CGNE && sp->solver != LQ_BICGSTAB) {
+        why = "unknown solver";
+        return false;
+    }
+    if (sp->inner < LQ_F64 || sp->inner > LQ_F16) {
+        why = "unknown inner precision";
+        return false;
+    }
+    if (!sp->even_odd && sp->solver != LQ_CGNE) {
+        why = "the full-lattice solve is CGNE only";
+        return false;
+    }
+    return true;
 }
 
 }  // namespace lq
@@ -364,13 +387,9 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
         set_error("lq_solve: mode must be LQ_D, LQ_DDAG or LQ_DDAGD");
         return LQ_ERR_ARG;
     }
-    if (nrhs < 1 || sp->max_iter < 0 || sp->max_outer < 0 || !(sp->tol > 0) || !(sp->inner_tol > 0) ||
-        (sp->solver != LQ_CGNE && sp->solver != LQ_BICGSTAB) || (sp->inner < LQ_F64 || sp->inner > LQ_F16)) {
-        set_error("lq_solve: invalid solver parameters");
-        return LQ_ERR_ARG;
-    }
-    if (!sp->even_odd && sp->solver != LQ_CGNE) {
-        set_error("lq_solve: the full-lattice solve is CGNE only");
+    std::string why;
+    if (nrhs < 1 || !valid_solver_params(sp, why)) {
+        set_error("lq_solve: invalid solver parameters: " + (nrhs < 1 ? std::string("nrhs < 1") : why));
         return LQ_ERR_ARG;
     }
     if (!op->gauge_set) {
@@ -380,7 +399,12 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
     try {
         set_error("");
         LQ_HIP(hipSetDevice(op->device));
-        hipStream_t s = static_cast<hipStream_t>(stream);
+        // the solve runs on the operator's own stream (capturable), ordered
+        // after the caller's stream and synchronized before returning
+        hipStream_t us = static_cast<hipStream_t>(stream);
+        LQ_HIP(hipEventRecord(op->ev_in, us));
+        LQ_HIP(hipStreamWaitEvent(op->stream, op->ev_in, 0));
+        hipStream_t s = op->stream;
         const Geom &g = op->g;
         const size_t full = 2 * (size_t)fb(F64, g) * nrhs;
         op->tmp[4].ensure(full);
@@ -403,42 +427,41 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
             if (use_x0) LQ_HIP(launch_gamma5(xfull, s));
             st = solve_packed(op, *sp, nrhs, xp, bp, use_x0, stats, s);
             LQ_HIP(launch_gamma5(xfull, s));
-            LQ_HIP(launch_gamma5(bfull, s));
         } else {
-            // D^dag D x = b: y = (D^dag)^-1 b, then x = D^-1 y
+            // D^dag D x = b: y = (D^dag)^-1 b = gamma_5 D^-1 gamma_5 b, then x = D^-1 y
             std::vector<lq_solve_stats> st1(nrhs);
             LQ_HIP(launch_gamma5(bfull, s));
             st = solve_packed(op, *sp, nrhs, xp, bp, false, st1.data(), s);
             if (st < 0) return st;
             LQ_HIP(launch_gamma5(xfull, s));  // y
             LQ_HIP(launch_gamma5(bfull, s));  // b restored
-            op->tmp[0].ensure(full);
-            char *yp = op->tmp[0].ptr;
-            LQ_HIP(hipMemcpyAsync(yp, xp, full, hipMemcpyDeviceToDevice, s));
+            LQ_HIP(hipMemcpyAsync(bp, xp, full, hipMemcpyDeviceToDevice, s));  // b slot := y
             lq_solver_params sp2 = *sp;
             sp2.tol = sp->tol * 0.5;
-            st = solve_packed(op, sp2, nrhs, xp, yp, false, stats, s);
-            // diff of the normal system |b - D^dag D x| / |b|
+            st = solve_packed(op, sp2, nrhs, xp, bp, false, stats, s);
+            if (st < 0) return st;
+            // diff of the normal system |b - D^dag D x| / |b|, b re-packed
+            for (int p = 0; p < 2; ++p) LQ_HIP(launch_pack_spinor(g, p, 0, bsrc, full_parity_view(bp, F64, g, nrhs, p), s));
+            op->tmp[0].ensure(full);
             op->tmp[1].ensure(full);
-            dirac_full(op, F64, yp, xp, nrhs, false, s);
-            dirac_full(op, F64, op->tmp[1].ptr, yp, nrhs, true, s);
+            dirac_full(op, F64, op->tmp[0].ptr, xp, nrhs, false, s);
+            dirac_full(op, F64, op->tmp[1].ptr, op->tmp[0].ptr, nrhs, true, s);
+            SolveCtx c;
+            c.op = op;
+            c.s = s;
+            c.nsys = nrhs;
+            c.sc = reinterpret_cast<double *>(op->solver_sc.ptr);
+            c.hsc = op->host_sc;
+            c.partial = reinterpret_cast<double *>(op->partial.ptr);
+            const std::vector<double> bn2 = norms2(c, bfull, 2);
             const FieldView fy{op->tmp[1].ptr, F64, (long)g.vh, fb(F64, g), 2 * nrhs};
-            const FieldView fr{yp, F64, (long)g.vh, fb(F64, g), 2 * nrhs};
-            double *partial = reinterpret_cast<double *>(op->partial.ptr);
-            double *sc = reinterpret_cast<double *>(op->solver_sc.ptr);
-            std::vector<double> bn2(nrhs), rn2(nrhs);
-            LQ_HIP(launch_reduce(bfull, bfull, RED_NORM, partial, s));
-            LQ_HIP(launch_finish(partial, nrhs, 2, blas_blocks(g.vh), 1, FIN_NORM, sc, 0, s));
-            LQ_HIP(hipMemcpyAsync(op->host_sc, sc, sizeof(double) * NSC * nrhs, hipMemcpyDeviceToHost, s));
-            LQ_HIP(hipStreamSynchronize(s));
-            for (int i = 0; i < nrhs; ++i) bn2[i] = op->host_sc[i * NSC + SC_NORM2];
-            LQ_HIP(launch_xmy_norm(fr, bfull, fy, partial, s));
-            LQ_HIP(launch_finish(partial, nrhs, 2, blas_blocks(g.vh), 1, FIN_NORM, sc, 0, s));
-            LQ_HIP(hipMemcpyAsync(op->host_sc, sc, sizeof(double) * NSC * nrhs, hipMemcpyDeviceToHost, s));
-            LQ_HIP(hipStreamSynchronize(s));
+            const FieldView fr{op->tmp[0].ptr, F64, (long)g.vh, fb(F64, g), 2 * nrhs};
+            LQ_HIP(launch_xmy_norm(fr, bfull, fy, c.partial, s));
+            LQ_HIP(launch_finish(c.partial, nrhs, 2, blas_blocks(g.vh), 1, FIN_NORM, c.sc, 0, s));
+            c.pull();
             bool all = true;
             for (int i = 0; i < nrhs; ++i) {
-                const double d = bn2[i] > 0 ? std::sqrt(op->host_sc[i * NSC + SC_NORM2] / bn2[i]) : 0.0;
+                const double d = bn2[i] > 0 ? std::sqrt(c.hsc[i * NSC + SC_NORM2] / bn2[i]) : 0.0;
                 if (stats) {
                     stats[i].diff = d;
                     stats[i].converged = d <= sp->tol;
@@ -451,11 +474,13 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
                 }
                 all = all && d <= sp->tol;
             }
-            st = st < 0 ? st : (all ? LQ_OK : LQ_NOT_CONVERGED);
+            st = all ? LQ_OK : LQ_NOT_CONVERGED;
         }
         if (st < 0) return st;
         for (int p = 0; p < 2; ++p)
             LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(xp, F64, g, nrhs, p), xdst, s));
+        LQ_HIP(hipEventRecord(op->ev_out, s));
+        LQ_HIP(hipStreamWaitEvent(us, op->ev_out, 0));
         LQ_HIP(hipStreamSynchronize(s));
         return st;
     } catch (const Failure &f) {

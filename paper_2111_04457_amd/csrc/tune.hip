@@ -1,0 +1,229 @@
+// tune.hip -- autotuner of the hopping kernels.
+//
+// For each storage precision the Schur operator M (two fused hopping
+// kernels, the work of every solver iteration) is timed with HIP events for
+// every workgroup size {64, 128, 256} and both workgroup orders (plain,
+// XCD-aware); the output of every candidate must be bitwise equal to the
+// first candidate's (each site's sum is formed in the same order whatever
+// the launch shape).  The fastest candidate is kept on the operator.  Results
+// are cached in a JSON file keyed by kernel, precision, lattice, link format,
+// right-hand sides and architecture; a cached entry is applied without
+// timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "blas.h"
+#include "runtime.h"
+
+namespace lq {
+
+namespace {
+
+std::string tune_key(const lq_op *op, int prec, int nrhs)
+{
+    static const char *pn[3] = {"f64", "f32", "f16"};
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "schur_%s_%dx%dx%dx%d_nl%d_%s_nrhs%d_gfx950", pn[prec], op->g.L[0], op->g.L[1],
+                  op->g.L[2], op->g.L[3], op->nl(prec), op->has_clover ? "clover" : "wilson", nrhs);
+    return buf;
+}
+
+struct Entry {
+    std::string key;
+    int block = 256;
+    int xcd = 1;
+    double us = 0;
+};
+
+// The cache is a flat JSON object {"key": {"block": b, "xcd_remap": x, "us": t}, ...}
+// written by this file; the reader only understands that form.
+std::vector<Entry> read_cache(const std::string &path)
+{
+    std::vector<Entry> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t k0 = t.find('"', pos);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = t.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const std::string key = t.substr(k0 + 1, k1 - k0 - 1);
+        const size_t ob = t.find('{', k1);
+        const size_t cb = t.find('}', k1);
+        if (ob == std::string::npos || cb == std::string::npos || ob > cb) {
+            pos = k1 + 1;
+            continue;
+        }
+        const std::string body = t.substr(ob, cb - ob);
+        Entry e;
+        e.key = key;
+        auto num = [&](const char *name, double dflt) {
+            const size_t p = body.find(std::string("\"") + name + "\"");
+            if (p == std::string::npos) return dflt;
+            const size_t c = body.find(':', p);
+            return c == std::string::npos ? dflt : std::atof(body.c_str() + c + 1);
+        };
+        e.block = (int)num("block", 256);
+        e.xcd = (int)num("xcd_remap", 1);
+        e.us = num("us", 0);
+        if (e.block == 64 || e.block == 128 || e.block == 256) out.push_back(e);
+        pos = cb + 1;
+    }
+    return out;
+}
+
+void write_cache(const std::string &path, const std::vector<Entry> &entries)
+{
+    const std::string tmp = path + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i) {
+        const Entry &e = entries[i];
+        f << "  \"" << e.key << "\": {\"block\": " << e.block << ", \"xcd_remap\": " << e.xcd << ", \"us\": " << e.us
+          << "}" << (i + 1 < entries.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+}  // namespace
+
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, size_t report_len,
+                             void *stream)
+{
+    if (!op) {
+        set_error("lq_tune: null operator");
+        return LQ_ERR_ARG;
+    }
+    if (nrhs < 1) {
+        set_error("lq_tune: nrhs must be >= 1");
+        return LQ_ERR_ARG;
+    }
+    if (!op->gauge_set) {
+        set_error("lq_tune: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    try {
+        set_error("");
+        LQ_HIP(hipSetDevice(op->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::string path = cache_path ? cache_path : "";
+        if (path.empty()) {
+            const char *env = std::getenv("LQ_TUNE_CACHE");
+            if (env) path = env;
+        }
+        std::vector<Entry> cache = path.empty() ? std::vector<Entry>{} : read_cache(path);
+        const Geom &g = op->g;
+        std::ostringstream rep;
+        rep << "{";
+        bool changed = false;
+        hipEvent_t e0, e1;
+        LQ_HIP(hipEventCreate(&e0));
+        LQ_HIP(hipEventCreate(&e1));
+        for (int prec = F64; prec <= F16; ++prec) {
+            const std::string key = tune_key(op, prec, nrhs);
+            Entry best;
+            best.key = key;
+            bool found = false;
+            for (const Entry &e : cache)
+                if (e.key == key) {
+                    best = e;
+                    found = true;
+                }
+            if (!found) {
+                const size_t b = (size_t)fb(prec, g) * nrhs;
+                op->tmp[2].ensure(b);
+                op->tmp[3].ensure(b);
+                // input: a deterministic smooth test field, the same for every rhs
+                const FieldView in = parity_view(op->tmp[2].ptr, prec, g, nrhs);
+                const FieldView out = parity_view(op->tmp[3].ptr, prec, g, nrhs);
+                std::vector<double> host(24 * (size_t)g.vh);
+                for (size_t i = 0; i < host.size(); ++i) host[i] = std::sin(0.37 * (double)(i % 1021) + 0.11 * (double)(i / 1021));
+                op->tmp[5].ensure(host.size() * sizeof(double));
+                LQ_HIP(hipMemcpyAsync(op->tmp[5].ptr, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, s));
+                for (int r = 0; r < nrhs; ++r)
+                    LQ_HIP(launch_pack_spinor(g, 0, 1, reinterpret_cast<const double *>(op->tmp[5].ptr),
+                                              FieldView{in.base + r * in.rs, prec, in.n, in.rs, 1}, s));
+                const int save_block = op->hop_block[prec], save_remap = op->xcd_remap[prec];
+                double best_us = 1e30;
+                bool first = true;
+                std::vector<char> ref_host(b), cur_host(b);
+                for (int block : {256, 128, 64}) {
+                    for (int remap : {1, 0}) {
+                        op->hop_block[prec] = block;
+                        op->xcd_remap[prec] = remap;
+                        for (int w = 0; w < 2; ++w) apply_packed(op, LQ_SCHUR, prec, out.base, in.base, nrhs, s);
+                        const int reps = g.vh >= (1 << 18) ? 10 : 40;
+                        std::vector<float> t(reps);
+                        for (int k = 0; k < reps; ++k) {
+                            LQ_HIP(hipEventRecord(e0, s));
+                            apply_packed(op, LQ_SCHUR, prec, out.base, in.base, nrhs, s);
+                            LQ_HIP(hipEventRecord(e1, s));
+                            LQ_HIP(hipEventSynchronize(e1));
+                            LQ_HIP(hipEventElapsedTime(&t[k], e0, e1));
+                        }
+                        std::sort(t.begin(), t.end());
+                        const double us = 1e3 * t[reps / 2];
+                        LQ_HIP(hipMemcpyAsync(cur_host.data(), out.base, b, hipMemcpyDeviceToHost, s));
+                        LQ_HIP(hipStreamSynchronize(s));
+                        if (first) {
+                            ref_host = cur_host;
+                            first = false;
+                        } else if (cur_host != ref_host) {
+                            op->hop_block[prec] = save_block;
+                            op->xcd_remap[prec] = save_remap;
+                            throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results"};
+                        }
+                        if (us < best_us) {
+                            best_us = us;
+                            best.block = block;
+                            best.xcd = remap;
+                        }
+                    }
+                }
+                best.us = best_us;
+                cache.push_back(best);
+                changed = true;
+            }
+            op->hop_block[prec] = best.block;
+            op->xcd_remap[prec] = best.xcd;
+            rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
+                << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";
+        }
+        LQ_HIP(hipEventDestroy(e0));
+        LQ_HIP(hipEventDestroy(e1));
+        rep << "}";
+        op->clear_graphs();
+        if (changed && !path.empty()) write_cache(path, cache);
+        if (report && report_len) {
+            const std::string r = rep.str();
+            const size_t n = std::min(report_len - 1, r.size());
+            std::memcpy(report, r.data(), n);
+            report[n] = 0;
+        }
+        return LQ_OK;
+    } catch (const Failure &f) {
+        set_error(f.msg);
+        return f.code;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return LQ_ERR_STATE;
+    }
+}

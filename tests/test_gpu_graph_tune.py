@@ -1,0 +1,80 @@
+"""hipGraph capture of the solvers' inner iterations and the autotuner.
+
+A captured chunk of inner iterations is replayed many times per solve, with
+the host's eager work (scalar read-back, outer FP64 steps) between replays;
+the solution must equal, bit for bit, the solution of the same solve run
+eagerly.  The autotuner must give bitwise-identical operator output for the
+shape it picks, write and re-read its JSON cache, and leave the solver's
+results unchanged.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from lattice_inputs import ANTIPERIODIC_T, gauge_exp, gaussian_spinor, gaussian_parity_spinor
+from tests.gpu_common import announce, have_gpu, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 4, 8, 8)
+KAPPA, CSW = 0.13, 1.2
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    import paper_2111_04457_amd as lq
+    return lq
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    return gauge_exp(DIMS, 0.4, 1601), gaussian_spinor(DIMS, 2601, 2)
+
+
+@pytest.mark.parametrize("solver,inner", [("bicgstab", "f32"), ("bicgstab", "f16"), ("cgne", "f64")])
+def test_graph_replays_equal_eager(lq, inputs, solver, inner):
+    U, b = inputs
+    announce("graph vs eager: %s %s" % (solver, inner))
+    prm = lq.SolverParams(solver=solver, tol=1e-10, inner=inner, inner_tol=1e-2 if inner == "f16" else 1e-5,
+                          check_every=4)
+    res = {}
+    for graphs in (0, 1):
+        op = lq.Operator(DIMS, KAPPA, CSW, ANTIPERIODIC_T)
+        op.set_gauge(to_dev(U))
+        op.set_option("graphs", graphs)
+        x1, st1 = op.solve(to_dev(b), "D", prm)
+        x2, st2 = op.solve(to_dev(b), "D", prm)  # second solve replays cached graphs
+        res[graphs] = (to_host(x1), to_host(x2), st1, st2)
+        op.close()
+    e, g = res[0], res[1]
+    assert np.array_equal(e[0], g[0]) and np.array_equal(e[1], g[1]) and np.array_equal(g[0], g[1])
+    assert [s.nconv for s in e[2]] == [s.nconv for s in g[2]]
+    assert all(s.converged for s in g[2])
+
+
+def test_tuner_bitwise_cache_and_solve(lq, inputs, tmp_path):
+    U, b = inputs
+    ref = oracle.Operator(DIMS, U, KAPPA, CSW, ANTIPERIODIC_T)
+    op = lq.Operator(DIMS, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    xe = gaussian_parity_spinor(DIMS, 2602)
+    before = {p: to_host(op.apply("schur", to_dev(xe), p)) for p in ("f64", "f32", "f16")}
+    cache = str(tmp_path / "tune.json")
+    rep = op.tune(1, cache)
+    announce("tune report %s" % json.dumps(rep))
+    assert len(rep) == 3 and all(not v["cached"] for v in rep.values())
+    for p in ("f64", "f32", "f16"):
+        assert op.get_option("hop_block_" + p) in (64, 128, 256)
+        assert np.array_equal(to_host(op.apply("schur", to_dev(xe), p)), before[p])
+    data = json.load(open(cache))
+    assert set(data) == set(rep)
+    rep2 = op.tune(1, cache)
+    assert all(v["cached"] for v in rep2.values())
+    x, st = op.solve(to_dev(b[0]), "D", lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2))
+    assert st[0].converged and oracle.true_residual(ref, to_host(x), b[0]) <= 1.01e-10
+    op.close()
