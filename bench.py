@@ -70,6 +70,7 @@ def main(argv=None):
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32-inner reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -102,6 +103,11 @@ def main(argv=None):
     op.set_gauge(U_d)
     del U_d
     torch.cuda.synchronize()
+    tune = None
+    if not args.no_tune:
+        t_tune = time.time()
+        tune = op.tune(1)
+        print("bench: tuned in %.1f s: %s" % (time.time() - t_tune, json.dumps(tune)), file=sys.stderr, flush=True)
 
     inner_tol = {"f16": 1e-2, "f32": 1e-5, "f64": 1e-5}[args.inner]
     prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10)
@@ -175,7 +181,8 @@ def main(argv=None):
         kern["dslash_%s_GBs" % prec] = gbs
         kern["dslash_%s_TFLOPs" % prec] = fps * (V // 2) / (ms * 1e-3) / 1e12
         if prec == args.inner or (prec == "f16" and roof is None):
-            tag = "hop_kernel<%s,%d,dag=0,clov=0,xpay=0,red=0,256>" % (prec, 18 if prec == "f64" else args.recon)
+            blk = op.get_option("hop_block_" + prec)
+            tag = "hop_kernel<%s,%d,dag=0,clov=0,xpay=0,red=0,%d>" % (prec, 18 if prec == "f64" else args.recon, blk)
             traffic = _traffic_from_profile(tag) if prec == "f16" else None
             roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                     "traffic": traffic, "kernel": tag, "bytes_per_launch": bps * (V // 2),
@@ -232,6 +239,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "time_to_solution": tts,
         "kernels": kern,
+        "tuning": tune,
     }
     print(json.dumps(line), flush=True)
     return 0

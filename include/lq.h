@@ -192,7 +192,11 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
 /* Other execution options (none changes a result bit):
  *   "xcd_remap" 0|1  XCD-aware order of the hopping kernel's workgroups (default 1),
  *                    all precisions; "xcd_remap_f64" / "_f32" / "_f16" per precision;
- *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1).
+ *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
+ *   "rhs_per_thread" 1|2|4  right-hand sides one thread of the hopping kernel
+ *                    handles when several are applied together (each loaded
+ *                    link is used for all of them; default 2); per precision
+ *                    "rhs_per_thread_f64" / "_f32" / "_f16".
  * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16".
  * LQ_ERR_ARG for an unknown name or value. */
 lq_status lq_op_set_option(lq_op *op, const char *name, int value);

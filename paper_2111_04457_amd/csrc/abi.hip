@@ -82,7 +82,7 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
             return arg_error("lq_op_create: every dimension must be even and >= 2");
         vol *= p->dims[i];
     }
-    if (vol > (1L << 30)) return arg_error("lq_op_create: volume above 2^30 sites");
+    if (vol > (1L << 28)) return arg_error("lq_op_create: volume above 2^28 sites");
     if (!std::isfinite(p->kappa) || !std::isfinite(p->csw)) return arg_error("lq_op_create: kappa and csw must be finite");
     for (int i = 0; i < 4; ++i) {
         const double m = std::hypot(p->bc[i][0], p->bc[i][1]);
@@ -337,6 +337,11 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
     else if (n == "xcd_remap_f64" && (value == 0 || value == 1)) op->xcd_remap[F64] = value;
     else if (n == "xcd_remap_f32" && (value == 0 || value == 1)) op->xcd_remap[F32] = value;
     else if (n == "xcd_remap_f16" && (value == 0 || value == 1)) op->xcd_remap[F16] = value;
+    else if (n == "rhs_per_thread" && (value == 1 || value == 2 || value == 4))
+        op->rhs_per_thread[0] = op->rhs_per_thread[1] = op->rhs_per_thread[2] = value;
+    else if (n == "rhs_per_thread_f64" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F64] = value;
+    else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F32] = value;
+    else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F16] = value;
     else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
     else return arg_error("lq_op_set_option: unknown option or value: " + n);
     op->clear_graphs();
@@ -350,6 +355,9 @@ lq_status lq_op_get_option(const lq_op *op, const char *name, int *value)
     if (n == "xcd_remap" || n == "xcd_remap_f16") *value = op->xcd_remap[F16];
     else if (n == "xcd_remap_f64") *value = op->xcd_remap[F64];
     else if (n == "xcd_remap_f32") *value = op->xcd_remap[F32];
+    else if (n == "rhs_per_thread_f64") *value = op->rhs_per_thread[F64];
+    else if (n == "rhs_per_thread_f32") *value = op->rhs_per_thread[F32];
+    else if (n == "rhs_per_thread" || n == "rhs_per_thread_f16") *value = op->rhs_per_thread[F16];
     else if (n == "graphs") *value = op->use_graphs;
     else if (n == "hop_block_f64") *value = op->hop_block[F64];
     else if (n == "hop_block_f32") *value = op->hop_block[F32];

@@ -47,7 +47,10 @@ int blas_blocks(long n);
 
 // partials of <x, y> / |x|^2 over every slice (y unused for RED_NORM);
 // RED_DOT_NORM gives <x, y> and |y|^2.
-hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s);
+// With mask (solver scalars, sps slices per system) frozen systems are
+// skipped (their partials are zero).
+hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s,
+                         const double *mask = nullptr, int sps = 1);
 // finish: sums partials of nsys systems (sps slices each, nblocks per slice,
 // K values) and runs op on the scalars sc[sys * NSC + ...].
 hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,

@@ -21,13 +21,15 @@ __device__ __forceinline__ bool frozen(const double *sc) { return sc[SC_DONE] !=
 // ------------------------------------------------------------ reductions --
 
 template <int P, int MODE>
-__global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, double *partial)
+__global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, double *partial, const double *mask,
+                                                   int sps)
 {
     using R = typename PT<P>::R;
     const long i = (long)blockIdx.x * BT + threadIdx.x;
     const int slice = blockIdx.y;
     double a = 0, b = 0, c = 0;
-    if (i < x.n) {
+    const bool live = !mask || !frozen(mask + (slice / sps) * NSC);
+    if (i < x.n && live) {
         const Spinor<R> xv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
         if constexpr (MODE == RED_NORM) {
 #pragma unroll
@@ -58,13 +60,14 @@ __global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, do
     }
 }
 
-hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s)
+hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s, const double *mask,
+                         int sps)
 {
     const dim3 grid(blas_blocks(x.n), x.nrhs);
-#define LQ_RED(P)                                                                                      \
-    if (mode == RED_NORM) reduce_kernel<P, RED_NORM><<<grid, BT, 0, s>>>(x, y, partial);              \
-    else if (mode == RED_DOT) reduce_kernel<P, RED_DOT><<<grid, BT, 0, s>>>(x, y, partial);           \
-    else reduce_kernel<P, RED_DOT_NORM><<<grid, BT, 0, s>>>(x, y, partial);
+#define LQ_RED(P)                                                                                            \
+    if (mode == RED_NORM) reduce_kernel<P, RED_NORM><<<grid, BT, 0, s>>>(x, y, partial, mask, sps);         \
+    else if (mode == RED_DOT) reduce_kernel<P, RED_DOT><<<grid, BT, 0, s>>>(x, y, partial, mask, sps);      \
+    else reduce_kernel<P, RED_DOT_NORM><<<grid, BT, 0, s>>>(x, y, partial, mask, sps);
     switch (x.prec) {
     case F64: LQ_RED(F64) break;
     case F32: LQ_RED(F32) break;
@@ -291,9 +294,9 @@ __global__ __launch_bounds__(BT) void cg_xr_kernel(FieldView x, FieldView r, Fie
     const int slice = blockIdx.y;
     const double *s = sc + (slice / sps) * NSC;
     double a = 0;
-    if (i < r.n) {
+    if (i < r.n && !frozen(s)) {
         Spinor<R> rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
-        if (!frozen(s)) {
+        {
             const R al = (R)s[SC_ALPHA_RE];
             const Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
             const Spinor<R> qv = load_spinor<P>(q.base + slice * q.rs, i, q.n);
@@ -377,16 +380,14 @@ __global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, F
             store_spinor<PX>(x.base + slice * x.rs, i, x.n, xv);
             store_spinor<P>(r.base + slice * r.rs, i, r.n, rv);
             if constexpr (PT<P>::scaled) rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
-        } else {
-            rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
-        }
-        const Spinor<R> hv = load_spinor<P>(rhat.base + slice * rhat.rs, i, rhat.n);
+            const Spinor<R> hv = load_spinor<P>(rhat.base + slice * rhat.rs, i, rhat.n);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const cx<R> d = cmulc(hv.c[k], rv.c[k]);
-            a += (double)d.re;
-            b += (double)d.im;
-            c += (double)norm2(rv.c[k]);
+            for (int k = 0; k < 12; ++k) {
+                const cx<R> d = cmulc(hv.c[k], rv.c[k]);
+                a += (double)d.re;
+                b += (double)d.im;
+                c += (double)norm2(rv.c[k]);
+            }
         }
     }
     __shared__ double lds[BT / 64];

@@ -40,13 +40,18 @@ struct HopArgs {
     long w_n;
     long w_rs;
     int xcd_remap;       // 1: XCD-aware tile order (result independent of it)
+    // per-rhs freeze mask (solver scalars): a right-hand side r with
+    // mask[r * mask_stride + mask_off0] or [.. + mask_off1] nonzero is skipped
+    const double *mask;
+    int mask_stride, mask_off0, mask_off1;
 };
 
 // Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;
 // dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result;
 // xpay: add y; red: 0 none, 1 |out|^2, 2 <w, out> per right-hand side.
-// block: threads per workgroup (a multiple of 64).
-hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int block,
+// nr: right-hand sides per thread (1, or 2 / 4 without reduction);
+// block: threads per workgroup (64, 128 or 256).
+hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int nr, int block,
                       hipStream_t s);
 
 // Number of workgroups launch_hop uses for a lattice of vh sites.

@@ -1,19 +1,31 @@
-// dslash.hip -- dispatch of the hopping kernels by storage precision.
+// dslash.hip -- dispatch of the hopping kernels by storage precision and sign.
 #include "dslash.h"
 
 namespace lq {
 
-hipError_t launch_hop_f64(const HopArgs &a, int recon, bool dag, int clov, bool xpay, int red, int block, hipStream_t s);
-hipError_t launch_hop_f32(const HopArgs &a, int recon, bool dag, int clov, bool xpay, int red, int block, hipStream_t s);
-hipError_t launch_hop_f16(const HopArgs &a, int recon, bool dag, int clov, bool xpay, int red, int block, hipStream_t s);
+hipError_t launch_hop_f64_n(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
+hipError_t launch_hop_f64_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
+hipError_t launch_hop_f32_n(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
+hipError_t launch_hop_f32_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
+hipError_t launch_hop_f16_n(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
+hipError_t launch_hop_f16_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s);
 
-hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int block,
+hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int nr, int block,
                       hipStream_t s)
 {
     switch (prec) {
-    case F64: return launch_hop_f64(a, recon, dag, clov, xpay, red, block, s);
-    case F32: return launch_hop_f32(a, recon, dag, clov, xpay, red, block, s);
-    case F16: return launch_hop_f16(a, recon, dag, clov, xpay, red, block, s);
+    case F64: return dag ? launch_hop_f64_d(a, recon, clov, xpay, red, nr, block, s)
+                         : launch_hop_f64_n(a, recon, clov, xpay, red, nr, block, s);
+    case F32: return dag ? launch_hop_f32_d(a, recon, clov, xpay, red, nr, block, s)
+                         : launch_hop_f32_n(a, recon, clov, xpay, red, nr, block, s);
+    case F16: return dag ? launch_hop_f16_d(a, recon, clov, xpay, red, nr, block, s)
+                         : launch_hop_f16_n(a, recon, clov, xpay, red, nr, block, s);
     }
     return hipErrorInvalidValue;
 }

@@ -1,0 +1,13 @@
+// dslash_f16_d.hip -- instantiations of the hopping kernels, F16 storage,
+// signs of H^dag.
+#include "dslash_impl.h"
+
+namespace lq {
+
+hipError_t launch_hop_f16_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s)
+{
+    return launch_pd<F16, true>(a, recon, clov, xpay, red, nr, block, s);
+}
+
+}  // namespace lq

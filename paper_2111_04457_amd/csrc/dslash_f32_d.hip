@@ -1,0 +1,13 @@
+// dslash_f32_d.hip -- instantiations of the hopping kernels, F32 storage,
+// signs of H^dag.
+#include "dslash_impl.h"
+
+namespace lq {
+
+hipError_t launch_hop_f32_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s)
+{
+    return launch_pd<F32, true>(a, recon, clov, xpay, red, nr, block, s);
+}
+
+}  // namespace lq

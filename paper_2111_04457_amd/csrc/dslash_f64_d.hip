@@ -1,0 +1,13 @@
+// dslash_f64_d.hip -- instantiations of the hopping kernels, F64 storage,
+// signs of H^dag.
+#include "dslash_impl.h"
+
+namespace lq {
+
+hipError_t launch_hop_f64_d(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block,
+                         hipStream_t s)
+{
+    return launch_pd<F64, true>(a, recon, clov, xpay, red, nr, block, s);
+}
+
+}  // namespace lq

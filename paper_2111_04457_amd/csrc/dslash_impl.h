@@ -1,8 +1,10 @@
 // dslash_impl.h -- hopping term of eq. (1) (Sec. 3) on one parity for gfx950.
-// One thread per output site; the input spinor field, links and clover are
-// read through the plane layout of lq_common.h (16-byte elements, a
-// wavefront reads 1 KiB contiguous per load).  Neighbour spinors are re-used
-// through the L2 and the Infinity Cache; links are read exactly once.
+// One thread per output site and group of NR right-hand sides: each link is
+// loaded once per direction and applied to the NR neighbour spinors, and the
+// clover block once per site.  Fields are read through the plane layout of
+// lq_common.h (16-byte elements, a wavefront reads 1 KiB contiguous per
+// load).  Neighbour spinors are re-used through the L2 and the Infinity
+// Cache; links are read once per NR right-hand sides.
 #pragma once
 
 #include "dslash.h"
@@ -10,168 +12,281 @@
 
 namespace lq {
 
-template <int P, int NL, bool DAG, int MU>
-__device__ __forceinline__ void hop_dir(const HopArgs &a, const char *__restrict__ in, int cb, const int c[4],
-                                        int p_out, cx<typename PT<P>::R> acc[12])
+// The eight neighbour terms are processed as a software pipeline over
+// "halves" k = 0..7 (direction k/2, forward for even k): the loads of half
+// k + PF are issued before half k is computed, so every thread keeps PF
+// neighbours' links and spinors in flight.  The loads land in raw storage
+// registers (binary16 data stays packed until it is used).
+template <int P, int NL, int NR> struct HalfRaw {
+    typename PT<P>::S link[NL];
+    typename PT<P>::S sp[NR][24];
+    float scale[NR];
+    bool wrap;
+};
+
+template <int P, int NL, int NR, int K>
+__device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
+                                       HalfRaw<P, NL, NR> &h)
 {
-    using R = typename PT<P>::R;
-    constexpr int SF = DAG ? +1 : -1;  // forward: (1 - gamma) for H, (1 + gamma) for H^dag
-    constexpr int SB = -SF;
-    const int vh = a.g.vh;
-    {
-        int d[4] = {c[0], c[1], c[2], c[3]};
-        const bool wrap = (d[MU] == a.g.L[MU] - 1);
-        d[MU] = wrap ? 0 : d[MU] + 1;
-        const int nb = cb_index(a.g, d);
-        const Spinor<R> ps = load_spinor<P>(in, nb, a.in_n);
-        cx<R> h[6], u[9], o[6];
-        project<MU, SF>(ps, h);
-        load_link<P, NL>(a.links, vh, p_out, MU, cb, u);
-        if (wrap) {
-            const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], (R)a.g.bc_im[MU]};
-#pragma unroll
-            for (int i = 0; i < 6; ++i) h[i] = ph * h[i];
-        }
-        su3_mul<false>(u, h, o);
-        reconstruct<MU, SF>(acc, o);
+    using S = typename PT<P>::S;
+    constexpr int MU = K / 2;
+    constexpr bool FWD = (K % 2) == 0;
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    int nb;
+    if constexpr (FWD) {
+        h.wrap = (d[MU] == a.g.L[MU] - 1);
+        d[MU] = h.wrap ? 0 : d[MU] + 1;
+        nb = cb_index(a.g, d);
+        load_planes<S, NL>(a.links + (long)(a.p_out * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), cb, a.g.vh,
+                           h.link);
+    } else {
+        h.wrap = (d[MU] == 0);
+        d[MU] = h.wrap ? a.g.L[MU] - 1 : d[MU] - 1;
+        nb = cb_index(a.g, d);
+        load_planes<S, NL>(a.links + (long)((1 - a.p_out) * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), nb,
+                           a.g.vh, h.link);
     }
-    {
-        int d[4] = {c[0], c[1], c[2], c[3]};
-        const bool wrap = (d[MU] == 0);
-        d[MU] = wrap ? a.g.L[MU] - 1 : d[MU] - 1;
-        const int nb = cb_index(a.g, d);
-        const Spinor<R> ps = load_spinor<P>(in, nb, a.in_n);
-        cx<R> h[6], u[9], o[6];
-        project<MU, SB>(ps, h);
-        load_link<P, NL>(a.links, vh, 1 - p_out, MU, nb, u);
-        if (wrap) {
-            const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], -(R)a.g.bc_im[MU]};
 #pragma unroll
-            for (int i = 0; i < 6; ++i) h[i] = ph * h[i];
-        }
-        su3_mul<true>(u, h, o);
-        reconstruct<MU, SB>(acc, o);
+    for (int r = 0; r < NR; ++r) {
+        // right-hand sides past the group's end re-read the last one (discarded)
+        const int rr = r < nr ? r : nr - 1;
+        const char *base = in + rr * a.in_rs;
+        load_planes<S, 24>(base, nb, a.in_n, h.sp[r]);
+        if constexpr (PT<P>::scaled)
+            h.scale[r] = *reinterpret_cast<const float *>(base + 48 * (size_t)a.in_n + (uint32_t)nb * 4u);
     }
 }
 
-template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT>
-__global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
+template <int P, int NL, bool DAG, int NR, int K>
+__device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, NR> &h,
+                                        cx<typename PT<P>::R> (&acc)[NR][12])
 {
     using R = typename PT<P>::R;
+    constexpr int MU = K / 2;
+    constexpr bool FWD = (K % 2) == 0;
+    // forward: (1 - gamma) U(x) for H, (1 + gamma) for H^dag; backward the opposite sign with U(x-mu)^dag
+    constexpr int SG = (FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1));
+    cx<R> u[9];
+#pragma unroll
+    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)h.link[2 * i], (R)h.link[2 * i + 1]};
+    if constexpr (NL == 12) {
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+    const cx<R> ph = h.wrap ? cx<R>{(R)a.g.bc_re[MU], FWD ? (R)a.g.bc_im[MU] : -(R)a.g.bc_im[MU]} : cx<R>{1, 0};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        Spinor<R> ps;
+        if constexpr (PT<P>::scaled) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                ps.c[i] = cx<R>{(R)h.sp[r][2 * i] * h.scale[r], (R)h.sp[r][2 * i + 1] * h.scale[r]};
+        } else {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) ps.c[i] = cx<R>{(R)h.sp[r][2 * i], (R)h.sp[r][2 * i + 1]};
+        }
+        cx<R> hh[6], o[6];
+        project<MU, SG>(ps, hh);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) hh[i] = ph * hh[i];
+        su3_mul<!FWD>(u, hh, o);
+        reconstruct<MU, SG>(acc[r], o);
+    }
+}
+
+// Pipeline step K: compute half K from slot K % PF, then refill that slot
+// with half K + PF.
+template <int P, int NL, bool DAG, int NR, int PF, int K>
+__device__ __forceinline__ void pipeline(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
+                                         HalfRaw<P, NL, NR> (&slot)[PF], cx<typename PT<P>::R> (&acc)[NR][12])
+{
+    if constexpr (K < 8) {
+        consume<P, NL, DAG, NR, K>(a, slot[K % PF], acc);
+        if constexpr (K + PF < 8) gather<P, NL, NR, K + PF>(a, in, nr, cb, c, slot[K % PF]);
+        pipeline<P, NL, DAG, NR, PF, K + 1>(a, in, nr, cb, c, slot, acc);
+    }
+}
+
+template <int P, int NL, int NR, int PF, int K>
+__device__ __forceinline__ void prologue(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
+                                         HalfRaw<P, NL, NR> (&slot)[PF])
+{
+    if constexpr (K < PF) {
+        gather<P, NL, NR, K>(a, in, nr, cb, c, slot[K]);
+        prologue<P, NL, NR, PF, K + 1>(a, in, nr, cb, c, slot);
+    }
+}
+
+// prefetch depth (halves in flight per thread) by storage precision
+// (several right-hand sides per thread already multiply the loads in flight)
+template <int P, int NR> struct Prefetch {
+    static constexpr int base = P == F16 ? 4 : P == F32 ? 2 : 1;
+    static constexpr int value = base / NR > 0 ? base / NR : 1;
+};
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR, int PF = Prefetch<P, NR>::value>
+__device__ __forceinline__ void hop_body(const HopArgs &a)
+{
+    using R = typename PT<P>::R;
+    using S = typename PT<P>::S;
     // Workgroups are dispatched to the 8 XCDs round-robin; give each XCD a
-    // contiguous range of (site block, rhs) tiles so that neighbour spinors
-    // and, with several right-hand sides, the shared links of a site block
-    // are re-read from that XCD's L2.  rhs varies fastest within the range.
+    // contiguous range of (site block, rhs group) tiles so that neighbour
+    // spinors and the links shared by the groups of a site block are
+    // re-read from that XCD's L2.  The rhs group varies fastest.
     const int nbs = (a.g.vh + NT - 1) / NT;
-    const int total = nbs * a.nrhs;
+    const int ngr = (a.nrhs + NR - 1) / NR;
+    const int total = nbs * ngr;
     const int full = a.xcd_remap ? (total / 8) * 8 : 0;
     const int id = blockIdx.x;
     const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
-    const int sblk = t / a.nrhs;
-    const int rhs = t - sblk * a.nrhs;
+    const int sblk = t / ngr;
+    const int rhs0 = (t - sblk * ngr) * NR;
+    int nr = min(NR, a.nrhs - rhs0);
+    // a tile whose right-hand sides are all frozen (converged or broken-down
+    // systems of a solver) exits at once; a tile with a live one runs whole
+    if (a.mask) {
+        bool any = false;
+        for (int r = 0; r < nr; ++r) {
+            const double *m = a.mask + (long)(rhs0 + r) * a.mask_stride;
+            any = any || (m[a.mask_off0] == 0.0 && m[a.mask_off1] == 0.0);
+        }
+        if (!any) nr = 0;
+    }
     const int cb = sblk * NT + threadIdx.x;
-    const bool valid = cb < a.g.vh;
-    double red0 = 0.0, red1 = 0.0;
+    const bool valid = cb < a.g.vh && nr > 0;
+    double red0[NR], red1[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red0[r] = red1[r] = 0.0;
     if (valid) {
-        const char *in = a.in + rhs * a.in_rs;
+        const char *in = a.in + rhs0 * a.in_rs;
         int c[4];
         cb_coords(a.g, a.p_out, cb, c);
-        cx<R> acc[12];
+        cx<R> acc[NR][12];
 #pragma unroll
-        for (int i = 0; i < 12; ++i) acc[i] = cx<R>{0, 0};
-        hop_dir<P, NL, DAG, 0>(a, in, cb, c, a.p_out, acc);
-        hop_dir<P, NL, DAG, 1>(a, in, cb, c, a.p_out, acc);
-        hop_dir<P, NL, DAG, 2>(a, in, cb, c, a.p_out, acc);
-        hop_dir<P, NL, DAG, 3>(a, in, cb, c, a.p_out, acc);
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc[r][i] = cx<R>{0, 0};
+        HalfRaw<P, NL, NR> slot[PF];
+        prologue<P, NL, NR, PF, 0>(a, in, nr, cb, c, slot);
+        pipeline<P, NL, DAG, NR, PF, 0>(a, in, nr, cb, c, slot, acc);
+        S craw[CLOV ? 72 : 1];
+        if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
         const R coef = (R)a.coef;
-        Spinor<R> res;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[i];
-        if constexpr (XPAY) {
-            Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
-            if constexpr (CLOV == 1) clover_mul<P>(a.clov, a.g.vh, cb, yv);
+        for (int r = 0; r < NR; ++r) {
+            if (r < nr) {
+                const int rhs = rhs0 + r;
+                Spinor<R> res;
 #pragma unroll
-            for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
-        }
-        if constexpr (CLOV == 2) clover_mul<P>(a.clov, a.g.vh, cb, res);
-        store_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n, res);
-        if constexpr (RED == 1) {
-            // the norm of what was stored (FP16: of the rounded values)
-            if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
+                for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[r][i];
+                if constexpr (XPAY) {
+                    Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
+                    if constexpr (CLOV == 1) clover_mul_raw(craw, yv);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) red0 += (double)norm2(res.c[i]);
-        } else if constexpr (RED == 2) {
-            if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
-            const Spinor<R> wv = load_spinor<P>(a.w + rhs * a.w_rs, cb, a.w_n);
+                    for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
+                }
+                if constexpr (CLOV == 2) clover_mul_raw(craw, res);
+                store_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n, res);
+                if constexpr (RED == 1) {
+                    // the norm of what was stored (FP16: of the rounded values)
+                    if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) {
-                const cx<R> t = cmulc(wv.c[i], res.c[i]);
-                red0 += (double)t.re;
-                red1 += (double)t.im;
+                    for (int i = 0; i < 12; ++i) red0[r] += (double)norm2(res.c[i]);
+                } else if constexpr (RED == 2) {
+                    if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
+                    const Spinor<R> wv = load_spinor<P>(a.w + rhs * a.w_rs, cb, a.w_n);
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) {
+                        const cx<R> q = cmulc(wv.c[i], res.c[i]);
+                        red0[r] += (double)q.re;
+                        red1[r] += (double)q.im;
+                    }
+                }
             }
         }
     }
     if constexpr (RED != 0) {
         __shared__ double lds[NT / 64];
-        const double s0 = block_sum<NT>(red0, lds);
-        if constexpr (RED == 1) {
-            if (threadIdx.x == 0) a.partial[(long)rhs * nbs + sblk] = s0;
-        } else {
-            const double s1 = block_sum<NT>(red1, lds);
-            if (threadIdx.x == 0) {
-                a.partial[2 * ((long)rhs * nbs + sblk)] = s0;
-                a.partial[2 * ((long)rhs * nbs + sblk) + 1] = s1;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r < nr) {
+                const long slot = (long)(rhs0 + r) * nbs + sblk;
+                const double s0 = block_sum<NT>(red0[r], lds);
+                if constexpr (RED == 1) {
+                    if (threadIdx.x == 0) a.partial[slot] = s0;
+                } else {
+                    const double s1 = block_sum<NT>(red1[r], lds);
+                    if (threadIdx.x == 0) {
+                        a.partial[2 * slot] = s0;
+                        a.partial[2 * slot + 1] = s1;
+                    }
+                }
             }
         }
     }
 }
 
-template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR>
+__global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
+{
+    hop_body<P, NL, DAG, CLOV, XPAY, RED, NT, NR>(a);
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NR>
 static hipError_t launch_nt(const HopArgs &a, int block, hipStream_t s)
 {
-    const dim3 grid(hop_blocks(a.g.vh, block) * a.nrhs);
+    const int ngr = (a.nrhs + NR - 1) / NR;
+    const dim3 grid(hop_blocks(a.g.vh, block) * ngr);
     switch (block) {
-    case 64: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 64><<<grid, 64, 0, s>>>(a); break;
-    case 128: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 128><<<grid, 128, 0, s>>>(a); break;
-    case 256: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 256><<<grid, 256, 0, s>>>(a); break;
+    case 64: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 64, NR><<<grid, 64, 0, s>>>(a); break;
+    case 128: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 128, NR><<<grid, 128, 0, s>>>(a); break;
+    case 256: hop_kernel<P, NL, DAG, CLOV, XPAY, RED, 256, NR><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Right-hand sides per thread: NR = 1, or 2 / 4 for the epilogues of the
+// operators (plain, clover on the result, clover on y with axpy, axpy).
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
+{
+    if constexpr (RED == 0) {
+        if (nr == 2) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 2>(a, block, s);
+        if (nr == 4) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 4>(a, block, s);
+    }
+    if (nr == 1) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 1>(a, block, s);
+    return hipErrorInvalidValue;
 }
 
 // The epilogue combinations the operators use:
 //   (clov, xpay, red) in {(0,0,0) plain hop, (2,0,0) C H x, (1,1,*) C y + c H x,
 //                         (0,1,*) y + c H x, (2,1,0) C (y + c H x)}
 template <int P, int NL, bool DAG>
-static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int block, hipStream_t s)
+static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
     if (!xpay && red == 0) {
-        if (clov == 0) return launch_nt<P, NL, DAG, 0, false, 0>(a, block, s);
-        if (clov == 2) return launch_nt<P, NL, DAG, 2, false, 0>(a, block, s);
+        if (clov == 0) return launch_nr<P, NL, DAG, 0, false, 0>(a, nr, block, s);
+        if (clov == 2) return launch_nr<P, NL, DAG, 2, false, 0>(a, nr, block, s);
     } else if (xpay) {
-        if (clov == 0 && red == 0) return launch_nt<P, NL, DAG, 0, true, 0>(a, block, s);
-        if (clov == 0 && red == 1) return launch_nt<P, NL, DAG, 0, true, 1>(a, block, s);
-        if (clov == 0 && red == 2) return launch_nt<P, NL, DAG, 0, true, 2>(a, block, s);
-        if (clov == 1 && red == 0) return launch_nt<P, NL, DAG, 1, true, 0>(a, block, s);
-        if (clov == 1 && red == 1) return launch_nt<P, NL, DAG, 1, true, 1>(a, block, s);
-        if (clov == 1 && red == 2) return launch_nt<P, NL, DAG, 1, true, 2>(a, block, s);
-        if (clov == 2 && red == 0) return launch_nt<P, NL, DAG, 2, true, 0>(a, block, s);
+        if (clov == 0 && red == 0) return launch_nr<P, NL, DAG, 0, true, 0>(a, nr, block, s);
+        if (clov == 0 && red == 1) return launch_nr<P, NL, DAG, 0, true, 1>(a, nr, block, s);
+        if (clov == 0 && red == 2) return launch_nr<P, NL, DAG, 0, true, 2>(a, nr, block, s);
+        if (clov == 1 && red == 0) return launch_nr<P, NL, DAG, 1, true, 0>(a, nr, block, s);
+        if (clov == 1 && red == 1) return launch_nr<P, NL, DAG, 1, true, 1>(a, nr, block, s);
+        if (clov == 1 && red == 2) return launch_nr<P, NL, DAG, 1, true, 2>(a, nr, block, s);
+        if (clov == 2 && red == 0) return launch_nr<P, NL, DAG, 2, true, 0>(a, nr, block, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int P>
-static hipError_t launch_p(const HopArgs &a, int recon, bool dag, int clov, bool xpay, int red, int block,
-                           hipStream_t s)
+template <int P, bool DAG>
+static hipError_t launch_pd(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
-    if (recon == 18) {
-        return dag ? launch_epi<P, 18, true>(a, clov, xpay, red, block, s)
-                   : launch_epi<P, 18, false>(a, clov, xpay, red, block, s);
-    }
+    if (recon == 18) return launch_epi<P, 18, DAG>(a, clov, xpay, red, nr, block, s);
     if constexpr (P != F64) {
-        if (recon == 12)
-            return dag ? launch_epi<P, 12, true>(a, clov, xpay, red, block, s)
-                       : launch_epi<P, 12, false>(a, clov, xpay, red, block, s);
+        if (recon == 12) return launch_epi<P, 12, DAG>(a, clov, xpay, red, nr, block, s);
     }
     return hipErrorInvalidValue;
 }

@@ -69,20 +69,27 @@ template <typename T, int N> struct Planes {
     __host__ __device__ static constexpr long field_bytes(long n) { return (long)BYTES * n; }
 };
 
+// Addresses are formed as (plane base, uniform across the wavefront) +
+// (32-bit per-lane byte offset), the form the hardware takes as a scalar
+// base plus a vector offset; a plane of n sites is below 2^31 bytes
+// (n <= 2^27 is enforced when an operator is created).
 template <typename T, int N>
 __device__ __forceinline__ void load_planes(const char *__restrict__ base, long s, long n, T *__restrict__ out)
 {
     using PL = Planes<T, N>;
+    const uint32_t o16 = (uint32_t)s * 16u;
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(base + ((long)k * n + s) * 16);
+        const char *pl = base + (size_t)k * 16 * (size_t)n;
+        const uint4 q = *reinterpret_cast<const uint4 *>(pl + o16);
         __builtin_memcpy(out + k * PL::PER16, &q, 16);
     }
+    const char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
     if constexpr (PL::TAIL == 8) {
-        const uint2 q = *reinterpret_cast<const uint2 *>(base + (long)PL::K16 * 16 * n + s * 8);
+        const uint2 q = *reinterpret_cast<const uint2 *>(tl + (uint32_t)s * 8u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 8);
     } else if constexpr (PL::TAIL == 4) {
-        const uint32_t q = *reinterpret_cast<const uint32_t *>(base + (long)PL::K16 * 16 * n + s * 4);
+        const uint32_t q = *reinterpret_cast<const uint32_t *>(tl + (uint32_t)s * 4u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 4);
     }
 }
@@ -91,20 +98,23 @@ template <typename T, int N>
 __device__ __forceinline__ void store_planes(char *__restrict__ base, long s, long n, const T *__restrict__ in)
 {
     using PL = Planes<T, N>;
+    const uint32_t o16 = (uint32_t)s * 16u;
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
         uint4 q;
         __builtin_memcpy(&q, in + k * PL::PER16, 16);
-        *reinterpret_cast<uint4 *>(base + ((long)k * n + s) * 16) = q;
+        char *pl = base + (size_t)k * 16 * (size_t)n;
+        *reinterpret_cast<uint4 *>(pl + o16) = q;
     }
+    char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
     if constexpr (PL::TAIL == 8) {
         uint2 q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 8);
-        *reinterpret_cast<uint2 *>(base + (long)PL::K16 * 16 * n + s * 8) = q;
+        *reinterpret_cast<uint2 *>(tl + (uint32_t)s * 8u) = q;
     } else if constexpr (PL::TAIL == 4) {
         uint32_t q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 4);
-        *reinterpret_cast<uint32_t *>(base + (long)PL::K16 * 16 * n + s * 4) = q;
+        *reinterpret_cast<uint32_t *>(tl + (uint32_t)s * 4u) = q;
     }
 }
 
@@ -128,7 +138,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__r
     load_planes<S, 24>(base, s, n, raw);
     Spinor<R> o;
     if constexpr (PT<P>::scaled) {
-        const float sc = *reinterpret_cast<const float *>(base + 48 * n + 4 * s);
+        const float sc = *reinterpret_cast<const float *>(base + 48 * (size_t)n + (uint32_t)s * 4u);
 #pragma unroll
         for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i] * sc, (R)raw[2 * i + 1] * sc};
     } else {
@@ -155,7 +165,7 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, lo
             raw[2 * i] = (S)(v.c[i].re * inv);
             raw[2 * i + 1] = (S)(v.c[i].im * inv);
         }
-        *reinterpret_cast<float *>(base + 48 * n + 4 * s) = m;
+        *reinterpret_cast<float *>(base + 48 * (size_t)n + (uint32_t)s * 4u) = m;
     } else {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {

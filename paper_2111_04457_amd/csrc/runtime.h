@@ -54,6 +54,7 @@ struct lq_op {
     bool has_clover = false;
     int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
     int xcd_remap[3] = {1, 1, 1};        // XCD-aware tile order of the hop kernel per precision
+    int rhs_per_thread[3] = {2, 2, 2};   // right-hand sides per thread of the hop kernel (nrhs > 1)
     lq::Buf links[3];                    // packed links per precision ([parity][mu])
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
@@ -65,6 +66,7 @@ struct lq_op {
     double *host_sc = nullptr;           // pinned host mirror of the solver scalars
     size_t host_sc_n = 0;
     int use_graphs = 1;                  // capture inner-iteration chunks in hipGraphs
+    const double *hop_mask = nullptr;    // per-system freeze flags for hop kernels (set by the solvers)
     hipStream_t stream = nullptr;        // internal stream of solves (capturable)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // captured inner-iteration chunks, keyed by everything the kernels read

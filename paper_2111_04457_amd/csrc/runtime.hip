@@ -1,7 +1,12 @@
 // runtime.hip -- operator applies on packed fields.
 #include "runtime.h"
 
+#include "blas.h"
+
 namespace lq {
+
+// layout of the solver scalars read as a freeze mask by the hop kernels
+constexpr int MASK_STRIDE = NSC, MASK_DONE = SC_DONE, MASK_BREAK = SC_BREAK;
 
 static thread_local std::string g_last_error;
 
@@ -61,12 +66,19 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
     a.coef = coef;
     a.xcd_remap = op->xcd_remap[prec];
+    if (op->hop_mask) {
+        a.mask = op->hop_mask;
+        a.mask_stride = MASK_STRIDE;
+        a.mask_off0 = MASK_DONE;
+        a.mask_off1 = MASK_BREAK;
+    }
     const int block = op->hop_block[prec];
     if (red) {
         op->partial.ensure((size_t)hop_blocks(g.vh, block) * in.nrhs * 2 * sizeof(double));
         a.partial = reinterpret_cast<double *>(op->partial.ptr);
     }
-    LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, block, s));
+    const int nr = (red == 0 && in.nrhs > 1) ? op->rhs_per_thread[prec] : 1;
+    LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, nr, block, s));
 }
 
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s)

@@ -26,6 +26,9 @@ struct SolveCtx {
     char *odd_tmp[3] = {nullptr, nullptr, nullptr};
     long n_hop = 0;
     double hop_bytes = 0;
+    // inside an inner-iteration chunk: kernels skip frozen systems and hop
+    // applies are counted afterwards from the systems' iteration counters
+    bool masked = false;
     // FP64 vectors of the solve space
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
@@ -34,6 +37,9 @@ struct SolveCtx {
     FieldView space(char *base, int p) const;
     size_t space_bytes(int p) const;
     void count_hops(int prec, int n);
+    // account 4 hopping applies (two operator applies) per inner iteration
+    // the systems performed since the last call
+    void count_iterations(std::vector<double> &prev);
     // out = M in (dag: M^dag), in the precision of the views
     void apply(const FieldView &out, const FieldView &in, bool dag);
     void reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin);
@@ -52,10 +58,14 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
         for (int k = 0; k < chunk; ++k) body();
         return;
     }
+    // the graph replays the chunk with the masking state it was captured with
+    const long masked_key = masked ? 1 : 0;
     const std::vector<long> key = {kind, chunk, nsys, eo ? 1 : 0, pin, px, (long)op->solver_ws.ptr,
                                    (long)op->solver_ws.bytes, (long)partial, (long)sc,
                                    (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
-                                   (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2], (long)(void *)s};
+                                   (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
+                                   (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1],
+                                   (long)op->rhs_per_thread[2], (long)(void *)s, masked_key};
     lq_op::GraphEntry *e = nullptr;
     for (auto &g : op->graphs)
         if (g.key == key) e = &g;

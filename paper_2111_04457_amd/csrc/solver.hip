@@ -54,9 +54,11 @@ int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
     LQ_HIP(launch_copy(c.irhat, c.irin, c.sc, c.sps, false, c.s));
     LQ_HIP(launch_copy(c.ip, c.irin, c.sc, c.sps, false, c.s));
     c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_BICG);
+    std::vector<double> prev(c.nsys, 0.0);
     int it = 0;
     while (it < max_iter) {
         const int chunk = std::min(check_every, max_iter - it);
+        c.masked = true;
         c.run_chunk(1, chunk, [&]() {
             c.apply(c.iv, c.ip, false);
             c.reduce_finish(c.irhat, c.iv, RED_DOT, FIN_BICG_ALPHA);
@@ -67,8 +69,10 @@ int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
             c.finish(3, FIN_BICG_RHO, c.ir.n);
             LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));
         });
+        c.masked = false;
         it += chunk;
         c.pull();
+        c.count_iterations(prev);
         if (all_frozen(c)) break;
     }
     return it;
@@ -84,9 +88,11 @@ int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, int check_every)
     else c.apply(c.ir, c.irin, true);
     LQ_HIP(launch_copy(c.ip, c.ir, c.sc, c.sps, false, c.s));
     c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_CG);
+    std::vector<double> prev(c.nsys, 0.0);
     int it = 0;
     while (it < max_iter) {
         const int chunk = std::min(check_every, max_iter - it);
+        c.masked = true;
         c.run_chunk(2, chunk, [&]() {
             c.apply(c.iw, c.ip, false);
             c.reduce_finish(c.iw, c.iw, RED_NORM, FIN_CG_ALPHA);
@@ -95,8 +101,10 @@ int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, int check_every)
             c.finish(1, FIN_CG_BETA, c.ir.n);
             LQ_HIP(launch_cg_p(c.ip, c.ir, c.sc, c.sps, c.s));
         });
+        c.masked = false;
         it += chunk;
         c.pull();
+        c.count_iterations(prev);
         if (all_frozen(c)) break;
     }
     return it;
@@ -114,22 +122,43 @@ size_t SolveCtx::space_bytes(int p) const { return (size_t)fb(p, op->g) * nsys *
 void SolveCtx::count_hops(int prec, int n)
 {
     double b, f;
-    lq_op_traffic(op, (lq_prec)prec, 1, op->has_clover ? 1 : 0, &b, &f);
+    // per output site and system, the links shared by the nsys systems
+    lq_op_traffic(op, (lq_prec)prec, nsys, op->has_clover ? 1 : 0, &b, &f);
     n_hop += n;
     hop_bytes += (double)n * b * op->g.vh * nsys;
+}
+
+void SolveCtx::count_iterations(std::vector<double> &prev)
+{
+    double b, f;
+    lq_op_traffic(op, (lq_prec)pin, nsys, op->has_clover ? 1 : 0, &b, &f);
+    for (int i = 0; i < nsys; ++i) {
+        const double it = hsc[i * NSC + SC_ITER];
+        const double d = it - prev[i];
+        prev[i] = it;
+        n_hop += (long)(4 * d);
+        hop_bytes += 4.0 * d * b * op->g.vh;
+    }
 }
 
 void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
 {
     const int p = in.prec;
-    if (eo) schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, dag, s);
-    else dirac_full(op, p, out.base, in.base, nsys, dag, s);
-    count_hops(p, 2);
+    op->hop_mask = masked ? sc : nullptr;
+    try {
+        if (eo) schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, dag, s);
+        else dirac_full(op, p, out.base, in.base, nsys, dag, s);
+    } catch (...) {
+        op->hop_mask = nullptr;
+        throw;
+    }
+    op->hop_mask = nullptr;
+    if (!masked) count_hops(p, 2);
 }
 
 void SolveCtx::reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin)
 {
-    LQ_HIP(launch_reduce(x, y, mode, partial, s));
+    LQ_HIP(launch_reduce(x, y, mode, partial, s, masked ? sc : nullptr, sps));
     const int K = mode == RED_NORM ? 1 : mode == RED_DOT ? 2 : 3;
     LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(x.n), K, op_fin, sc, 1e-30, s));
 }

@@ -128,4 +128,32 @@ __device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh
     }
 }
 
+// The same product with the 72 packed reals already loaded (one load of the
+// clover block serves several right-hand sides).
+template <typename S, typename R>
+__device__ __forceinline__ void clover_mul_raw(const S *__restrict__ raw, Spinor<R> &v)
+{
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const S *c = raw + 36 * b;
+        cx<R> x[6], y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = v.c[6 * b + i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) y[i] = (R)c[i] * x[i];
+        int k = 6;
+#pragma unroll
+        for (int i = 1; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < i; ++j) {
+                const cx<R> l = cx<R>{(R)c[k], (R)c[k + 1]};
+                k += 2;
+                y[i] = y[i] + l * x[j];
+                y[j] = y[j] + cmulc(l, x[i]);
+            }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v.c[6 * b + i] = y[i];
+    }
+}
+
 }  // namespace lq

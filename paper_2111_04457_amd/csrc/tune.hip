@@ -39,6 +39,7 @@ struct Entry {
     std::string key;
     int block = 256;
     int xcd = 1;
+    int nr = 2;
     double us = 0;
 };
 
@@ -76,6 +77,7 @@ std::vector<Entry> read_cache(const std::string &path)
         };
         e.block = (int)num("block", 256);
         e.xcd = (int)num("xcd_remap", 1);
+        e.nr = (int)num("rhs_per_thread", 2);
         e.us = num("us", 0);
         if (e.block == 64 || e.block == 128 || e.block == 256) out.push_back(e);
         pos = cb + 1;
@@ -91,7 +93,8 @@ void write_cache(const std::string &path, const std::vector<Entry> &entries)
     f << "{\n";
     for (size_t i = 0; i < entries.size(); ++i) {
         const Entry &e = entries[i];
-        f << "  \"" << e.key << "\": {\"block\": " << e.block << ", \"xcd_remap\": " << e.xcd << ", \"us\": " << e.us
+        f << "  \"" << e.key << "\": {\"block\": " << e.block << ", \"xcd_remap\": " << e.xcd
+          << ", \"rhs_per_thread\": " << e.nr << ", \"us\": " << e.us
           << "}" << (i + 1 < entries.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -165,10 +168,14 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 double best_us = 1e30;
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
+                const int save_nr = op->rhs_per_thread[prec];
+                const std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{save_nr};
+                for (int nrt : nrs)
                 for (int block : {256, 128, 64}) {
                     for (int remap : {1, 0}) {
                         op->hop_block[prec] = block;
                         op->xcd_remap[prec] = remap;
+                        op->rhs_per_thread[prec] = nrt;
                         for (int w = 0; w < 2; ++w) apply_packed(op, LQ_SCHUR, prec, out.base, in.base, nrhs, s);
                         const int reps = g.vh >= (1 << 18) ? 10 : 40;
                         std::vector<float> t(reps);
@@ -189,12 +196,14 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         } else if (cur_host != ref_host) {
                             op->hop_block[prec] = save_block;
                             op->xcd_remap[prec] = save_remap;
+                            op->rhs_per_thread[prec] = save_nr;
                             throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results"};
                         }
                         if (us < best_us) {
                             best_us = us;
                             best.block = block;
                             best.xcd = remap;
+                            best.nr = nrt;
                         }
                     }
                 }
@@ -204,7 +213,9 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             }
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
+            if (nrhs > 1 && (best.nr == 1 || best.nr == 2 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
+                << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";
         }
         LQ_HIP(hipEventDestroy(e0));
