@@ -57,6 +57,84 @@ def _traffic_from_profile(kernel_tag: str):
         return None
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, 1e3 * (time.perf_counter() - t)
+
+
+def _extras(lq, torch):
+    """The other workloads, each timed once after a warm-up call:
+    - the 12 spin-colour point sources of one propagator on 24^3x48 (clover,
+      kappa 0.135, c_sw 1.7) as one 12-RHS solve vs 12 single solves;
+    - a ragged batch 8^4, 12^4, 16^3x32, 20^3x40 (4 Gaussian sources each)
+      in one batched solve vs separate solves;
+    - the pseudofermion force on 16^4 Wilson (kappa 0.125), FP64 and FP32."""
+    from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_parity_spinor, gaussian_spinor,
+                                point_sources, workload_gauge)
+    out = {}
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2, check_every=10)
+    w = WORKLOADS["clover_24x24x24x48"]
+    d = w["dims"]
+    op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(torch.from_numpy(workload_gauge("clover_24x24x24x48")).cuda())
+    op.tune(12)
+    src = torch.from_numpy(point_sources(d)).cuda()
+    op.solve(src, "D", prm)
+    (_, st), ms12 = _timed(torch, lambda: op.solve(src, "D", prm))
+    op.solve(src[0], "D", prm)
+    ms1 = 0.0
+    for k in range(12):
+        _, m = _timed(torch, lambda: op.solve(src[k], "D", prm))
+        ms1 += m
+    out["propagator_24x24x24x48_12rhs_ms"] = ms12
+    out["propagator_24x24x24x48_12_single_ms"] = ms1
+    out["propagator_12rhs_speedup"] = ms1 / ms12
+    out["propagator_max_diff"] = max(s.diff for s in st)
+    out["propagator_iters"] = [s.nconv for s in st]
+    op.close()
+    print("bench: propagator %.1f ms (12 RHS) vs %.1f ms (12 single)" % (ms12, ms1), file=sys.stderr, flush=True)
+
+    ops, bs = [], []
+    for i, dd in enumerate(RAGGED_DIMS):
+        o = lq.Operator(dd, 0.135, 1.7, ANTIPERIODIC_T, link_recon=12)
+        o.set_gauge(torch.from_numpy(workload_gauge("clover_24x24x24x48", dims=dd)).cuda())
+        ops.append(o)
+        bs.append(torch.from_numpy(gaussian_spinor(dd, 2003 + 10 * i, 4)).cuda())
+    batch = lq.Batch(ops, [4] * len(ops))
+    batch.solve(bs, prm)
+    (_, stb), msb = _timed(torch, lambda: batch.solve(bs, prm))
+    mss = 0.0
+    for o, b in zip(ops, bs):
+        o.solve(b, "D", prm)
+        _, m = _timed(torch, lambda: o.solve(b, "D", prm))
+        mss += m
+    out["ragged_batch_ms"] = msb
+    out["ragged_separate_ms"] = mss
+    out["ragged_batch_speedup"] = mss / msb
+    out["ragged_max_diff"] = max(s.diff for s in stb)
+    batch.close()
+    for o in ops:
+        o.close()
+    print("bench: ragged batch %.1f ms vs %.1f ms separate" % (msb, mss), file=sys.stderr, flush=True)
+
+    w = WORKLOADS["wilson_16x16x16x16"]
+    d = w["dims"]
+    op = lq.Operator(d, w["kappa"], 0.0, ANTIPERIODIC_T)
+    op.set_gauge(torch.from_numpy(workload_gauge("wilson_16x16x16x16")).cuda())
+    phi = torch.from_numpy(gaussian_parity_spinor(d, 2004)).cuda()
+    for prec, inner in (("f64", "f64"), ("f32", "f32")):
+        fp = lq.SolverParams(solver="cgne", tol=1e-12, inner=inner)
+        lq.pf_force(op, phi, fp, "eo", prec)
+        (res, ms) = _timed(torch, lambda: lq.pf_force(op, phi, fp, "eo", prec))
+        out["force_16x16x16x16_%s_ms" % prec] = ms
+        out["force_16x16x16x16_%s_iters" % prec] = res[4].nconv
+    op.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +149,8 @@ def main(argv=None):
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32-inner reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 12-RHS propagator, ragged batch and force measurements")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -159,29 +239,39 @@ def main(argv=None):
             tts["speedup_vs_fp64"] = tts["fp64_ms"] / ms_per_step
         print("bench: reference solves %s" % json.dumps(tts), file=sys.stderr, flush=True)
 
-    # dslash kernel alone: hopping term even -> odd on resident packed fields
+    # dslash kernel alone: hopping term even -> odd on resident packed fields,
+    # at each workgroup size the library offers (the best one is reported)
     kern = {}
     roof = None
     for prec in ("f16", "f32", "f64"):
         fin = lq.Field(op, prec)
         fout = lq.Field(op, prec)
         fin.load(b_d.reshape(-1, 4, 3)[: V // 2].contiguous())
-        for _ in range(3):
-            lq.apply_field(op, "hop_oe", fout, fin)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.kernel_reps):
-            lq.apply_field(op, "hop_oe", fout, fin)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.kernel_reps
+        tuned_blk = op.get_option("hop_block_" + prec)
+        best = None
+        for blk in (256, 128, 64):
+            op.set_block(prec, blk)
+            for _ in range(3):
+                lq.apply_field(op, "hop_oe", fout, fin)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.kernel_reps):
+                lq.apply_field(op, "hop_oe", fout, fin)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.kernel_reps
+            kern["dslash_%s_b%d_us" % (prec, blk)] = 1e3 * ms
+            if best is None or ms < best[1]:
+                best = (blk, ms)
+        op.set_block(prec, tuned_blk)
+        blk, ms = best
         bps, fps = op.traffic(prec, 1, clover=False)
         gbs = bps * (V // 2) / (ms * 1e-3) / 1e9
         kern["dslash_%s_us" % prec] = 1e3 * ms
+        kern["dslash_%s_block" % prec] = blk
         kern["dslash_%s_GBs" % prec] = gbs
         kern["dslash_%s_TFLOPs" % prec] = fps * (V // 2) / (ms * 1e-3) / 1e12
         if prec == args.inner or (prec == "f16" and roof is None):
-            blk = op.get_option("hop_block_" + prec)
             tag = "hop_kernel<%s,%d,dag=0,clov=0,xpay=0,red=0,%d>" % (prec, 18 if prec == "f64" else args.recon, blk)
             traffic = _traffic_from_profile(tag) if prec == "f16" else None
             roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
@@ -203,6 +293,9 @@ def main(argv=None):
     del a, c
     print("bench: kernels %s" % json.dumps(kern), file=sys.stderr, flush=True)
 
+    op.close()
+    extras = None if args.no_extras else _extras(lq, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -218,7 +311,6 @@ def main(argv=None):
                "sample": "%d full-lattice FP64 hopping-term applies of the oracle on %s (%d sites each), %.2f s each"
                          % (reps, args.workload, V, tc)}
 
-    op.close()
     line = {
         "metric": "dslash GB/s (% HBM peak); time to 1e-10 residual, mixed vs FP64 solve",
         "value": value,
@@ -240,6 +332,7 @@ def main(argv=None):
         "time_to_solution": tts,
         "kernels": kern,
         "tuning": tune,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
     return 0

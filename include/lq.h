@@ -66,6 +66,7 @@ extern "C" {
 
 typedef struct lq_op lq_op;
 typedef struct lq_field lq_field;
+typedef struct lq_batch lq_batch;
 
 typedef enum {
     LQ_OK = 0,
@@ -193,9 +194,11 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *   "xcd_remap" 0|1  XCD-aware order of the hopping kernel's workgroups (default 1),
  *                    all precisions; "xcd_remap_f64" / "_f32" / "_f16" per precision;
  *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
- *   "rhs_per_thread" 1|2|4  right-hand sides one thread of the hopping kernel
+ *   "rhs_per_thread" 1|2  right-hand sides one thread of the hopping kernel
  *                    handles when several are applied together (each loaded
- *                    link is used for all of them; default 2); per precision
+ *                    link is used for both; default 1, where the right-hand
+ *                    sides of one site block run in adjacent workgroups and
+ *                    share the links through the L2); per precision
  *                    "rhs_per_thread_f64" / "_f32" / "_f16".
  * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16".
  * LQ_ERR_ARG for an unknown name or value. */
@@ -219,10 +222,26 @@ lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, dou
 lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
                    int use_x0, lq_solve_stats *stats, void *stream);
 
+/* Batched solve over several lattices (a ragged batch: operators of
+ * different volumes and gauge fields, nrhs[i] right-hand sides each).
+ * lq_batch_create validates (distinct operators on one device, nrhs >= 1)
+ * and keeps the list; the operators must outlive the batch.
+ * lq_batch_solve solves D_i x_i = b_i for every lattice with the same
+ * solver parameters: b[i], x[i] are device complex128 full fields
+ * [nrhs[i]][V_i][4][3]; stats receives sum(nrhs) entries in batch order.
+ * Every chunk of inner iterations of all lattices is one hipGraph launch
+ * (one branch per lattice).  Results equal those of separate lq_solve calls
+ * bit for bit. */
+lq_status lq_batch_create(lq_op *const *ops, int nops, const int *nrhs, lq_batch **out);
+lq_status lq_batch_solve(lq_batch *batch, const lq_solver_params *sp, void *const *x, const void *const *b,
+                         lq_solve_stats *stats, void *stream);
+void lq_batch_destroy(lq_batch *batch);
+
 /* Autotuner: for each storage precision, times the Schur operator (the two
  * fused hopping kernels of every solver iteration, nrhs right-hand sides)
- * over workgroup sizes {64, 128, 256} and both workgroup orders with HIP
- * events, requires every candidate's output to be bitwise equal to the
+ * over workgroup sizes {64, 128, 256}, both workgroup orders and, for
+ * nrhs > 1, one or two right-hand sides per thread, with HIP events,
+ * requires every candidate's output to be bitwise equal to the
  * first's, and keeps the fastest on the operator.  Results are cached in
  * the JSON file cache_path (or $LQ_TUNE_CACHE; NULL and unset: no cache),
  * keyed by kernel, precision, lattice, link format, nrhs and architecture;

@@ -6,12 +6,13 @@ include/lq.h; this package only marshals torch tensors and streams to it.
 """
 from ._lib import LQError, load  # noqa: F401
 
-__all__ = ["Operator", "Field", "SolverParams", "SolveStats", "apply_field", "pf_force", "PseudofermionAction",
+__all__ = ["Operator", "Field", "Batch", "SolverParams", "SolveStats", "apply_field", "pf_force", "PseudofermionAction",
            "LQError", "load"]
 
 
 def __getattr__(name):
-    if name in ("Operator", "Field", "SolverParams", "SolveStats", "apply_field", "pf_force", "PseudofermionAction"):
+    if name in ("Operator", "Field", "Batch", "SolverParams", "SolveStats", "apply_field", "pf_force",
+                "PseudofermionAction"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

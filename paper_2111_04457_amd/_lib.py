@@ -66,6 +66,10 @@ SIGNATURES = {
     "lq_op_get_option": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
     "lq_op_traffic": (I, [P, I, I, I, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "lq_solve": (I, [P, ctypes.POINTER(SolverParams), I, I, P, P, I, ctypes.POINTER(SolveStats), P]),
+    "lq_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(I), ctypes.POINTER(P)]),
+    "lq_batch_solve": (I, [P, ctypes.POINTER(SolverParams), ctypes.POINTER(P), ctypes.POINTER(P),
+                           ctypes.POINTER(SolveStats), P]),
+    "lq_batch_destroy": (None, [P]),
     "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),

@@ -268,3 +268,44 @@ class PseudofermionAction(torch.autograd.Function):
     def backward(ctx, gS):
         grad_U, X = ctx.saved_tensors
         return gS * grad_U, 2.0 * gS * X, None, None, None, None
+
+
+class Batch:
+    """A ragged batch: several operators (lattices of different volumes),
+    nrhs[i] right-hand sides each, solved together (lq_batch_solve)."""
+
+    def __init__(self, ops, nrhs):
+        self.ops = list(ops)
+        self.nrhs = [int(n) for n in nrhs]
+        arr = (ctypes.c_void_p * len(self.ops))(*[o.handle for o in self.ops])
+        nr = (ctypes.c_int * len(self.ops))(*self.nrhs)
+        h = ctypes.c_void_p()
+        check(load().lq_batch_create(arr, len(self.ops), nr, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lq_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, params: SolverParams | None = None):
+        """bs[i]: [nrhs[i], Lt, Lz, Ly, Lx, 4, 3] complex128 CUDA tensors.
+        Returns ([x_i], [SolveStats] in batch order)."""
+        params = params or SolverParams()
+        bs = [_dev(b, op.full_shape, "b").reshape((n,) + op.full_shape) for b, op, n in zip(bs, self.ops, self.nrhs)]
+        xs = [torch.zeros_like(b) for b in bs]
+        total = sum(self.nrhs)
+        stats = (_lib.SolveStats * total)()
+        xa = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        ba = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
+        cp = params.to_c()
+        check(load().lq_batch_solve(self._h, ctypes.byref(cp), xa, ba, stats, _stream()), allow_not_converged=True)
+        out = [SolveStats(s.nconv, s.nouter, s.restarts, bool(s.converged), s.diff, s.t_solve_ms, s.hop_bytes, s.n_hop)
+               for s in stats]
+        return xs, out

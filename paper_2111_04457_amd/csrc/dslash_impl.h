@@ -24,7 +24,7 @@ template <int P, int NL, int NR> struct HalfRaw {
     bool wrap;
 };
 
-template <int P, int NL, int NR, int K>
+template <int P, int NL, int NR, int K, bool NTL = false>
 __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
                                        HalfRaw<P, NL, NR> &h)
 {
@@ -37,14 +37,14 @@ __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict_
         h.wrap = (d[MU] == a.g.L[MU] - 1);
         d[MU] = h.wrap ? 0 : d[MU] + 1;
         nb = cb_index(a.g, d);
-        load_planes<S, NL>(a.links + (long)(a.p_out * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), cb, a.g.vh,
-                           h.link);
+        load_planes<S, NL, NTL>(a.links + (long)(a.p_out * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), cb,
+                                a.g.vh, h.link);
     } else {
         h.wrap = (d[MU] == 0);
         d[MU] = h.wrap ? a.g.L[MU] - 1 : d[MU] - 1;
         nb = cb_index(a.g, d);
-        load_planes<S, NL>(a.links + (long)((1 - a.p_out) * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), nb,
-                           a.g.vh, h.link);
+        load_planes<S, NL, NTL>(a.links + (long)((1 - a.p_out) * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), nb,
+                                a.g.vh, h.link);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -97,24 +97,24 @@ __device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, N
 
 // Pipeline step K: compute half K from slot K % PF, then refill that slot
 // with half K + PF.
-template <int P, int NL, bool DAG, int NR, int PF, int K>
+template <int P, int NL, bool DAG, int NR, int PF, int K, bool NTL>
 __device__ __forceinline__ void pipeline(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
                                          HalfRaw<P, NL, NR> (&slot)[PF], cx<typename PT<P>::R> (&acc)[NR][12])
 {
     if constexpr (K < 8) {
         consume<P, NL, DAG, NR, K>(a, slot[K % PF], acc);
-        if constexpr (K + PF < 8) gather<P, NL, NR, K + PF>(a, in, nr, cb, c, slot[K % PF]);
-        pipeline<P, NL, DAG, NR, PF, K + 1>(a, in, nr, cb, c, slot, acc);
+        if constexpr (K + PF < 8) gather<P, NL, NR, K + PF, NTL>(a, in, nr, cb, c, slot[K % PF]);
+        pipeline<P, NL, DAG, NR, PF, K + 1, NTL>(a, in, nr, cb, c, slot, acc);
     }
 }
 
-template <int P, int NL, int NR, int PF, int K>
+template <int P, int NL, int NR, int PF, int K, bool NTL>
 __device__ __forceinline__ void prologue(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
                                          HalfRaw<P, NL, NR> (&slot)[PF])
 {
     if constexpr (K < PF) {
-        gather<P, NL, NR, K>(a, in, nr, cb, c, slot[K]);
-        prologue<P, NL, NR, PF, K + 1>(a, in, nr, cb, c, slot);
+        gather<P, NL, NR, K, NTL>(a, in, nr, cb, c, slot[K]);
+        prologue<P, NL, NR, PF, K + 1, NTL>(a, in, nr, cb, c, slot);
     }
 }
 
@@ -125,7 +125,9 @@ template <int P, int NR> struct Prefetch {
     static constexpr int value = base / NR > 0 ? base / NR : 1;
 };
 
-template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR, int PF = Prefetch<P, NR>::value>
+// CACHE: bit 0 non-temporal link loads, bit 1 non-temporal output stores.
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR, int PF = Prefetch<P, NR>::value,
+          int CACHE = 0>
 __device__ __forceinline__ void hop_body(const HopArgs &a)
 {
     using R = typename PT<P>::R;
@@ -168,8 +170,8 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
 #pragma unroll
             for (int i = 0; i < 12; ++i) acc[r][i] = cx<R>{0, 0};
         HalfRaw<P, NL, NR> slot[PF];
-        prologue<P, NL, NR, PF, 0>(a, in, nr, cb, c, slot);
-        pipeline<P, NL, DAG, NR, PF, 0>(a, in, nr, cb, c, slot, acc);
+        prologue<P, NL, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot);
+        pipeline<P, NL, DAG, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot, acc);
         S craw[CLOV ? 72 : 1];
         if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
         const R coef = (R)a.coef;
@@ -187,7 +189,7 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
                     for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
                 }
                 if constexpr (CLOV == 2) clover_mul_raw(craw, res);
-                store_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n, res);
+                store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
                 if constexpr (RED == 1) {
                     // the norm of what was stored (FP16: of the rounded values)
                     if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
@@ -247,14 +249,13 @@ static hipError_t launch_nt(const HopArgs &a, int block, hipStream_t s)
     return hipGetLastError();
 }
 
-// Right-hand sides per thread: NR = 1, or 2 / 4 for the epilogues of the
+// Right-hand sides per thread: NR = 1, or 2 for the epilogues of the
 // operators (plain, clover on the result, clover on y with axpy, axpy).
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
 static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 {
     if constexpr (RED == 0) {
         if (nr == 2) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 2>(a, block, s);
-        if (nr == 4) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 4>(a, block, s);
     }
     if (nr == 1) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 1>(a, block, s);
     return hipErrorInvalidValue;

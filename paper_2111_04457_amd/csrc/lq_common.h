@@ -41,16 +41,35 @@ template <typename R> struct cx {
 template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
 template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+// All code is compiled without implicit multiply-add contraction; fused
+// multiply-adds are written out, so every instantiation of a kernel (any
+// launch shape, any number of right-hand sides per thread) rounds exactly
+// the same operations and produces bit-identical results.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// (a plain product: a fused form here doubles the register use of the
+// binary16 hopping kernels)
 template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
 {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a b
+template <typename R> __device__ __forceinline__ cx<R> cmac(cx<R> acc, cx<R> a, cx<R> b)
+{
+    return {fmar(a.re, b.re, fmar(-a.im, b.im, acc.re)), fmar(a.re, b.im, fmar(a.im, b.re, acc.im))};
+}
+// acc + conj(a) b
+template <typename R> __device__ __forceinline__ cx<R> cmacc(cx<R> acc, cx<R> a, cx<R> b)
+{
+    return {fmar(a.re, b.re, fmar(a.im, b.im, acc.re)), fmar(a.re, b.im, fmar(-a.im, b.re, acc.im))};
 }
 template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
 template <typename R> __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
 // conj(a) * b
 template <typename R> __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b)
 {
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fmar(a.re, b.re, a.im * b.im), fmar(a.re, b.im, -(a.im * b.re))};
 }
 // multiply by +i / -i
 template <typename R> __device__ __forceinline__ cx<R> ti(cx<R> a) { return {-a.im, a.re}; }
@@ -73,7 +92,23 @@ template <typename T, int N> struct Planes {
 // (32-bit per-lane byte offset), the form the hardware takes as a scalar
 // base plus a vector offset; a plane of n sites is below 2^31 bytes
 // (n <= 2^27 is enforced when an operator is created).
-template <typename T, int N>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// NTL / NTS: non-temporal access (streamed data with no reuse, kept from
+// displacing reused data in the caches).
+template <typename V, bool NT> __device__ __forceinline__ V ld(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else return *reinterpret_cast<const V *>(p);
+}
+template <typename V, bool NT> __device__ __forceinline__ void st(void *p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    else *reinterpret_cast<V *>(p) = v;
+}
+
+template <typename T, int N, bool NTL = false>
 __device__ __forceinline__ void load_planes(const char *__restrict__ base, long s, long n, T *__restrict__ out)
 {
     using PL = Planes<T, N>;
@@ -81,40 +116,39 @@ __device__ __forceinline__ void load_planes(const char *__restrict__ base, long 
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
         const char *pl = base + (size_t)k * 16 * (size_t)n;
-        const uint4 q = *reinterpret_cast<const uint4 *>(pl + o16);
+        const u32x4 q = ld<u32x4, NTL>(pl + o16);
         __builtin_memcpy(out + k * PL::PER16, &q, 16);
     }
     const char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
     if constexpr (PL::TAIL == 8) {
-        const uint2 q = *reinterpret_cast<const uint2 *>(tl + (uint32_t)s * 8u);
+        const u32x2 q = ld<u32x2, NTL>(tl + (uint32_t)s * 8u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 8);
     } else if constexpr (PL::TAIL == 4) {
-        const uint32_t q = *reinterpret_cast<const uint32_t *>(tl + (uint32_t)s * 4u);
+        const uint32_t q = ld<uint32_t, NTL>(tl + (uint32_t)s * 4u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 4);
     }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool NTS = false>
 __device__ __forceinline__ void store_planes(char *__restrict__ base, long s, long n, const T *__restrict__ in)
 {
     using PL = Planes<T, N>;
     const uint32_t o16 = (uint32_t)s * 16u;
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
-        uint4 q;
+        u32x4 q;
         __builtin_memcpy(&q, in + k * PL::PER16, 16);
-        char *pl = base + (size_t)k * 16 * (size_t)n;
-        *reinterpret_cast<uint4 *>(pl + o16) = q;
+        st<u32x4, NTS>(base + (size_t)k * 16 * (size_t)n + o16, q);
     }
     char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
     if constexpr (PL::TAIL == 8) {
-        uint2 q;
+        u32x2 q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 8);
-        *reinterpret_cast<uint2 *>(tl + (uint32_t)s * 8u) = q;
+        st<u32x2, NTS>(tl + (uint32_t)s * 8u, q);
     } else if constexpr (PL::TAIL == 4) {
         uint32_t q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 4);
-        *reinterpret_cast<uint32_t *>(tl + (uint32_t)s * 4u) = q;
+        st<uint32_t, NTS>(tl + (uint32_t)s * 4u, q);
     }
 }
 
@@ -148,7 +182,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__r
     return o;
 }
 
-template <int P>
+template <int P, bool NTS = false>
 __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, long n,
                                              const Spinor<typename PT<P>::R> &v)
 {
@@ -165,7 +199,7 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, lo
             raw[2 * i] = (S)(v.c[i].re * inv);
             raw[2 * i + 1] = (S)(v.c[i].im * inv);
         }
-        *reinterpret_cast<float *>(base + 48 * (size_t)n + (uint32_t)s * 4u) = m;
+        st<float, NTS>(base + 48 * (size_t)n + (uint32_t)s * 4u, m);
     } else {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
@@ -173,7 +207,7 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, lo
             raw[2 * i + 1] = (S)v.c[i].im;
         }
     }
-    store_planes<S, 24>(base, s, n, raw);
+    store_planes<S, 24, NTS>(base, s, n, raw);
 }
 
 // ------------------------------------------------------------- geometry --

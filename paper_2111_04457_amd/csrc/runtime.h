@@ -54,7 +54,7 @@ struct lq_op {
     bool has_clover = false;
     int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
     int xcd_remap[3] = {1, 1, 1};        // XCD-aware tile order of the hop kernel per precision
-    int rhs_per_thread[3] = {2, 2, 2};   // right-hand sides per thread of the hop kernel (nrhs > 1)
+    int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
     lq::Buf links[3];                    // packed links per precision ([parity][mu])
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
@@ -78,8 +78,10 @@ struct lq_op {
         double hop_bytes = 0;
     };
     std::vector<GraphEntry> graphs;
+    long generation = 0;                 // bumped whenever captured graphs become stale
     void clear_graphs()
     {
+        ++generation;
         for (auto &e : graphs) {
             if (e.exec) (void)hipGraphExecDestroy(e.exec);
             if (e.graph) (void)hipGraphDestroy(e.graph);

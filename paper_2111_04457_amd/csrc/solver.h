@@ -111,6 +111,14 @@ struct OuterStats {
 OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool normal, const FieldView &rhs,
                              const std::vector<double> &target2);
 
+// Inner Krylov pieces: initialisation from e = 0 and one iteration,
+// launched on c.s (used by the single solve and by the batched solve).
+void bicg_init(SolveCtx &c);
+void bicg_iter(SolveCtx &c);
+void cg_init(SolveCtx &c, bool normal_rhs);
+void cg_iter(SolveCtx &c);
+bool all_frozen(const SolveCtx &c);
+
 // Host-side validation of solver parameters; why holds the reason.
 bool valid_solver_params(const lq_solver_params *sp, std::string &why);
 

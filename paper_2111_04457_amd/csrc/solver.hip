@@ -37,6 +37,52 @@ struct Arena {
     }
 };
 
+}  // namespace
+
+// Inner BiCGStab on M e = rin from e = 0 (SC_TARGET2 relative to |rin|).
+void bicg_init(SolveCtx &c)
+{
+    LQ_HIP(launch_zero(c.ix, c.s));
+    LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    LQ_HIP(launch_copy(c.irhat, c.irin, c.sc, c.sps, false, c.s));
+    LQ_HIP(launch_copy(c.ip, c.irin, c.sc, c.sps, false, c.s));
+    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_BICG);
+}
+
+void bicg_iter(SolveCtx &c)
+{
+    c.apply(c.iv, c.ip, false);
+    c.reduce_finish(c.irhat, c.iv, RED_DOT, FIN_BICG_ALPHA);
+    LQ_HIP(launch_bicg_s(c.is, c.ir, c.iv, c.sc, c.sps, c.s));
+    c.apply(c.it, c.is, false);
+    c.reduce_finish(c.is, c.it, RED_DOT_NORM, FIN_BICG_OMEGA);
+    LQ_HIP(launch_bicg_xr(c.ix, c.ir, c.ip, c.is, c.it, c.irhat, c.sc, c.sps, c.partial, c.s));
+    c.finish(3, FIN_BICG_RHO, c.ir.n);
+    LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));
+}
+
+// Inner CG from e = 0 on M^dag M e = M^dag rin (normal_rhs = false) or on
+// M^dag M e = rin (normal_rhs = true); SC_TARGET2 relative to the initial
+// residual.
+void cg_init(SolveCtx &c, bool normal_rhs)
+{
+    LQ_HIP(launch_zero(c.ix, c.s));
+    if (normal_rhs) LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    else c.apply(c.ir, c.irin, true);
+    LQ_HIP(launch_copy(c.ip, c.ir, c.sc, c.sps, false, c.s));
+    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_CG);
+}
+
+void cg_iter(SolveCtx &c)
+{
+    c.apply(c.iw, c.ip, false);
+    c.reduce_finish(c.iw, c.iw, RED_NORM, FIN_CG_ALPHA);
+    c.apply(c.iv, c.iw, true);
+    LQ_HIP(launch_cg_xr(c.ix, c.ir, c.ip, c.iv, c.sc, c.sps, c.partial, c.s));
+    c.finish(1, FIN_CG_BETA, c.ir.n);
+    LQ_HIP(launch_cg_p(c.ip, c.ir, c.sc, c.sps, c.s));
+}
+
 bool all_frozen(const SolveCtx &c)
 {
     for (int i = 0; i < c.nsys; ++i) {
@@ -46,29 +92,27 @@ bool all_frozen(const SolveCtx &c)
     return true;
 }
 
-// Inner BiCGStab on M e = rin from e = 0 (SC_TARGET2 relative to |rin|).
-int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
+namespace {
+
+// Run inner iterations in chunks of check_every (captured in a hipGraph),
+// reading the scalars back after each chunk, until every system is frozen
+// or max_iter iterations were made.
+int inner_loop(SolveCtx &c, int kind, int max_iter, int check_every)
 {
-    LQ_HIP(launch_zero(c.ix, c.s));
-    LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
-    LQ_HIP(launch_copy(c.irhat, c.irin, c.sc, c.sps, false, c.s));
-    LQ_HIP(launch_copy(c.ip, c.irin, c.sc, c.sps, false, c.s));
-    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_BICG);
     std::vector<double> prev(c.nsys, 0.0);
     int it = 0;
     while (it < max_iter) {
         const int chunk = std::min(check_every, max_iter - it);
         c.masked = true;
-        c.run_chunk(1, chunk, [&]() {
-            c.apply(c.iv, c.ip, false);
-            c.reduce_finish(c.irhat, c.iv, RED_DOT, FIN_BICG_ALPHA);
-            LQ_HIP(launch_bicg_s(c.is, c.ir, c.iv, c.sc, c.sps, c.s));
-            c.apply(c.it, c.is, false);
-            c.reduce_finish(c.is, c.it, RED_DOT_NORM, FIN_BICG_OMEGA);
-            LQ_HIP(launch_bicg_xr(c.ix, c.ir, c.ip, c.is, c.it, c.irhat, c.sc, c.sps, c.partial, c.s));
-            c.finish(3, FIN_BICG_RHO, c.ir.n);
-            LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));
-        });
+        try {
+            c.run_chunk(kind, chunk, [&]() {
+                if (kind == 1) bicg_iter(c);
+                else cg_iter(c);
+            });
+        } catch (...) {
+            c.masked = false;
+            throw;
+        }
         c.masked = false;
         it += chunk;
         c.pull();
@@ -78,36 +122,16 @@ int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
     return it;
 }
 
-// Inner CG from e = 0 on M^dag M e = M^dag rin (normal_rhs = false) or on
-// M^dag M e = rin (normal_rhs = true); SC_TARGET2 relative to the initial
-// residual.
+int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
+{
+    bicg_init(c);
+    return inner_loop(c, 1, max_iter, check_every);
+}
+
 int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, int check_every)
 {
-    LQ_HIP(launch_zero(c.ix, c.s));
-    if (normal_rhs) LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
-    else c.apply(c.ir, c.irin, true);
-    LQ_HIP(launch_copy(c.ip, c.ir, c.sc, c.sps, false, c.s));
-    c.reduce_finish(c.ir, c.ir, RED_NORM, FIN_INIT_CG);
-    std::vector<double> prev(c.nsys, 0.0);
-    int it = 0;
-    while (it < max_iter) {
-        const int chunk = std::min(check_every, max_iter - it);
-        c.masked = true;
-        c.run_chunk(2, chunk, [&]() {
-            c.apply(c.iw, c.ip, false);
-            c.reduce_finish(c.iw, c.iw, RED_NORM, FIN_CG_ALPHA);
-            c.apply(c.iv, c.iw, true);
-            LQ_HIP(launch_cg_xr(c.ix, c.ir, c.ip, c.iv, c.sc, c.sps, c.partial, c.s));
-            c.finish(1, FIN_CG_BETA, c.ir.n);
-            LQ_HIP(launch_cg_p(c.ip, c.ir, c.sc, c.sps, c.s));
-        });
-        c.masked = false;
-        it += chunk;
-        c.pull();
-        c.count_iterations(prev);
-        if (all_frozen(c)) break;
-    }
-    return it;
+    cg_init(c, normal_rhs);
+    return inner_loop(c, 2, max_iter, check_every);
 }
 
 }  // namespace

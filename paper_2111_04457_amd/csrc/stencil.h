@@ -84,15 +84,31 @@ __device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[6], cx<R
             cx<R> acc;
             if constexpr (!DAGU) {
                 acc = u[a * 3 + 0] * h[s * 3 + 0];
-                acc = acc + u[a * 3 + 1] * h[s * 3 + 1];
-                acc = acc + u[a * 3 + 2] * h[s * 3 + 2];
+                acc = cmac(acc, u[a * 3 + 1], h[s * 3 + 1]);
+                acc = cmac(acc, u[a * 3 + 2], h[s * 3 + 2]);
             } else {
                 acc = cmulc(u[0 * 3 + a], h[s * 3 + 0]);
-                acc = acc + cmulc(u[1 * 3 + a], h[s * 3 + 1]);
-                acc = acc + cmulc(u[2 * 3 + a], h[s * 3 + 2]);
+                acc = cmacc(acc, u[1 * 3 + a], h[s * 3 + 1]);
+                acc = cmacc(acc, u[2 * 3 + a], h[s * 3 + 2]);
             }
             o[s * 3 + a] = acc;
         }
+}
+
+// y_i += l x_j and y_j += conj(l) x_i for one strictly-lower entry l of a
+// Hermitian block.  Fused in single precision, separate products in double
+// (the forms the register allocator handles best for each type; both are
+// the same in every kernel that uses them).
+template <typename R>
+__device__ __forceinline__ void clov_acc(cx<R> &yi, cx<R> &yj, const cx<R> l, const cx<R> xi, const cx<R> xj)
+{
+    if constexpr (sizeof(R) == 4) {
+        yi = cmac(yi, l, xj);
+        yj = cmacc(yj, l, xi);
+    } else {
+        yi = yi + l * xj;
+        yj = yj + cmulc(l, xi);
+    }
 }
 
 // y = C x with C two packed 6x6 Hermitian blocks: per block 6 real diagonal
@@ -120,8 +136,7 @@ __device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh
             for (int j = 0; j < i; ++j) {
                 const cx<R> l = cx<R>{(R)c[k], (R)c[k + 1]};
                 k += 2;
-                y[i] = y[i] + l * x[j];
-                y[j] = y[j] + cmulc(l, x[i]);
+                clov_acc(y[i], y[j], l, x[i], x[j]);
             }
 #pragma unroll
         for (int i = 0; i < 6; ++i) v.c[6 * b + i] = y[i];
@@ -148,8 +163,7 @@ __device__ __forceinline__ void clover_mul_raw(const S *__restrict__ raw, Spinor
             for (int j = 0; j < i; ++j) {
                 const cx<R> l = cx<R>{(R)c[k], (R)c[k + 1]};
                 k += 2;
-                y[i] = y[i] + l * x[j];
-                y[j] = y[j] + cmulc(l, x[i]);
+                clov_acc(y[i], y[j], l, x[i], x[j]);
             }
 #pragma unroll
         for (int i = 0; i < 6; ++i) v.c[6 * b + i] = y[i];

@@ -77,7 +77,7 @@ std::vector<Entry> read_cache(const std::string &path)
         };
         e.block = (int)num("block", 256);
         e.xcd = (int)num("xcd_remap", 1);
-        e.nr = (int)num("rhs_per_thread", 2);
+        e.nr = (int)num("rhs_per_thread", 1);
         e.us = num("us", 0);
         if (e.block == 64 || e.block == 128 || e.block == 256) out.push_back(e);
         pos = cb + 1;
@@ -169,7 +169,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
                 const int save_nr = op->rhs_per_thread[prec];
-                const std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{save_nr};
+                const std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2} : std::vector<int>{save_nr};
                 for (int nrt : nrs)
                 for (int block : {256, 128, 64}) {
                     for (int remap : {1, 0}) {
@@ -213,7 +213,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             }
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
-            if (nrhs > 1 && (best.nr == 1 || best.nr == 2 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
+            if (nrhs > 1 && (best.nr == 1 || best.nr == 2)) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
                 << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";

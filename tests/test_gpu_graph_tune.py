@@ -78,3 +78,23 @@ def test_tuner_bitwise_cache_and_solve(lq, inputs, tmp_path):
     x, st = op.solve(to_dev(b[0]), "D", lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2))
     assert st[0].converged and oracle.true_residual(ref, to_host(x), b[0]) <= 1.01e-10
     op.close()
+
+
+def test_tuner_multi_rhs_shapes_bitwise(lq, inputs):
+    """With several right-hand sides the tuner also sweeps the number of
+    right-hand sides per thread; every shape must give the same bits (the
+    tuner rejects the sweep otherwise), so the output is unchanged."""
+    U, _ = inputs
+    op = lq.Operator(DIMS, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    xe = np.stack([gaussian_parity_spinor(DIMS, 2610 + i) for i in range(5)])
+    before = {p: to_host(op.apply("schur", to_dev(xe), p)) for p in ("f64", "f32", "f16")}
+    rep = op.tune(5)
+    announce("tune(5) report %s" % json.dumps(rep))
+    for p in ("f64", "f32", "f16"):
+        assert op.get_option("rhs_per_thread_" + p) in (1, 2)
+        assert np.array_equal(to_host(op.apply("schur", to_dev(xe), p)), before[p])
+    for p, nr in (("f32", 1), ("f32", 2), ("f16", 1), ("f16", 2), ("f64", 2)):
+        op.set_option("rhs_per_thread_" + p, nr)
+        assert np.array_equal(to_host(op.apply("schur", to_dev(xe), p)), before[p]), (p, nr)
+    op.close()
