@@ -71,9 +71,11 @@ def _extras(lq, torch):
       kappa 0.135, c_sw 1.7) as one 12-RHS solve vs 12 single solves;
     - a ragged batch 8^4, 12^4, 16^3x32, 20^3x40 (4 Gaussian sources each)
       in one batched solve vs separate solves;
+    - time to solution on 16^3x32 clover (kappa 0.13, c_sw 1.0): FP64
+      BiCGStab and CGNE vs FP32- and FP16-inner BiCGStab;
     - the pseudofermion force on 16^4 Wilson (kappa 0.125), FP64 and FP32."""
     from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_parity_spinor, gaussian_spinor,
-                                point_sources, workload_gauge)
+                                point_sources, workload_gauge, workload_source)
     out = {}
     prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2, check_every=10)
     w = WORKLOADS["clover_24x24x24x48"]
@@ -119,6 +121,29 @@ def _extras(lq, torch):
     for o in ops:
         o.close()
     print("bench: ragged batch %.1f ms vs %.1f ms separate" % (msb, mss), file=sys.stderr, flush=True)
+
+    w = WORKLOADS["clover_16x16x16x32"]
+    d = w["dims"]
+    op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(torch.from_numpy(workload_gauge("clover_16x16x16x32")).cuda())
+    b1 = torch.from_numpy(workload_source("clover_16x16x16x32")).cuda()
+    x64 = None
+    for name, solver, inner, itol in (("fp64", "bicgstab", "f64", 1e-5), ("fp64_cgne", "cgne", "f64", 1e-5),
+                                      ("mixed_f32", "bicgstab", "f32", 1e-5), ("mixed_f16", "bicgstab", "f16", 1e-2)):
+        p1 = lq.SolverParams(solver=solver, tol=1e-10, inner=inner, inner_tol=itol, check_every=10)
+        op.solve(b1, "D", p1)
+        (xs, st1), ms = _timed(torch, lambda: op.solve(b1, "D", p1))
+        out["clover_16x16x16x32_%s_ms" % name] = ms
+        out["clover_16x16x16x32_%s_iters" % name] = st1[0].nconv
+        out["clover_16x16x16x32_%s_diff" % name] = st1[0].diff
+        if name == "fp64":
+            x64 = xs
+        else:
+            out["clover_16x16x16x32_%s_err_vs_fp64" % name] = float(torch.linalg.vector_norm(xs - x64) /
+                                                                    torch.linalg.vector_norm(x64))
+    op.close()
+    print("bench: 16x16x16x32 ladder %s" % json.dumps({k: v for k, v in out.items() if k.startswith("clover_16")}),
+          file=sys.stderr, flush=True)
 
     w = WORKLOADS["wilson_16x16x16x16"]
     d = w["dims"]
@@ -180,9 +205,13 @@ def main(argv=None):
     U_d = torch.from_numpy(U).cuda()
     b_d = torch.from_numpy(b).cuda()
     op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=args.recon)
-    op.set_gauge(U_d)
-    del U_d
+    op.set_gauge(U_d)  # first call also allocates the operator's fields
     torch.cuda.synchronize()
+    t_set = time.perf_counter()
+    op.set_gauge(U_d)  # link packing (all precisions) + clover build and inverse
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t_set)
+    del U_d
     tune = None
     if not args.no_tune:
         t_tune = time.time()
@@ -216,23 +245,27 @@ def main(argv=None):
           (args.steps, ms_per_step, stats[-1].nconv, stats[-1].nouter, stats[-1].diff), file=sys.stderr, flush=True)
 
     # time to solution of the reference solves on the same GPU
-    tts = {"mixed_%s_ms" % args.inner: ms_per_step, "mixed_%s_iters" % args.inner: stats[-1].nconv,
+    tts = {"setup_ms": setup_ms, "mixed_%s_ms" % args.inner: ms_per_step, "mixed_%s_iters" % args.inner: stats[-1].nconv,
            "mixed_%s_outer" % args.inner: stats[-1].nouter, "mixed_%s_diff" % args.inner: stats[-1].diff}
     if not args.no_compare:
         refs = {}
-        for inner in ("f64", "f32"):
-            if inner == args.inner:
+        runs = [("f64", args.solver, "fp64"), ("f32", args.solver, "mixed_f32")]
+        if args.solver == "bicgstab":
+            runs.append(("f64", "cgne", "fp64_cgne"))
+        for inner, solver, name in runs:
+            if inner == args.inner and solver == args.solver:
                 continue
-            p2 = lq.SolverParams(solver=args.solver, tol=args.tol, inner=inner,
-                                 inner_tol={"f32": 1e-5, "f64": 1e-5}[inner], check_every=10)
+            p2 = lq.SolverParams(solver=solver, tol=args.tol, inner=inner, inner_tol=1e-5, check_every=10)
+            op.solve(b_d, "D", p2)  # captures this solver's graphs
             torch.cuda.synchronize()
             ta = time.perf_counter()
             xr, sr = op.solve(b_d, "D", p2)
             torch.cuda.synchronize()
-            tts["%s_ms" % ("fp64" if inner == "f64" else "mixed_f32")] = 1e3 * (time.perf_counter() - ta)
-            tts["%s_iters" % ("fp64" if inner == "f64" else "mixed_f32")] = sr[0].nconv
-            tts["%s_diff" % ("fp64" if inner == "f64" else "mixed_f32")] = sr[0].diff
-            refs[inner] = xr
+            tts["%s_ms" % name] = 1e3 * (time.perf_counter() - ta)
+            tts["%s_iters" % name] = sr[0].nconv
+            tts["%s_diff" % name] = sr[0].diff
+            if solver == args.solver:
+                refs[inner] = xr
         if "f64" in refs:
             x64 = refs["f64"]
             tts["err_vs_fp64_solution"] = float(torch.linalg.vector_norm(x_d - x64) / torch.linalg.vector_norm(x64))

@@ -191,8 +191,13 @@ lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_fie
 lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
 
 /* Other execution options (none changes a result bit):
- *   "xcd_remap" 0|1  XCD-aware order of the hopping kernel's workgroups (default 1),
- *                    all precisions; "xcd_remap_f64" / "_f32" / "_f16" per precision;
+ *   "xcd_remap" 0|1|2  order of the hopping kernel's workgroups: 0 plain,
+ *                    1 XCD-aware (each XCD takes a contiguous range of site
+ *                    blocks; default), 2 XCD-aware with the blocks of
+ *                    neighbouring time slices visited one after another
+ *                    (used when a time slice of one parity is a whole number
+ *                    of workgroups, else as 1); all precisions;
+ *                    "xcd_remap_f64" / "_f32" / "_f16" per precision;
  *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
  *   "rhs_per_thread" 1|2  right-hand sides one thread of the hopping kernel
  *                    handles when several are applied together (each loaded
@@ -239,7 +244,7 @@ void lq_batch_destroy(lq_batch *batch);
 
 /* Autotuner: for each storage precision, times the Schur operator (the two
  * fused hopping kernels of every solver iteration, nrhs right-hand sides)
- * over workgroup sizes {64, 128, 256}, both workgroup orders and, for
+ * over workgroup sizes {64, 128, 256}, the three workgroup orders and, for
  * nrhs > 1, one or two right-hand sides per thread, with HIP events,
  * requires every candidate's output to be bitwise equal to the
  * first's, and keeps the fastest on the operator.  Results are cached in

@@ -333,10 +333,11 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
 {
     if (!op || !name) return arg_error("lq_op_set_option: null argument");
     const std::string n(name);
-    if (n == "xcd_remap" && (value == 0 || value == 1)) op->xcd_remap[0] = op->xcd_remap[1] = op->xcd_remap[2] = value;
-    else if (n == "xcd_remap_f64" && (value == 0 || value == 1)) op->xcd_remap[F64] = value;
-    else if (n == "xcd_remap_f32" && (value == 0 || value == 1)) op->xcd_remap[F32] = value;
-    else if (n == "xcd_remap_f16" && (value == 0 || value == 1)) op->xcd_remap[F16] = value;
+    const bool order_ok = value >= 0 && value <= 2;
+    if (n == "xcd_remap" && order_ok) op->xcd_remap[0] = op->xcd_remap[1] = op->xcd_remap[2] = value;
+    else if (n == "xcd_remap_f64" && order_ok) op->xcd_remap[F64] = value;
+    else if (n == "xcd_remap_f32" && order_ok) op->xcd_remap[F32] = value;
+    else if (n == "xcd_remap_f16" && order_ok) op->xcd_remap[F16] = value;
     else if (n == "rhs_per_thread" && (value == 1 || value == 2))
         op->rhs_per_thread[0] = op->rhs_per_thread[1] = op->rhs_per_thread[2] = value;
     else if (n == "rhs_per_thread_f64" && (value == 1 || value == 2)) op->rhs_per_thread[F64] = value;

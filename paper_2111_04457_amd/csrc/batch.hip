@@ -237,6 +237,7 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
         const int kind = sp->solver == LQ_CGNE ? 2 : 1;
         int total_inner = 0;
         std::vector<int> live(n, 1);
+        ChunkPlan plan;  // one chunk length for all lattices: the largest hint
         for (int step = 0; step <= sp->max_outer; ++step) {
             // residuals of the lattices still running
             for (int i = 0; i < n; ++i) {
@@ -282,7 +283,7 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
             }
             constexpr int kInnerCap = 1000;
             const int budget = std::min(sp->max_iter - total_inner, kInnerCap);
-            const int every = std::max(1, sp->check_every);
+            plan.start(sp->check_every);
             std::vector<std::vector<double>> prev(n);
             for (int i = 0; i < n; ++i) prev[i].assign(cs[i].nsys, 0.0);
             std::vector<int> act = live;
@@ -291,7 +292,7 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
             for (int i = 0; i < n; ++i)
                 if (act[i] && (cs[i].pull(), all_frozen(cs[i]))) act[i] = 0;
             while (it < budget && std::any_of(act.begin(), act.end(), [](int v) { return v != 0; })) {
-                const int chunk = std::min(every, budget - it);
+                const int chunk = plan.next(budget - it);
                 run_batch_chunk(bt, cs, act, kind, chunk);
                 it += chunk;
                 for (int i = 0; i < n; ++i) {
@@ -302,6 +303,14 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
                 }
             }
             total_inner += it;
+            int most = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!live[i]) continue;
+                ChunkPlan one;
+                one.learn(cs[i]);
+                most = std::max(most, one.hint);
+            }
+            plan.hint = most;
             for (int i = 0; i < n; ++i) {
                 if (!live[i]) continue;
                 SolveCtx &c = cs[i];

@@ -87,8 +87,24 @@ __global__ __launch_bounds__(BT) void finish_kernel(const double *partial, int s
     const long cnt = (long)sps * nblocks;
     const double *p = partial + (long)sys * cnt * K;
     double v[3] = {0, 0, 0};
-    for (long j = threadIdx.x; j < cnt; j += BT)
-        for (int k = 0; k < K; ++k) v[k] += p[j * K + k];
+    // each thread adds its partials j = tid, tid + BT, ... in that order;
+    // the loads of 8 of them are issued together
+    constexpr int U = 8;
+    for (long j0 = threadIdx.x; j0 < cnt; j0 += U * BT) {
+        double t[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long j = j0 + (long)u * BT;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t[u][k] = (j < cnt && k < K) ? p[j * K + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + (long)u * BT < cnt)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < K) v[k] += t[u][k];
+    }
     __shared__ double lds[BT / 64];
     double tot[3];
     for (int k = 0; k < 3; ++k) tot[k] = block_sum<BT>(v[k], lds);

@@ -40,6 +40,11 @@ struct HopArgs {
     long w_n;
     long w_rs;
     int xcd_remap;       // 1: XCD-aware tile order (result independent of it)
+    // slice order: > 0 when one time slice of the output parity is exactly
+    // slice_tiles workgroups; the tiles of tgroup consecutive slices are then
+    // visited slice-fastest (result independent of it)
+    int slice_tiles;
+    int tgroup;
     // per-rhs freeze mask (solver scalars): a right-hand side r with
     // mask[r * mask_stride + mask_off0] or [.. + mask_off1] nonzero is skipped
     const double *mask;
@@ -49,7 +54,7 @@ struct HopArgs {
 // Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;
 // dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result;
 // xpay: add y; red: 0 none, 1 |out|^2, 2 <w, out> per right-hand side.
-// nr: right-hand sides per thread (1, or 2 / 4 without reduction);
+// nr: right-hand sides per thread (1, or 2 without reduction);
 // block: threads per workgroup (64, 128 or 256).
 hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int nr, int block,
                       hipStream_t s);

@@ -118,6 +118,22 @@ __device__ __forceinline__ void prologue(const HopArgs &a, const char *__restric
     }
 }
 
+// Tile k of the visiting order -> site block.  The site blocks of tg
+// consecutive time slices (S blocks per slice) are visited slice-fastest:
+// the t +- 1 neighbours of a block were read a few workgroups earlier and are
+// still in the L2, where in plain order they lie a whole slice of links and
+// spinors (more than the L2 holds) away.
+__device__ __forceinline__ int slice_order(int k, int S, int tg, int Lt)
+{
+    const int gsz = tg * S;
+    const int grp = k / gsz;
+    const int l = k - grp * gsz;
+    const int nt = min(tg, Lt - grp * tg);
+    const int j = l / nt;
+    const int tt = l - j * nt;
+    return (grp * tg + tt) * S + j;
+}
+
 // prefetch depth (halves in flight per thread) by storage precision
 // (several right-hand sides per thread already multiply the loads in flight)
 template <int P, int NR> struct Prefetch {
@@ -142,8 +158,9 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
     const int full = a.xcd_remap ? (total / 8) * 8 : 0;
     const int id = blockIdx.x;
     const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
-    const int sblk = t / ngr;
-    const int rhs0 = (t - sblk * ngr) * NR;
+    const int k = t / ngr;
+    const int rhs0 = (t - k * ngr) * NR;
+    const int sblk = a.slice_tiles > 0 ? slice_order(k, a.slice_tiles, a.tgroup, a.g.L[3]) : k;
     int nr = min(NR, a.nrhs - rhs0);
     // a tile whose right-hand sides are all frozen (converged or broken-down
     // systems of a solver) exits at once; a tile with a live one runs whole

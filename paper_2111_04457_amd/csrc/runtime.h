@@ -53,7 +53,9 @@ struct lq_op {
     bool gauge_set = false;
     bool has_clover = false;
     int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
-    int xcd_remap[3] = {1, 1, 1};        // XCD-aware tile order of the hop kernel per precision
+    // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
+    // 2 XCD-aware and time slices interleaved
+    int xcd_remap[3] = {1, 1, 1};
     int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
     lq::Buf links[3];                    // packed links per precision ([parity][mu])
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])

@@ -1,6 +1,8 @@
 // runtime.hip -- operator applies on packed fields.
 #include "runtime.h"
 
+#include <algorithm>
+
 #include "blas.h"
 
 namespace lq {
@@ -65,7 +67,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     if (clov_mode && !op->has_clover) clov_mode = 0;
     if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
     a.coef = coef;
-    a.xcd_remap = op->xcd_remap[prec];
+    a.xcd_remap = op->xcd_remap[prec] != 0 ? 1 : 0;
     if (op->hop_mask) {
         a.mask = op->hop_mask;
         a.mask_stride = MASK_STRIDE;
@@ -73,6 +75,13 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         a.mask_off1 = MASK_BREAK;
     }
     const int block = op->hop_block[prec];
+    if (op->xcd_remap[prec] == 2) {
+        const long slice = (long)g.L[0] * g.L[1] * g.L[2] / 2;  // sites of one parity per time slice
+        if (slice % block == 0) {
+            a.slice_tiles = (int)(slice / block);
+            a.tgroup = std::max(1, g.L[3] / 8);  // one group of slices per XCD
+        }
+    }
     if (red) {
         op->partial.ensure((size_t)hop_blocks(g.vh, block) * in.nrhs * 2 * sizeof(double));
         a.partial = reinterpret_cast<double *>(op->partial.ptr);

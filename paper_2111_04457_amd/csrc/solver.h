@@ -52,6 +52,36 @@ struct SolveCtx {
     template <typename Body> void run_chunk(int kind, int chunk, Body body);
 };
 
+// Lengths of the inner-iteration chunks of one inner solve.  The host reads
+// the scalars back after each chunk; a system that converges inside a chunk
+// is masked for the rest of it, so the lengths change only how many masked
+// (nearly empty) iterations are launched, never a result.  The first chunk
+// is the iteration count of the previous inner solve of the same outer loop
+// (every inner solve reduces its residual by about the same factor), then
+// one short chunk, then check_every.
+struct ChunkPlan {
+    int hint = 0;   // iterations the previous inner solve needed (0: none yet)
+    int every = 10;
+    int done = 0;   // iterations launched in this inner solve
+    int extra = 0;  // chunks launched past the hint
+    void start(int check_every)
+    {
+        every = check_every < 1 ? 1 : check_every;
+        done = extra = 0;
+    }
+    int next(int budget_left)
+    {
+        int c;
+        if (hint > done) c = hint - done < every ? hint - done : every;
+        else c = (extra++ == 0 && every > 2) ? 2 : every;
+        if (c > budget_left) c = budget_left;
+        done += c;
+        return c < 1 ? 1 : c;
+    }
+    // after the inner solve: the most iterations a live system made
+    void learn(const SolveCtx &c);
+};
+
 template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body)
 {
     if (!op->use_graphs) {

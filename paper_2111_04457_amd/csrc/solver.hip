@@ -97,12 +97,12 @@ namespace {
 // Run inner iterations in chunks of check_every (captured in a hipGraph),
 // reading the scalars back after each chunk, until every system is frozen
 // or max_iter iterations were made.
-int inner_loop(SolveCtx &c, int kind, int max_iter, int check_every)
+int inner_loop(SolveCtx &c, int kind, int max_iter, ChunkPlan &plan)
 {
     std::vector<double> prev(c.nsys, 0.0);
     int it = 0;
     while (it < max_iter) {
-        const int chunk = std::min(check_every, max_iter - it);
+        const int chunk = plan.next(max_iter - it);
         c.masked = true;
         try {
             c.run_chunk(kind, chunk, [&]() {
@@ -119,22 +119,33 @@ int inner_loop(SolveCtx &c, int kind, int max_iter, int check_every)
         c.count_iterations(prev);
         if (all_frozen(c)) break;
     }
+    plan.learn(c);
     return it;
 }
 
-int inner_bicgstab(SolveCtx &c, int max_iter, int check_every)
+int inner_bicgstab(SolveCtx &c, int max_iter, ChunkPlan &plan)
 {
     bicg_init(c);
-    return inner_loop(c, 1, max_iter, check_every);
+    return inner_loop(c, 1, max_iter, plan);
 }
 
-int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, int check_every)
+int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, ChunkPlan &plan)
 {
     cg_init(c, normal_rhs);
-    return inner_loop(c, 2, max_iter, check_every);
+    return inner_loop(c, 2, max_iter, plan);
 }
 
 }  // namespace
+
+void ChunkPlan::learn(const SolveCtx &c)
+{
+    int most = 0;
+    for (int i = 0; i < c.nsys; ++i) {
+        const double *h = c.hsc + i * NSC;
+        if (h[SC_ODONE] == 0.0 && h[SC_ITER] > most) most = (int)h[SC_ITER];
+    }
+    hint = most;
+}
 
 FieldView SolveCtx::space(char *base, int p) const
 {
@@ -268,6 +279,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     os.outer.assign(nsys, 0);
     os.restarts.assign(nsys, 0);
     int total_inner = 0;
+    ChunkPlan plan;
     for (int step = 0; step <= sp.max_outer; ++step) {
         // r = rhs - A x, |r|^2 (FIN_NORM also flags systems below target)
         c.pull();
@@ -305,11 +317,11 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         // kInnerCap iterations (a restart from the current FP64 iterate)
         constexpr int kInnerCap = 1000;
         const int budget = std::min(sp.max_iter - total_inner, kInnerCap);
-        const int every = std::max(1, sp.check_every);
+        plan.start(sp.check_every);
         int it;
-        if (normal) it = inner_cg(c, true, budget, every);
-        else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, every);
-        else it = inner_bicgstab(c, budget, every);
+        if (normal) it = inner_cg(c, true, budget, plan);
+        else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, plan);
+        else it = inner_bicgstab(c, budget, plan);
         total_inner += it;
         for (int i = 0; i < nsys; ++i) {
             const double *h = c.hsc + i * NSC;

@@ -172,7 +172,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 const std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2} : std::vector<int>{save_nr};
                 for (int nrt : nrs)
                 for (int block : {256, 128, 64}) {
-                    for (int remap : {1, 0}) {
+                    for (int remap : {2, 1, 0}) {
                         op->hop_block[prec] = block;
                         op->xcd_remap[prec] = remap;
                         op->rhs_per_thread[prec] = nrt;

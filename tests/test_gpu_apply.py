@@ -124,3 +124,29 @@ def test_f64_hop_bitwise_across_workgroup_sizes(lib):
         outs.append(to_host(op.apply("schur", src, "f64")))
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_bitwise_across_workgroup_orders_and_sizes(lib, prec):
+    """Every workgroup order (plain, XCD-aware, time slices interleaved) and
+    size gives the same bits; 8x8x4x20 has 128 sites of a parity per time
+    slice, so the interleaved order is active for 64 and 128 threads (groups
+    of 2 slices) and falls back to the XCD order for 256."""
+    dims, kappa, csw = (8, 8, 4, 20), 0.13, 1.5
+    U = gauge_exp(dims, 0.5, 611)
+    op = lib.Operator(dims, kappa, csw, BC, link_recon=12)
+    op.set_gauge(to_dev(U))
+    src = to_dev(gaussian_parity_spinor(dims, 612, 3))
+    ref = oracle.Operator(dims, U, kappa, csw, BC)
+    outs = []
+    for order in (0, 1, 2):
+        op.set_option("xcd_remap_" + prec, order)
+        for block in (64, 128, 256):
+            op.set_block(prec, block)
+            outs.append(to_host(op.apply("schur", src, prec)))
+            outs.append(to_host(op.apply("hop_oe_dag", src, prec)))
+    for k in range(2, len(outs)):
+        assert np.array_equal(outs[k % 2], outs[k]), k
+    for r in range(3):
+        assert rel_err(outs[0][r], ref.schur(to_host(src)[r])) < TOL[prec]
+    op.close()

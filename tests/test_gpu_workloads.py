@@ -1,0 +1,148 @@
+"""Parity at the benchmark's full workload sizes and launch configurations.
+
+- 32^3 x 64 clover (kappa 0.1355, c_sw 1.7, links exp(i 0.5 H)): the hopping
+  kernel the roofline figure is measured on (even -> odd, 12-real links) in
+  FP16, FP32 and FP64 at every workgroup size the bench sweeps: the outputs
+  of all sizes are bit-identical, and 4096 sampled output sites agree with
+  the oracle's per-site hopping sum (FP64, computed site by site).
+- The same lattice's propagator solve as the bench runs it (FP16-storage
+  inner BiCGStab, FP64 defect correction, tuned launch shape) and its FP32-
+  and FP64-inner counterparts: the oracle's own D gives a true residual at
+  or below 1e-10 for each, equal to the reported diff, and the solutions
+  agree within cond(D) * 1e-10.
+- The 24^3 x 48 propagator (12 point sources, one 12-RHS solve) and the
+  ragged batch 8^4, 12^4, 16^3 x 32, 20^3 x 40 (4 Gaussian sources each):
+  every system's true residual, recomputed by the oracle, is at or below
+  1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_spinor, point_sources, workload_gauge,
+                            workload_source)
+from tests.gpu_common import announce, have_gpu, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 5e-3}
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    import paper_2111_04457_amd as lq
+    return lq
+
+
+@pytest.fixture(scope="module")
+def big():
+    name = "clover_32x32x32x64"
+    w = WORKLOADS[name]
+    return w["dims"], workload_gauge(name), workload_source(name), w
+
+
+def _true_residual(dims, U, kappa, csw, x, b, F=None):
+    if F is None and csw != 0.0:
+        F = oracle.clover(dims, U, csw, kappa)
+    r = b - oracle.dirac(dims, U, ANTIPERIODIC_T, kappa, x, F)
+    return float(np.linalg.norm(r.reshape(-1)) / np.linalg.norm(b.reshape(-1)))
+
+
+def test_full_size_hop_sampled_all_blocks(lq, big):
+    dims, U, b, w = big
+    V = int(np.prod(dims))
+    vh = V // 2
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    be = oracle.to_parity(dims, b, 0)
+    full_e = oracle.from_parity(dims, be, 0)  # odd half zero: H psi on odd sites is H_oe psi_e
+    cb = np.sort(np.random.default_rng(7).choice(vh, 4096, replace=False))
+    cb[-1] = vh - 1  # the last site of the ragged tail of every launch shape
+    lex = oracle.parity_sites(dims, 1)[cb]
+    ref = oracle.hop_sites(dims, U, ANTIPERIODIC_T, full_e, lex)
+    for prec in ("f16", "f32", "f64"):
+        announce("full-size hop_oe %s 32x32x32x64" % prec)
+        fin, fout = lq.Field(op, prec), lq.Field(op, prec)
+        fin.load(to_dev(be))
+        outs = []
+        for blk in (256, 128, 64):
+            op.set_block(prec, blk)
+            lq.apply_field(op, "hop_oe", fout, fin)
+            outs.append(to_host(fout.read())[cb])
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o)
+        err = rel_err(outs[0], ref)
+        announce("  sampled rel err %.3e" % err)
+        assert err < TOL[prec]
+        fin.close()
+        fout.close()
+    op.close()
+
+
+def test_full_size_mixed_solves_true_residual(lq, big):
+    dims, U, b, w = big
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    op.tune(1)
+    F = oracle.clover(dims, U, w["csw"], w["kappa"])
+    xs = {}
+    for inner, itol in (("f16", 1e-2), ("f32", 1e-5), ("f64", 1e-5)):
+        announce("full-size solve inner %s 32x32x32x64" % inner)
+        prm = lq.SolverParams(solver="bicgstab", tol=1e-10, inner=inner, inner_tol=itol, check_every=10)
+        x, st = op.solve(to_dev(b), "D", prm)
+        xh = to_host(x)
+        res = _true_residual(dims, U, w["kappa"], w["csw"], xh, b, F)
+        announce("  iters %d outer %d diff %.3e oracle residual %.3e" % (st[0].nconv, st[0].nouter, st[0].diff, res))
+        assert st[0].converged and res <= 1e-10
+        assert abs(res - st[0].diff) <= 1e-3 * res + 1e-15
+        xs[inner] = xh
+    for inner in ("f16", "f32"):
+        assert rel_err(xs[inner], xs["f64"]) < 20 * 2e-10
+    op.close()
+
+
+def test_propagator_24x24x24x48_twelve_rhs(lq):
+    name = "clover_24x24x24x48"
+    w = WORKLOADS[name]
+    dims = w["dims"]
+    U = workload_gauge(name)
+    src = point_sources(dims)
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    op.tune(12)
+    announce("12-RHS propagator 24x24x24x48")
+    x, st = op.solve(to_dev(src), "D", lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2, check_every=10))
+    xh = to_host(x)
+    F = oracle.clover(dims, U, w["csw"], w["kappa"])
+    for k in range(12):
+        res = _true_residual(dims, U, w["kappa"], w["csw"], xh[k], src[k], F)
+        assert st[k].converged and res <= 1e-10, (k, res)
+    op.close()
+
+
+def test_ragged_batch_full_sizes(lq):
+    announce("ragged batch %s" % (RAGGED_DIMS,))
+    ops, bs, Us = [], [], []
+    for i, dd in enumerate(RAGGED_DIMS):
+        U = workload_gauge("clover_24x24x24x48", dims=dd)
+        o = lq.Operator(dd, 0.135, 1.7, ANTIPERIODIC_T, link_recon=12)
+        o.set_gauge(to_dev(U))
+        ops.append(o)
+        Us.append(U)
+        bs.append(gaussian_spinor(dd, 2003 + 10 * i, 4))
+    batch = lq.Batch(ops, [4] * len(ops))
+    xs, st = batch.solve([to_dev(b) for b in bs], lq.SolverParams(tol=1e-10, inner="f16", inner_tol=1e-2,
+                                                                    check_every=10))
+    k = 0
+    for dd, U, b, x in zip(RAGGED_DIMS, Us, bs, xs):
+        xh = to_host(x)
+        F = oracle.clover(dd, U, 1.7, 0.135)
+        for r in range(4):
+            res = _true_residual(dd, U, 0.135, 1.7, xh[r], b[r], F)
+            assert st[k].converged and res <= 1e-10, (dd, r, res)
+            k += 1
+    batch.close()
+    for o in ops:
+        o.close()
