@@ -9,9 +9,10 @@ prepare / reconstruct and the final full-lattice residual included.
 Printed: one JSON line.  `value` is the whole-step dslash throughput: the
 algorithmic bytes of every hopping-term apply the solve performed (links,
 spinor in/out, clover block, per apply) divided by the step time.  The
-`roofline` entry times the dslash kernel alone (FP16, 12-real links) with
-HIP events on the stream it runs on; `cpu_baseline` times the FP64 oracle's
-hopping term on the host cores.  Inputs are generated on the host and
+`roofline` entry times the solver's dominant kernels alone: the FP16
+Schur operator (two fused hopping kernels, 12-real links) replayed from a
+captured graph between HIP events on the stream it runs on; `cpu_baseline`
+times the FP64 oracle's hopping term on the host cores.  Inputs are generated on the host and
 copied to HBM before timing.
 """
 from __future__ import annotations
@@ -41,7 +42,7 @@ def _kernel_source_hash():
 def _traffic_from_profile(kernel_tag: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_dslash_f16_32x32x32x64.txt")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_schur_f16_32x32x32x64.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -49,7 +50,8 @@ def _traffic_from_profile(kernel_tag: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != _kernel_source_hash() or vals.get("kernel") != kernel_tag:
+    # the tag names the kernels without the workgroup size the tuner picked
+    if vals.get("kernel_source_hash") != _kernel_source_hash() or vals.get("kernel") != kernel_tag.split(" (")[0]:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -63,6 +65,89 @@ def _timed(torch, fn):
     out = fn()
     torch.cuda.synchronize()
     return out, 1e3 * (time.perf_counter() - t)
+
+
+def _graph_time_us(torch, fn, reps):
+    """Average duration of fn's launches: reps calls captured in one graph,
+    replayed between two HIP events on the stream the kernels run on."""
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del g
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def _kernels(lq, torch, op, b_d, V, recon, reps):
+    """Per-kernel figures on resident packed fields (no host work inside the
+    timed region): the Schur operator of the solver (two fused hop kernels)
+    in FP16 / FP32 / FP64 at the tuned launch shape, and the plain hopping
+    term (even -> odd) at each workgroup size."""
+    kern = {}
+    roof = None
+    bps_schur = {}
+    for prec in ("f16", "f32", "f64"):
+        fin = lq.Field(op, prec)
+        fout = lq.Field(op, prec)
+        fin.load(b_d.reshape(-1, 4, 3)[: V // 2].contiguous())
+        us = _graph_time_us(torch, lambda: lq.apply_field(op, "schur", fout, fin), reps)
+        b1, f1 = op.traffic(prec, 1, clover=False)
+        b2, f2 = op.traffic(prec, 1, clover=True)
+        # kernel 1: clover-inverse epilogue (+ clover block); kernel 2: clover on y, axpy (+ clover, + y)
+        spinor = {"f16": 52.0, "f32": 96.0, "f64": 192.0}[prec]
+        bps = (b2) + (b2 + spinor)
+        bps_schur[prec] = bps
+        kern["schur_%s_us" % prec] = us
+        kern["schur_%s_GBs" % prec] = bps * (V // 2) / (us * 1e-6) / 1e9
+        kern["schur_%s_block" % prec] = op.get_option("hop_block_" + prec)
+        if prec == "f16":
+            blk = op.get_option("hop_block_f16")
+            gbs = kern["schur_f16_GBs"]
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "traffic": None,
+                    "kernel": "Schur operator, FP16 storage, %d-real links: hop_kernel<f16,%d,clov=inv> + "
+                              "hop_kernel<f16,%d,clov=y,xpay> (%d threads)" % (recon, recon, recon, blk),
+                    "bytes_per_launch": bps * (V // 2), "avg_launch_us": us}
+        tuned_blk = op.get_option("hop_block_" + prec)
+        best = None
+        for blk in (256, 128, 64):
+            op.set_block(prec, blk)
+            t = _graph_time_us(torch, lambda: lq.apply_field(op, "hop_oe", fout, fin), reps)
+            kern["dslash_%s_b%d_us" % (prec, blk)] = t
+            if best is None or t < best[1]:
+                best = (blk, t)
+        op.set_block(prec, tuned_blk)
+        kern["dslash_%s_us" % prec] = best[1]
+        kern["dslash_%s_block" % prec] = best[0]
+        kern["dslash_%s_GBs" % prec] = b1 * (V // 2) / (best[1] * 1e-6) / 1e9
+        kern["dslash_%s_TFLOPs" % prec] = f1 * (V // 2) / (best[1] * 1e-6) / 1e12
+        fin.close()
+        fout.close()
+    # device copy probe (1 GiB read + 1 GiB write per copy)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        c.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kern["copy_probe_GBs"] = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    return kern, roof
 
 
 def _extras(lq, torch):
@@ -176,6 +261,8 @@ def main(argv=None):
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 12-RHS propagator, ragged batch and force measurements")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -217,6 +304,12 @@ def main(argv=None):
         t_tune = time.time()
         tune = op.tune(1)
         print("bench: tuned in %.1f s: %s" % (time.time() - t_tune, json.dumps(tune)), file=sys.stderr, flush=True)
+
+    if args.kernels_only:
+        kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps)
+        print(json.dumps({"kernels": kern, "roofline": roof}), flush=True)
+        op.close()
+        return 0
 
     inner_tol = {"f16": 1e-2, "f32": 1e-5, "f64": 1e-5}[args.inner]
     prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10)
@@ -272,58 +365,9 @@ def main(argv=None):
             tts["speedup_vs_fp64"] = tts["fp64_ms"] / ms_per_step
         print("bench: reference solves %s" % json.dumps(tts), file=sys.stderr, flush=True)
 
-    # dslash kernel alone: hopping term even -> odd on resident packed fields,
-    # at each workgroup size the library offers (the best one is reported)
-    kern = {}
-    roof = None
-    for prec in ("f16", "f32", "f64"):
-        fin = lq.Field(op, prec)
-        fout = lq.Field(op, prec)
-        fin.load(b_d.reshape(-1, 4, 3)[: V // 2].contiguous())
-        tuned_blk = op.get_option("hop_block_" + prec)
-        best = None
-        for blk in (256, 128, 64):
-            op.set_block(prec, blk)
-            for _ in range(3):
-                lq.apply_field(op, "hop_oe", fout, fin)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.kernel_reps):
-                lq.apply_field(op, "hop_oe", fout, fin)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.kernel_reps
-            kern["dslash_%s_b%d_us" % (prec, blk)] = 1e3 * ms
-            if best is None or ms < best[1]:
-                best = (blk, ms)
-        op.set_block(prec, tuned_blk)
-        blk, ms = best
-        bps, fps = op.traffic(prec, 1, clover=False)
-        gbs = bps * (V // 2) / (ms * 1e-3) / 1e9
-        kern["dslash_%s_us" % prec] = 1e3 * ms
-        kern["dslash_%s_block" % prec] = blk
-        kern["dslash_%s_GBs" % prec] = gbs
-        kern["dslash_%s_TFLOPs" % prec] = fps * (V // 2) / (ms * 1e-3) / 1e12
-        if prec == args.inner or (prec == "f16" and roof is None):
-            tag = "hop_kernel<%s,%d,dag=0,clov=0,xpay=0,red=0,%d>" % (prec, 18 if prec == "f64" else args.recon, blk)
-            traffic = _traffic_from_profile(tag) if prec == "f16" else None
-            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                    "traffic": traffic, "kernel": tag, "bytes_per_launch": bps * (V // 2),
-                    "avg_launch_us": 1e3 * ms}
-        fin.close()
-        fout.close()
-    # device copy probe (1 GiB read + 1 GiB write)
-    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    c = torch.empty_like(a)
-    c.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        c.copy_(a)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    kern["copy_probe_GBs"] = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, c
+    kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps)
+    if roof is not None:
+        roof["traffic"] = _traffic_from_profile(roof["kernel"])
     print("bench: kernels %s" % json.dumps(kern), file=sys.stderr, flush=True)
 
     op.close()
