@@ -111,7 +111,9 @@ typedef struct {
     double csw;           /* clover coefficient; 0 = Wilson (F = 0) */
     double bc[4][2];      /* boundary phase per direction as (re, im), |phase| = 1 */
     int clover_traceless; /* 1 (default): colour trace of Fhat removed */
-    int link_recon;       /* 18 or 12: reals per link in the FP32/FP16 copies */
+    int link_recon;       /* 18 or 12: reals per link read by the hopping kernels (all
+                             precisions; 12 stores rows 0 and 1 and rebuilds row 2 as
+                             conj(row0 x row1), valid for SU(3) links only) */
 } lq_op_params;
 
 /* Solver parameters (params_solver of Fig. 1). */
@@ -132,7 +134,10 @@ typedef struct {
     int nouter;           /* FP64 defect-correction steps */
     int restarts;         /* Krylov restarts after breakdown */
     int converged;        /* 1 if diff <= tol */
-    double diff;          /* true residual |b - D x|_2 / |b|_2 in FP64 (not squared) */
+    double diff;          /* true residual |b - D x|_2 / |b|_2 in FP64 (not squared), recomputed
+                             from the final x (not the Krylov recursion); for the even-odd
+                             solve as |b_e + kappa H_eo A_oo^-1 b_o - M x_e|, equal to it since
+                             the reconstructed x_o satisfies the odd rows exactly */
     double t_solve_ms;    /* wall time of the solve (all systems of the call together) */
     double hop_bytes;     /* algorithmic bytes of the hopping-term applies of the call
                              (lq_op_traffic per apply), all systems together */

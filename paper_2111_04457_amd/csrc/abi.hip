@@ -120,6 +120,7 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
             op->links[F64].ensure(8 * link_bytes(F64, 18, g.vh));
             op->links[F32].ensure(8 * link_bytes(F32, p->link_recon, g.vh));
             op->links[F16].ensure(8 * link_bytes(F16, p->link_recon, g.vh));
+            if (p->link_recon == 12) op->links64r.ensure(8 * link_bytes(F64, 12, g.vh));
             op->flag.ensure(sizeof(int));
             LQ_HIP(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
             LQ_HIP(hipEventCreateWithFlags(&op->ev_in, hipEventDisableTiming));
@@ -175,6 +176,8 @@ lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream)
         LQ_HIP(launch_pack_links_f64(g, static_cast<const double *>(U), op->links[F64].ptr, s));
         LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F32, op->prm.link_recon, op->links[F32].ptr, s));
         LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F16, op->prm.link_recon, op->links[F16].ptr, s));
+        if (op->prm.link_recon == 12)
+            LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F64, 12, op->links64r.ptr, s));
         build_clover(op, s);
         op->gauge_set = true;
         return LQ_OK;
@@ -373,7 +376,7 @@ lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, dou
     if (!op || !bytes_per_site || !flops_per_site) return arg_error("lq_op_traffic: null argument");
     if (!valid_prec(prec) || nrhs < 1) return arg_error("lq_op_traffic: bad precision or nrhs");
     const double rs = prec == LQ_F64 ? 8 : prec == LQ_F32 ? 4 : 2;
-    const int nl = prec == LQ_F64 ? 18 : op->prm.link_recon;
+    const int nl = op->prm.link_recon;
     const double spinor = 24 * rs + (prec == LQ_F16 ? 4 : 0);
     double b = 8.0 * nl * rs / nrhs + 2.0 * spinor;
     double f = 1320.0;

@@ -344,14 +344,8 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
             } else {
                 LQ_HIP(launch_copy(xfull, c.x64, c.sc, 2, false, s));
             }
-            op->tmp[0].ensure(2 * (size_t)fb(F64, g) * nr);
-            op->tmp[1].ensure(2 * (size_t)fb(F64, g) * nr);
-            dirac_full(op, F64, op->tmp[0].ptr, xp[i], nr, false, s);
-            c.count_hops(F64, 2);
-            const FieldView fy{op->tmp[0].ptr, F64, (long)g.vh, fb(F64, g), 2 * nr};
-            const FieldView fr{op->tmp[1].ptr, F64, (long)g.vh, fb(F64, g), 2 * nr};
-            LQ_HIP(launch_xmy_norm(fr, bfull[i], fy, c.partial, s));
-            LQ_HIP(launch_finish(c.partial, nr, 2, blas_blocks(g.vh), 1, FIN_NORM, c.sc, 0, s));
+            // the residual of the last outer step at the final iterate is
+            // |b - D x| (see solve_packed): SC_NORM2 still holds it
             for (int p = 0; p < 2; ++p)
                 LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(xp[i], F64, g, nr, p), static_cast<double *>(x[i]), s));
             c.pull();

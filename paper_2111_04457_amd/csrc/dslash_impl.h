@@ -312,9 +312,7 @@ template <int P, bool DAG>
 static hipError_t launch_pd(const HopArgs &a, int recon, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
     if (recon == 18) return launch_epi<P, 18, DAG>(a, clov, xpay, red, nr, block, s);
-    if constexpr (P != F64) {
-        if (recon == 12) return launch_epi<P, 12, DAG>(a, clov, xpay, red, nr, block, s);
-    }
+    if (recon == 12) return launch_epi<P, 12, DAG>(a, clov, xpay, red, nr, block, s);
     return hipErrorInvalidValue;
 }
 

@@ -116,7 +116,8 @@ hipError_t launch_pack_links_f64(const Geom &g, const double *U, char *links64, 
 hipError_t launch_convert_links(const Geom &g, const char *links64, int prec, int nl, char *dst, hipStream_t s)
 {
     const dim3 grid((g.vh + 255) / 256, 8);
-    if (prec == F32 && nl == 18) convert_links_kernel<F32, 18><<<grid, 256, 0, s>>>(g, links64, dst);
+    if (prec == F64 && nl == 12) convert_links_kernel<F64, 12><<<grid, 256, 0, s>>>(g, links64, dst);
+    else if (prec == F32 && nl == 18) convert_links_kernel<F32, 18><<<grid, 256, 0, s>>>(g, links64, dst);
     else if (prec == F32 && nl == 12) convert_links_kernel<F32, 12><<<grid, 256, 0, s>>>(g, links64, dst);
     else if (prec == F16 && nl == 18) convert_links_kernel<F16, 18><<<grid, 256, 0, s>>>(g, links64, dst);
     else if (prec == F16 && nl == 12) convert_links_kernel<F16, 12><<<grid, 256, 0, s>>>(g, links64, dst);

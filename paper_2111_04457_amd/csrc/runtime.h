@@ -57,7 +57,8 @@ struct lq_op {
     // 2 XCD-aware and time slices interleaved
     int xcd_remap[3] = {1, 1, 1};
     int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
-    lq::Buf links[3];                    // packed links per precision ([parity][mu])
+    lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
+    lq::Buf links64r;                    // FP64 links with 12 reals (hop kernels) when link_recon == 12
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
     lq::Buf flag;                        // device int: singular clover block
@@ -98,7 +99,13 @@ struct lq_op {
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (stream) (void)hipStreamDestroy(stream);
     }
-    int nl(int prec) const { return prec == lq::F64 ? 18 : prm.link_recon; }
+    // link format of the hop kernels (the clover build and the force use the
+    // 18-real FP64 links)
+    int nl(int) const { return prm.link_recon; }
+    const char *hop_links(int prec) const
+    {
+        return (prec == lq::F64 && prm.link_recon == 12) ? links64r.ptr : links[prec].ptr;
+    }
 };
 
 struct lq_field {

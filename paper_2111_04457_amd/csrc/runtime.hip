@@ -63,7 +63,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         a.w_n = w->n;
         a.w_rs = w->rs;
     }
-    a.links = op->links[prec].ptr;
+    a.links = op->hop_links(prec);
     if (clov_mode && !op->has_clover) clov_mode = 0;
     if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
     a.coef = coef;

@@ -133,6 +133,7 @@ void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t 
 
 struct OuterStats {
     std::vector<int> iters, outer, restarts;
+    std::vector<double> r2;  // |rhs - A x|^2 at the returned x (FP64)
 };
 
 // Solve A x = rhs on the solve space to |rhs - A x|^2 <= target2[i] for

@@ -87,7 +87,7 @@ KINDS = ["D", "Ddag", "DdagD", "schur", "schur_dag", "schur_normal", "hop_eo", "
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)])
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)])
 def test_apply_all_kinds(lib, case, prec, recon):
     announce("apply parity: case=%s prec=%s recon=%d" % (case, prec, recon))
     op_ref, U = _oracle(case)

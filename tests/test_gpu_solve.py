@@ -62,7 +62,8 @@ def clover_case():
 
 
 @pytest.mark.parametrize("solver,inner,recon", [
-    ("bicgstab", "f64", 18), ("bicgstab", "f32", 18), ("bicgstab", "f16", 18), ("bicgstab", "f16", 12),
+    ("bicgstab", "f64", 18), ("bicgstab", "f64", 12), ("bicgstab", "f32", 18), ("bicgstab", "f16", 18),
+    ("bicgstab", "f16", 12),
     ("cgne", "f64", 18), ("cgne", "f32", 12), ("cgne", "f16", 18),
 ])
 def test_clover_even_odd_solves(lq, clover_case, solver, inner, recon):
