@@ -239,9 +239,12 @@ lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs
  * lq_batch_solve solves D_i x_i = b_i for every lattice with the same
  * solver parameters: b[i], x[i] are device complex128 full fields
  * [nrhs[i]][V_i][4][3]; stats receives sum(nrhs) entries in batch order.
- * Every chunk of inner iterations of all lattices is one hipGraph launch
- * (one branch per lattice).  Results equal those of separate lq_solve calls
- * bit for bit. */
+ * Each lattice's solve runs on its operator's stream from a host thread of
+ * its own, so the lattices' kernels overlap on the GPU; each is the same
+ * solve as lq_solve (its inner iterations replayed from hipGraphs), and the
+ * results equal those of separate lq_solve calls bit for bit.  On failure
+ * the status and message of the first failing lattice in batch order are
+ * returned (the other lattices' results are then unspecified). */
 lq_status lq_batch_create(lq_op *const *ops, int nops, const int *nrhs, lq_batch **out);
 lq_status lq_batch_solve(lq_batch *batch, const lq_solver_params *sp, void *const *x, const void *const *b,
                          lq_solve_stats *stats, void *stream);
