@@ -35,7 +35,7 @@ struct HopArgs {
     const char *links;   // packed links [parity][mu] (vh sites each)
     const char *clov;    // packed clover blocks of the output parity (vh sites)
     double coef;
-    double *partial;     // per-block partial sums (reduction epilogue) or null
+    double *partial;     // per-wavefront partial sums (reduction epilogue) or null
     const char *w;       // second operand of a fused dot product, or null
     long w_n;
     long w_rs;
@@ -53,7 +53,10 @@ struct HopArgs {
 
 // Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;
 // dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result;
-// xpay: add y; red: 0 none, 1 |out|^2, 2 <w, out> per right-hand side.
+// xpay: add y; red: 0 none, 2 <w, out>, 3 <w, out> and |out|^2 per
+// right-hand side (of the values as stored), written as one partial per
+// 64-site wavefront to partial[((rhs * nw) + cb / 64) * K + k], K = 2 or 3,
+// nw = ceil(vh / 64); red needs xpay and one right-hand side per thread.
 // nr: right-hand sides per thread (1, or 2 without reduction);
 // block: threads per workgroup (64, 128 or 256).
 hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int nr, int block,

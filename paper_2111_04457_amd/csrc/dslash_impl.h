@@ -183,9 +183,9 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
     }
     const int cb = sblk * NT + threadIdx.x;
     const bool valid = cb < a.g.vh && nr > 0;
-    double red0[NR], red1[NR];
+    double red0[NR], red1[NR], red2[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) red0[r] = red1[r] = 0.0;
+    for (int r = 0; r < NR; ++r) red0[r] = red1[r] = red2[r] = 0.0;
     if (valid) {
         const char *in = a.in + rhs0 * a.in_rs;
         int c[4];
@@ -216,39 +216,40 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
                 }
                 if constexpr (CLOV == 2) clover_mul_raw(craw, res);
                 store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
-                if constexpr (RED == 1) {
-                    // the norm of what was stored (FP16: of the rounded values)
-                    if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
-#pragma unroll
-                    for (int i = 0; i < 12; ++i) red0[r] += (double)norm2(res.c[i]);
-                } else if constexpr (RED == 2) {
-                    if constexpr (PT<P>::scaled) res = load_spinor<P>(a.out + rhs * a.out_rs, cb, a.out_n);
+                if constexpr (RED != 0) {
+                    // <w, out> (and |out|^2) of the values as stored
+                    const Spinor<R> sv = as_stored<P>(res);
                     const Spinor<R> wv = load_spinor<P>(a.w + rhs * a.w_rs, cb, a.w_n);
 #pragma unroll
                     for (int i = 0; i < 12; ++i) {
-                        const cx<R> q = cmulc(wv.c[i], res.c[i]);
+                        const cx<R> q = cmulc(wv.c[i], sv.c[i]);
                         red0[r] += (double)q.re;
                         red1[r] += (double)q.im;
+                        if constexpr (RED == 3) red2[r] += (double)norm2(sv.c[i]);
                     }
                 }
             }
         }
     }
     if constexpr (RED != 0) {
-        __shared__ double lds[NT / 64];
+        // one partial per wavefront of 64 consecutive sites, indexed by its
+        // first site: the sums depend neither on the workgroup size nor on
+        // the order in which workgroups run
+        constexpr int K = RED == 2 ? 2 : 3;
+        const long nw = ((long)a.g.vh + 63) / 64;
+        const long wave = ((long)sblk * NT + (threadIdx.x & ~63)) / 64;
+        const bool lead = (threadIdx.x & 63) == 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
-                const long slot = (long)(rhs0 + r) * nbs + sblk;
-                const double s0 = block_sum<NT>(red0[r], lds);
-                if constexpr (RED == 1) {
-                    if (threadIdx.x == 0) a.partial[slot] = s0;
-                } else {
-                    const double s1 = block_sum<NT>(red1[r], lds);
-                    if (threadIdx.x == 0) {
-                        a.partial[2 * slot] = s0;
-                        a.partial[2 * slot + 1] = s1;
-                    }
+                const double s0 = wave_sum(red0[r]);
+                const double s1 = wave_sum(red1[r]);
+                const double s2 = RED == 3 ? wave_sum(red2[r]) : 0.0;
+                if (lead && wave < nw) {
+                    double *o = a.partial + ((long)(rhs0 + r) * nw + wave) * K;
+                    o[0] = s0;
+                    o[1] = s1;
+                    if constexpr (K == 3) o[2] = s2;
                 }
             }
         }
@@ -298,11 +299,11 @@ static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int
         if (clov == 2) return launch_nr<P, NL, DAG, 2, false, 0>(a, nr, block, s);
     } else if (xpay) {
         if (clov == 0 && red == 0) return launch_nr<P, NL, DAG, 0, true, 0>(a, nr, block, s);
-        if (clov == 0 && red == 1) return launch_nr<P, NL, DAG, 0, true, 1>(a, nr, block, s);
         if (clov == 0 && red == 2) return launch_nr<P, NL, DAG, 0, true, 2>(a, nr, block, s);
+        if (clov == 0 && red == 3) return launch_nr<P, NL, DAG, 0, true, 3>(a, nr, block, s);
         if (clov == 1 && red == 0) return launch_nr<P, NL, DAG, 1, true, 0>(a, nr, block, s);
-        if (clov == 1 && red == 1) return launch_nr<P, NL, DAG, 1, true, 1>(a, nr, block, s);
         if (clov == 1 && red == 2) return launch_nr<P, NL, DAG, 1, true, 2>(a, nr, block, s);
+        if (clov == 1 && red == 3) return launch_nr<P, NL, DAG, 1, true, 3>(a, nr, block, s);
         if (clov == 2 && red == 0) return launch_nr<P, NL, DAG, 2, true, 0>(a, nr, block, s);
     }
     return hipErrorInvalidValue;

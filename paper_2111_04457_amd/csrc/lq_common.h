@@ -210,6 +210,30 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, lo
     store_planes<S, 24, NTS>(base, s, n, raw);
 }
 
+// The values load_spinor returns after store_spinor(v): v itself for FP64
+// and FP32 storage, v rounded to the scaled binary16 format otherwise
+// (the same operations as the store and the load).
+template <int P>
+__device__ __forceinline__ Spinor<typename PT<P>::R> as_stored(const Spinor<typename PT<P>::R> &v)
+{
+    if constexpr (!PT<P>::scaled) {
+        return v;
+    } else {
+        using S = typename PT<P>::S;
+        using R = typename PT<P>::R;
+        R m = 0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) m = fmaxf(m, fmaxf(fabsf(v.c[i].re), fabsf(v.c[i].im)));
+        const R inv = m > 0 ? (R)1 / m : (R)0;
+        const float sc = m;
+        Spinor<R> o;
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            o.c[i] = cx<R>{(R)(S)(v.c[i].re * inv) * sc, (R)(S)(v.c[i].im * inv) * sc};
+        return o;
+    }
+}
+
 // ------------------------------------------------------------- geometry --
 
 // Lattice geometry of one checkerboarded lattice, passed by value.

@@ -136,7 +136,8 @@ inline FieldView full_parity_view(char *base, int prec, const Geom &g, int nrhs,
 
 // Hopping term on packed fields: out = epilogue(coef * H_{p_out,1-p_out} in).
 // clov_mode: 0 none, 1 clover on y, 2 clover on the result; inv selects A^-1.
-// red: 0 none, 1 per-rhs |out|^2, 2 per-rhs <w, out> partials into op->partial.
+// red: 0 none, 2 per-rhs <w, out>, 3 <w, out> and |out|^2, as per-wavefront
+// partials into op->partial (see launch_hop).
 void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, bool dag, int clov_mode,
          bool inv, const FieldView *y, double coef, int red, const FieldView *w, hipStream_t s);
 
@@ -150,8 +151,9 @@ void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, co
 bool kind_is_full(lq_kind k);
 
 // Schur operator M (or M^dag) on packed even fields; t: odd scratch field.
+// red / w: reduction fused into the second kernel (as for hop).
 void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, bool dag,
-           hipStream_t s);
+           hipStream_t s, int red = 0, const FieldView *w = nullptr);
 // Full-lattice D (or D^dag) on full packed fields of nrhs systems.
 void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool dag, hipStream_t s);
 

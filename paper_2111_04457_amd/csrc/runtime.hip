@@ -83,7 +83,8 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         }
     }
     if (red) {
-        op->partial.ensure((size_t)hop_blocks(g.vh, block) * in.nrhs * 2 * sizeof(double));
+        // one partial per 64-site wavefront and right-hand side, K <= 3
+        op->partial.ensure((size_t)((g.vh + 63) / 64) * in.nrhs * 3 * sizeof(double));
         a.partial = reinterpret_cast<double *>(op->partial.ptr);
     }
     const int nr = (red == 0 && in.nrhs > 1) ? op->rhs_per_thread[prec] : 1;
@@ -106,11 +107,11 @@ void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, co
 // Schur operator M = A_ee - kappa^2 H_eo A_oo^-1 H_oe (dag: M^dag) on packed
 // even fields; t is an odd scratch field.
 void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, bool dag,
-                  hipStream_t s)
+           hipStream_t s, int red, const FieldView *w)
 {
     const double k = op->prm.kappa;
     hop(op, prec, t, in, 1, dag, 2, true, nullptr, 1.0, 0, nullptr, s);
-    hop(op, prec, out, t, 0, dag, 1, false, &in, -k * k, 0, nullptr, s);
+    hop(op, prec, out, t, 0, dag, 1, false, &in, -k * k, red, w, s);
 }
 
 // Full-lattice D (or D^dag): out_p = A_pp in_p - kappa H_{p,1-p} in_{1-p}.

@@ -43,6 +43,10 @@ struct SolveCtx {
     // out = M in (dag: M^dag), in the precision of the views
     void apply(const FieldView &out, const FieldView &in, bool dag);
     void reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin);
+    // out = M in with <w, out> (mode RED_DOT) or <w, out>, |out|^2
+    // (RED_DOT_NORM) reduced and finished with op_fin; fused into the
+    // operator's second kernel on the even-odd system
+    void apply_reduce_finish(const FieldView &out, const FieldView &in, const FieldView &w, int mode, int op_fin);
     void finish(int K, int op_fin, long n);
     void pull();
     void push();

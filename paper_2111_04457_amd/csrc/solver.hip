@@ -51,11 +51,9 @@ void bicg_init(SolveCtx &c)
 
 void bicg_iter(SolveCtx &c)
 {
-    c.apply(c.iv, c.ip, false);
-    c.reduce_finish(c.irhat, c.iv, RED_DOT, FIN_BICG_ALPHA);
+    c.apply_reduce_finish(c.iv, c.ip, c.irhat, RED_DOT, FIN_BICG_ALPHA);  // v = M p, <rhat, v>
     LQ_HIP(launch_bicg_s(c.is, c.ir, c.iv, c.sc, c.sps, c.s));
-    c.apply(c.it, c.is, false);
-    c.reduce_finish(c.is, c.it, RED_DOT_NORM, FIN_BICG_OMEGA);
+    c.apply_reduce_finish(c.it, c.is, c.is, RED_DOT_NORM, FIN_BICG_OMEGA);  // t = M s, <s, t>, |t|^2
     LQ_HIP(launch_bicg_xr(c.ix, c.ir, c.ip, c.is, c.it, c.irhat, c.sc, c.sps, c.partial, c.s));
     c.finish(3, FIN_BICG_RHO, c.ir.n);
     LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));
@@ -189,6 +187,30 @@ void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
     }
     op->hop_mask = nullptr;
     if (!masked) count_hops(p, 2);
+}
+
+void SolveCtx::apply_reduce_finish(const FieldView &out, const FieldView &in, const FieldView &w, int mode,
+                                   int op_fin)
+{
+    if (!eo) {
+        apply(out, in, false);
+        reduce_finish(w, out, mode, op_fin);
+        return;
+    }
+    const int p = in.prec;
+    const int red = mode == RED_DOT ? 2 : 3;
+    op->hop_mask = masked ? sc : nullptr;
+    try {
+        schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, false, s, red, &w);
+    } catch (...) {
+        op->hop_mask = nullptr;
+        throw;
+    }
+    op->hop_mask = nullptr;
+    if (!masked) count_hops(p, 2);
+    // partials: one per 64-site wavefront of the even sites, per system
+    const int nw = (op->g.vh + 63) / 64;
+    LQ_HIP(launch_finish(partial, nsys, 1, nw, red == 2 ? 2 : 3, op_fin, sc, 1e-30, s));
 }
 
 void SolveCtx::reduce_finish(const FieldView &x, const FieldView &y, int mode, int op_fin)
