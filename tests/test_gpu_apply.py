@@ -32,6 +32,8 @@ CASES = {
     "wilson_6x4x6x10": ((6, 4, 6, 10), 0.13, 0.0, "haar"),
     "clover_6x4x6x10": ((6, 4, 6, 10), 0.13, 1.7, "exp"),
     "clover_8x8x4x12": ((8, 8, 4, 12), 0.1355, 1.0, "exp"),
+    # extent 2 in x and z: x+mu and x-mu are the same site, both terms summed
+    "clover_2x4x2x6": ((2, 4, 2, 6), 0.12, 1.3, "exp"),
 }
 
 
