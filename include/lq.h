@@ -165,7 +165,8 @@ void lq_op_destroy(lq_op *op);
 /* Set the gauge field (set_config of Fig. 1).  U: device complex128 in the
  * gauge layout.  Packs FP64, FP32 and FP16 copies (even/odd split, SoA),
  * builds A = 1 + F and A_oo^-1 in FP64 and down-converts them.
- * LQ_ERR_SINGULAR if a clover block is not invertible. */
+ * LQ_ERR_SINGULAR if a clover block of an odd site is not invertible
+ * (A_oo is the block the even-odd solve inverts; A_ee is only applied). */
 lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream);
 
 /* Change kappa, csw and the boundary phases; rebuilds the clover term from

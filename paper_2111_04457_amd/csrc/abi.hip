@@ -150,18 +150,25 @@ static void build_clover(lq_op *op, hipStream_t s)
         op->clov[p].ensure(2 * clover_bytes(p, g.vh));
         op->clovinv[p].ensure(2 * clover_bytes(p, g.vh));
     }
-    LQ_HIP(launch_clover_build(g, op->links[F64].ptr, op->prm.csw, op->prm.kappa, op->prm.clover_traceless,
-                               op->clov[F64].ptr, s));
+    {
+        Buf fbuf;  // the field strengths, freed once the blocks are built
+        fbuf.ensure(clover_fbuf_bytes(g.vh));
+        LQ_HIP(launch_clover_build(g, op->links[F64].ptr, op->prm.csw, op->prm.kappa, op->prm.clover_traceless,
+                                   fbuf.ptr, op->clov[F64].ptr, s));
+        LQ_HIP(hipStreamSynchronize(s));
+    }
+    // only A_oo is inverted: the even-odd operators use A_ee and A_oo^-1
     LQ_HIP(hipMemsetAsync(op->flag.ptr, 0, sizeof(int), s));
-    LQ_HIP(launch_clover_invert(g, op->clov[F64].ptr, op->clovinv[F64].ptr, reinterpret_cast<int *>(op->flag.ptr), s));
+    LQ_HIP(launch_clover_invert(g, 1, op->clov[F64].ptr, op->clovinv[F64].ptr, reinterpret_cast<int *>(op->flag.ptr),
+                                s));
     for (int p = F32; p <= F16; ++p) {
         LQ_HIP(launch_convert_clover(g, op->clov[F64].ptr, p, op->clov[p].ptr, s));
-        LQ_HIP(launch_convert_clover(g, op->clovinv[F64].ptr, p, op->clovinv[p].ptr, s));
+        LQ_HIP(launch_convert_clover(g, op->clovinv[F64].ptr, p, op->clovinv[p].ptr, s, 1, 1));
     }
     int flag = 0;
     LQ_HIP(hipMemcpyAsync(&flag, op->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     LQ_HIP(hipStreamSynchronize(s));
-    if (flag) throw Failure{LQ_ERR_SINGULAR, "a clover block A = 1 + F is singular"};
+    if (flag) throw Failure{LQ_ERR_SINGULAR, "a clover block A_oo = 1 + F on an odd site is singular"};
 }
 
 lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream)

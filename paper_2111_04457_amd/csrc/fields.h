@@ -32,14 +32,18 @@ hipError_t launch_convert_links(const Geom &g, const char *links64, int prec, in
 
 // Clover blocks A = 1 + F in FP64 (72 reals per site: two packed 6x6
 // Hermitian blocks) for both parities, [parity][planes over vh], built from
-// the packed FP64 links.
+// the packed FP64 links; fbuf is scratch of clover_fbuf_bytes(vh) bytes
+// (the six field strengths of every site).
 hipError_t launch_clover_build(const Geom &g, const char *links64, double csw, double kappa, int traceless,
-                               char *clov64, hipStream_t s);
-// Per-block inverse by Gauss-Jordan with partial pivoting (FP64); sets
-// *flag nonzero if a block is singular.
-hipError_t launch_clover_invert(const Geom &g, const char *clov64, char *inv64, int *flag, hipStream_t s);
-// FP64 packed clover field (both parities) -> precision prec.
-hipError_t launch_convert_clover(const Geom &g, const char *clov64, int prec, char *dst, hipStream_t s);
+                               char *fbuf, char *clov64, hipStream_t s);
+inline size_t clover_fbuf_bytes(long vh) { return (size_t)2 * 6 * 18 * 8 * vh; }
+// Per-block inverse of the blocks of parity p by Gauss-Jordan with partial
+// pivoting (FP64), into parity p of inv64; sets *flag nonzero if a block is
+// singular.
+hipError_t launch_clover_invert(const Geom &g, int p, const char *clov64, char *inv64, int *flag, hipStream_t s);
+// FP64 packed clover field -> precision prec, parities p0 .. p0 + np - 1.
+hipError_t launch_convert_clover(const Geom &g, const char *clov64, int prec, char *dst, hipStream_t s, int p0 = 0,
+                                 int np = 2);
 // Site-local y = C x on one parity with packed clover C of that parity.
 hipError_t launch_clover_apply(const Geom &g, const char *clov, FieldView out, FieldView in, hipStream_t s);
 
