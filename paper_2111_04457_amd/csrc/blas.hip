@@ -78,36 +78,37 @@ hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hi
     return hipGetLastError();
 }
 
-// One workgroup per system: sum K values over sps * nblocks partials in a
-// fixed order, then update the system's scalars.
-__global__ __launch_bounds__(BT) void finish_kernel(const double *partial, int sps, int nblocks, int K, int op,
+// One workgroup of FT threads per system: sum K values over sps * nblocks
+// partials in a fixed order, then update the system's scalars.
+constexpr int FT = 1024;
+__global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int sps, int nblocks, int K, int op,
                                                    double *scal, double eps)
 {
     const int sys = blockIdx.x;
     const long cnt = (long)sps * nblocks;
     const double *p = partial + (long)sys * cnt * K;
     double v[3] = {0, 0, 0};
-    // each thread adds its partials j = tid, tid + BT, ... in that order;
+    // each thread adds its partials j = tid, tid + FT, ... in that order;
     // the loads of 8 of them are issued together
     constexpr int U = 8;
-    for (long j0 = threadIdx.x; j0 < cnt; j0 += U * BT) {
+    for (long j0 = threadIdx.x; j0 < cnt; j0 += U * FT) {
         double t[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long j = j0 + (long)u * BT;
+            const long j = j0 + (long)u * FT;
 #pragma unroll
             for (int k = 0; k < 3; ++k) t[u][k] = (j < cnt && k < K) ? p[j * K + k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j0 + (long)u * BT < cnt)
+            if (j0 + (long)u * FT < cnt)
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
                     if (k < K) v[k] += t[u][k];
     }
-    __shared__ double lds[BT / 64];
+    __shared__ double lds[FT / 64];
     double tot[3];
-    for (int k = 0; k < 3; ++k) tot[k] = block_sum<BT>(v[k], lds);
+    for (int k = 0; k < 3; ++k) tot[k] = block_sum<FT>(v[k], lds);
     if (threadIdx.x != 0) return;
     double *sc = scal + (long)sys * NSC;
     const bool fz = frozen(sc);
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(BT) void finish_kernel(const double *partial, int s
 hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,
                          double eps, hipStream_t s)
 {
-    finish_kernel<<<nsys, BT, 0, s>>>(partial, sps, nblocks, K, op, sc, eps);
+    finish_kernel<<<nsys, FT, 0, s>>>(partial, sps, nblocks, K, op, sc, eps);
     return hipGetLastError();
 }
 
