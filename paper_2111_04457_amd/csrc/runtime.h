@@ -57,6 +57,7 @@ struct lq_op {
     // 2 XCD-aware and time slices interleaved
     int xcd_remap[3] = {1, 1, 1};
     int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
+    int inner_hint = 0;                  // iterations the last inner solve needed (first chunk length)
     lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
     lq::Buf links64r;                    // FP64 links with 12 reals (hop kernels) when link_recon == 12
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])

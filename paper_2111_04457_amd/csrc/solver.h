@@ -60,9 +60,10 @@ struct SolveCtx {
 // the scalars back after each chunk; a system that converges inside a chunk
 // is masked for the rest of it, so the lengths change only how many masked
 // (nearly empty) iterations are launched, never a result.  The first chunk
-// is the iteration count of the previous inner solve of the same outer loop
-// (every inner solve reduces its residual by about the same factor), then
-// one short chunk, then check_every.
+// is the iteration count of the previous inner solve (of the same outer
+// loop, or of the operator's previous solve: every inner solve reduces its
+// residual by about the same factor), then one short chunk, then
+// check_every.
 struct ChunkPlan {
     int hint = 0;   // iterations the previous inner solve needed (0: none yet)
     int every = 10;

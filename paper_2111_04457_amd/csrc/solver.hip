@@ -302,6 +302,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     os.restarts.assign(nsys, 0);
     int total_inner = 0;
     ChunkPlan plan;
+    plan.hint = c.op->inner_hint;  // from the operator's previous solve
     for (int step = 0; step <= sp.max_outer; ++step) {
         // r = rhs - A x, |r|^2 (FIN_NORM also flags systems below target)
         c.pull();
@@ -357,6 +358,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         // x += |r| e
         LQ_HIP(launch_accum(c.x64, c.ix, c.sc, c.sps, true, c.s));
     }
+    if (plan.hint > 0) c.op->inner_hint = plan.hint;
     return os;
 }
 
