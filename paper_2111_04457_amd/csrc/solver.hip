@@ -303,11 +303,12 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     int total_inner = 0;
     ChunkPlan plan;
     plan.hint = c.op->inner_hint;  // from the operator's previous solve
+    // the outer target of each system (FIN_NORM flags systems below it)
+    c.pull();
+    for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
+    c.push();
     for (int step = 0; step <= sp.max_outer; ++step) {
-        // r = rhs - A x, |r|^2 (FIN_NORM also flags systems below target)
-        c.pull();
-        for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
-        c.push();
+        // r = rhs - A x, |r|^2
         if (normal) {
             c.apply(c.t64, c.x64, false);
             c.apply(c.y64, c.t64, true);
