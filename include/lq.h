@@ -266,11 +266,15 @@ lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, siz
 
 /* Pseudofermion action and force (molecular-dynamics force of the gauge-field
  * generation the paper's Sec. 2 describes, whose solves are the bottleneck):
- *   variant 0 (even-odd):  S = phi^dag (M^dag M)^-1 phi,  M = 1 - kappa^2 H_eo H_oe,
+ *   variant 0 (even-odd):  S = phi^dag (M^dag M)^-1 phi,  M = A_ee - kappa^2 H_eo A_oo^-1 H_oe,
  *                          phi a device complex128 parity field [V/2][4][3] on even sites;
  *   variant 1 (full):      S = phi^dag (D^dag D)^-1 phi,  phi a full field [V][4][3].
- * The solve runs with sp (FP64 defect correction around sp->inner); the force
- * kernel computes in force_prec (LQ_F64 or LQ_F32).  Outputs (device
+ * Wilson (csw = 0, A = 1) and Wilson-clover operators (eq. (1)); the clover
+ * term enters through the derivative of its leaves Q_{mu nu}(x), traceless or
+ * not as the operator was built.
+ * The solve runs with sp (FP64 defect correction around sp->inner); the
+ * hopping-term force kernel computes in force_prec (LQ_F64 or LQ_F32), the
+ * clover part always in FP64 (on the FP64 solution).  Outputs (device
  * complex128, each may be NULL):
  *   dSdU  [V][4][3][3]  the gradient of S with respect to the link entries,
  *                       dS = Re sum conj(dSdU) dU, i.e. M^dag for the matrix M
@@ -278,7 +282,8 @@ lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, siz
  *   G     [V][4][3][3]  the su(3) force -TA(U M), so that dS/de along
  *                       U -> exp(e X) U equals sum Re tr(G^dag X);
  *   X_out               X = (M^dag M)^-1 phi (layout of phi).
- * *S receives the action.  Wilson operator only (csw = 0, else LQ_ERR_ARG). */
+ * *S receives the action.  With clover, a workspace of 6 V 144 bytes stays
+ * with the operator (freed with it). */
 lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
                       void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream);
 

@@ -249,7 +249,7 @@ def pf_force(op: Operator, phi: torch.Tensor, params: SolverParams | None = None
 
 
 class PseudofermionAction(torch.autograd.Function):
-    """S(U, phi) = phi^dag (M^dag M)^-1 phi (Wilson, even-odd) or
+    """S(U, phi) = phi^dag (M^dag M)^-1 phi (Wilson or Wilson-clover, even-odd) or
     phi^dag (D^dag D)^-1 phi (variant "full") as a differentiable function.
 
     The forward pass loads U into the operator and runs one solve and the

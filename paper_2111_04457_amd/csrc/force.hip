@@ -15,11 +15,30 @@
 // The kernel writes the gradient M^dag (dS = Re sum conj(M^dag) dU) and the
 // su(3) force G = -TA(U M), where
 // TA(B) = (B - B^dag)/2 - tr(B - B^dag)/6.
+//
+// Clover operator (A = 1 + F, F = -c_sw kappa sum_{mu<nu} gamma_mu gamma_nu
+// (x) Fhat_{mu nu}, Fhat = (Q - Q^dag)/8 from the four counter-clockwise
+// leaves, trace removed if traceless): even-odd with
+// M = A_ee - kappa^2 H_eo A_oo^-1 H_oe, Z = A_oo^-1 H_oe X, W = A_oo^-1 H_eo^dag Y,
+//   dS = 2 kappa^2 Re[Y^dag dH_eo Z + W^dag dH_oe X] - 2 Re[Y^dag dA_ee X + kappa^2 W^dag dA_oo Z];
+// full lattice: dS = 2 kappa Re[Y^dag dH X] - 2 Re[Y^dag dA X].
+// For a pair Re[a^dag dA b] at site x, with
+// Lambda_{mu nu} = sum_{s s'} (gamma_mu gamma_nu)_{s s'} b_{s'} a_s^dag (3x3) and
+// Lt = Lambda - tr(Lambda)/3 (traceless) or Lambda:
+//   Re[a^dag dA b] = -c_sw kappa / 8 sum_{mu<nu} Re tr[dQ_{mu nu}(x) (Lt - Lt^dag)],
+// so the clover part is sum_x sum_{mu<nu} Re tr[dQ_{mu nu}(x) Gamma_{mu nu}(x)]
+// with the insertion Gamma = c (Lt - Lt^dag), c = c_sw kappa / 4 (even sites
+// or full lattice) or c_sw kappa^3 / 4 (odd sites).  Each link lies in two
+// plaquettes per plane it spans, each of them a leaf of Q at its four
+// corners: the link receives, per plaquette, the loop product that follows
+// it with Gamma inserted at each corner in turn (its conjugate transpose
+// where the loop walks the link backwards).
 #include <chrono>
 #include <cmath>
 
 #include "solver.h"
 #include "stencil.h"
+#include "su3.h"
 
 namespace lq {
 
@@ -120,6 +139,218 @@ __global__ __launch_bounds__(128) void force_kernel(ForceArgs f)
     force_dir<P, NL, 3>(f, p, cb, c, f.M, f.G, lex);
 }
 
+// ---------------------------------------------------------------- clover --
+
+// gamma_mu gamma_nu of the chiral basis, plane by plane (mu, nu) = (0,1),
+// (0,2), (0,3), (1,2), (1,3), (2,3): block-diagonal over chirality, each
+// block s_k i sigma_m, with m and the signs s_0 (spins 0, 1), s_1 (spins 2, 3).
+__device__ __forceinline__ void plane_spin(int pid, int &m, int &s0, int &s1)
+{
+    switch (pid) {
+    case 0: m = 3; s0 = 1; s1 = 1; break;    // xy
+    case 1: m = 2; s0 = -1; s1 = -1; break;  // xz
+    case 2: m = 1; s0 = -1; s1 = 1; break;   // xt
+    case 3: m = 1; s0 = 1; s1 = 1; break;    // yz
+    case 4: m = 2; s0 = -1; s1 = 1; break;   // yt
+    default: m = 3; s0 = -1; s1 = 1; break;  // zt
+    }
+}
+
+__device__ __forceinline__ int plane_id(int a, int b)
+{
+    // a < b
+    return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+
+struct InsertArgs {
+    Geom g;
+    FieldView a[2], b[2];  // the pair (a, b) on each parity (FP64)
+    double c[2];           // insertion coefficient per parity (0: none)
+    int traceless;
+    char *gam;             // [parity][plane] x 18 reals over vh
+};
+
+// One site per thread: Gamma_{mu nu}(x) = c (Lt - Lt^dag) for the six planes.
+__global__ __launch_bounds__(128) void clover_insert_kernel(InsertArgs f)
+{
+    const int cb = blockIdx.x * 128 + threadIdx.x;
+    const int p = blockIdx.y;
+    if (cb >= f.g.vh) return;
+    const double cf = f.c[p];
+    Spinor<double> av, bv;
+    if (cf != 0.0) {
+        av = load_spinor<F64>(f.a[p].base, cb, f.a[p].n);
+        bv = load_spinor<F64>(f.b[p].base, cb, f.b[p].n);
+    }
+    for (int pid = 0; pid < 6; ++pid) {
+        int m, s0, s1;
+        plane_spin(pid, m, s0, s1);
+        // i sigma_m as 2x2: entries (i, j)
+        cx<double> is[2][2];
+        if (m == 1) { is[0][0] = cx<double>{0, 0}; is[0][1] = cx<double>{0, 1}; is[1][0] = cx<double>{0, 1}; is[1][1] = cx<double>{0, 0}; }
+        else if (m == 2) { is[0][0] = cx<double>{0, 0}; is[0][1] = cx<double>{1, 0}; is[1][0] = cx<double>{-1, 0}; is[1][1] = cx<double>{0, 0}; }
+        else { is[0][0] = cx<double>{0, 1}; is[0][1] = cx<double>{0, 0}; is[1][0] = cx<double>{0, 0}; is[1][1] = cx<double>{0, -1}; }
+        // Lambda_{d c} = sum_{s s'} G_{s s'} b_{s' d} conj(a_{s c})
+        cx<double> L[9];
+        for (int i = 0; i < 9; ++i) L[i] = cx<double>{0, 0};
+        if (cf != 0.0)
+            for (int k = 0; k < 2; ++k) {
+                const double sk = k == 0 ? s0 : s1;
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) {
+                        const cx<double> gij = sk * is[i][j];
+                        if (gij.re == 0.0 && gij.im == 0.0) continue;
+                        const int s = 2 * k + i, sp = 2 * k + j;
+                        for (int d = 0; d < 3; ++d)
+                            for (int c = 0; c < 3; ++c)
+                                L[d * 3 + c] = L[d * 3 + c] + gij * cmulc(av.c[s * 3 + c], bv.c[sp * 3 + d]);
+                    }
+            }
+        if (f.traceless) {
+            const cx<double> tr = (1.0 / 3.0) * (L[0] + L[4] + L[8]);
+            L[0] = L[0] - tr;
+            L[4] = L[4] - tr;
+            L[8] = L[8] - tr;
+        }
+        double raw[18];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                // c (L - L^dag)_{ij}
+                const cx<double> v = L[i * 3 + j] - conj(L[j * 3 + i]);
+                raw[2 * (i * 3 + j)] = cf * v.re;
+                raw[2 * (i * 3 + j) + 1] = cf * v.im;
+            }
+        store_planes<double, 18>(f.gam + (long)(p * 6 + pid) * Planes<double, 18>::field_bytes(f.g.vh), cb, f.g.vh,
+                                 raw);
+    }
+}
+
+__device__ __forceinline__ M3 gamma_at(const Geom &g, const char *gam, const int c[4], int pid)
+{
+    const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+    double raw[18];
+    load_planes<double, 18>(gam + (long)(p * 6 + pid) * Planes<double, 18>::field_bytes(g.vh), cb_index(g, c), g.vh,
+                            raw);
+    M3 m;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m.e[i] = cx<double>{raw[2 * i], raw[2 * i + 1]};
+    return m;
+}
+
+// R = G0 A B C + A G1 B C + A B G2 C + A B C G3: the loop product that follows
+// a link (A, B, C the other three factors in loop order), with the insertion
+// of each corner after the link (G0 first, G3 at the link's own start).
+__device__ __forceinline__ M3 loop_insert(const M3 &A, const M3 &B, const M3 &C, const M3 &G0, const M3 &G1,
+                                          const M3 &G2, const M3 &G3)
+{
+    const M3 AB = mul(A, B);
+    const M3 ABC = mul(AB, C);
+    const M3 BC = mul(B, C);
+    M3 r = mul(G0, ABC);
+    r = add(r, mul(A, mul(G1, BC)));
+    r = add(r, mul(AB, mul(G2, C)));
+    r = add(r, mul(ABC, G3));
+    return r;
+}
+
+struct CloverForceArgs {
+    Geom g;
+    const char *links64;  // packed FP64 links, 18 reals
+    const char *gam;
+    double *M, *G;        // outputs of the hopping-term kernel, added to (each may be null)
+};
+
+// One (site, direction) per thread: the clover part Mc of the link's matrix;
+// adds Mc^dag to the gradient and -TA(U Mc) to the force (both linear in M).
+__global__ __launch_bounds__(128) void clover_force_kernel(CloverForceArgs f)
+{
+    const int cb = blockIdx.x * 128 + threadIdx.x;
+    const int p = blockIdx.y;
+    const int rho = blockIdx.z;
+    if (cb >= f.g.vh) return;
+    const Geom &g = f.g;
+    int y[4];
+    cb_coords(g, p, cb, y);
+    const long lex = y[0] + (long)g.L[0] * (y[1] + (long)g.L[1] * (y[2] + (long)g.L[2] * y[3]));
+    M3 m;
+    for (int i = 0; i < 9; ++i) m.e[i] = cx<double>{0, 0};
+    for (int sg = 0; sg < 4; ++sg) {
+        if (sg == rho) continue;
+        const int a = rho < sg ? rho : sg, b = rho < sg ? sg : rho;
+        const int pid = plane_id(a, b);
+        int c1[4], c2[4], c3[4], c4[4];
+        if (rho == a) {
+            // plaquette based at y: U_a(y) [the link] U_b(y+a) U_a(y+b)^dag U_b(y)^dag
+            shift(g, y, a, 1, b, 0, c2);
+            shift(g, y, a, 1, b, 1, c3);
+            shift(g, y, a, 0, b, 1, c4);
+            m = add(m, loop_insert(link_at(g, f.links64, c2, b), dag(link_at(g, f.links64, c4, a)),
+                                   dag(link_at(g, f.links64, y, b)), gamma_at(g, f.gam, c2, pid),
+                                   gamma_at(g, f.gam, c3, pid), gamma_at(g, f.gam, c4, pid),
+                                   gamma_at(g, f.gam, y, pid)));
+            // plaquette based at z = y - b, walking the link backwards:
+            // U_a(z) U_b(z+a) U_a(y)^dag U_b(z)^dag
+            shift(g, y, a, 0, b, -1, c1);  // z
+            shift(g, y, a, 1, b, -1, c2);  // z + a
+            shift(g, y, a, 1, b, 0, c3);   // y + a
+            m = add(m, dag(loop_insert(dag(link_at(g, f.links64, c1, b)), link_at(g, f.links64, c1, a),
+                                       link_at(g, f.links64, c2, b), gamma_at(g, f.gam, y, pid),
+                                       gamma_at(g, f.gam, c1, pid), gamma_at(g, f.gam, c2, pid),
+                                       gamma_at(g, f.gam, c3, pid))));
+        } else {
+            // plaquette based at y, walking the link backwards:
+            // U_a(y) U_b(y+a) U_a(y+b)^dag U_b(y)^dag
+            shift(g, y, a, 1, b, 0, c2);
+            shift(g, y, a, 1, b, 1, c3);
+            shift(g, y, a, 0, b, 1, c4);
+            m = add(m, dag(loop_insert(link_at(g, f.links64, y, a), link_at(g, f.links64, c2, b),
+                                       dag(link_at(g, f.links64, c4, a)), gamma_at(g, f.gam, y, pid),
+                                       gamma_at(g, f.gam, c2, pid), gamma_at(g, f.gam, c3, pid),
+                                       gamma_at(g, f.gam, c4, pid))));
+            // plaquette based at z = y - a: U_a(z) U_b(y) [the link] U_a(z+b)^dag U_b(z)^dag
+            shift(g, y, a, -1, b, 0, c1);  // z
+            shift(g, y, a, 0, b, 1, c3);   // y + b
+            shift(g, y, a, -1, b, 1, c4);  // z + b
+            m = add(m, loop_insert(dag(link_at(g, f.links64, c4, a)), dag(link_at(g, f.links64, c1, b)),
+                                   link_at(g, f.links64, c1, a), gamma_at(g, f.gam, c3, pid),
+                                   gamma_at(g, f.gam, c4, pid), gamma_at(g, f.gam, c1, pid),
+                                   gamma_at(g, f.gam, y, pid)));
+        }
+    }
+    if (f.M) {
+        double *o = f.M + (lex * 4 + rho) * 18;
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                o[2 * (i * 3 + k)] += m.e[k * 3 + i].re;
+                o[2 * (i * 3 + k) + 1] -= m.e[k * 3 + i].im;
+            }
+    }
+    if (f.G) {
+        const M3 bm = mul(link_at(g, f.links64, y, rho), m);
+        const double tri = (bm.e[0].im + bm.e[4].im + bm.e[8].im) / 3.0;
+        double *o = f.G + (lex * 4 + rho) * 18;
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const cx<double> bik = bm.e[i * 3 + k], bki = bm.e[k * 3 + i];
+                double re = 0.5 * (bki.re - bik.re);
+                double im = 0.5 * (-bki.im - bik.im);
+                if (i == k) im += tri;
+                o[(i * 3 + k) * 2] += re;
+                o[(i * 3 + k) * 2 + 1] += im;
+            }
+    }
+}
+
+static hipError_t launch_clover_force(const InsertArgs &ia, const CloverForceArgs &cf, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((ia.g.vh + 127) / 128);
+    clover_insert_kernel<<<dim3(nb, 2), 128, 0, s>>>(ia);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    clover_force_kernel<<<dim3(nb, 2, 4), 128, 0, s>>>(cf);
+    return hipGetLastError();
+}
+
 static hipError_t launch_force(const ForceArgs &f, int prec, int nl, hipStream_t s)
 {
     const dim3 grid((f.g.vh + 127) / 128, 2);
@@ -148,10 +379,6 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
     }
     if (force_prec != LQ_F64 && force_prec != LQ_F32) {
         set_error("lq_pf_force: force precision must be LQ_F64 or LQ_F32");
-        return LQ_ERR_ARG;
-    }
-    if (op->prm.csw != 0.0) {
-        set_error("lq_pf_force: the force is implemented for the Wilson operator (csw = 0)");
         return LQ_ERR_ARG;
     }
     std::string why;
@@ -210,6 +437,9 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
         f.links = op->links[fp].ptr;
         f.M = static_cast<double *>(dSdU);
         f.G = static_cast<double *>(G);
+        InsertArgs ia{};
+        ia.g = g;
+        ia.traceless = op->prm.clover_traceless;
         op->tmp[2].ensure(4 * (size_t)fb(F64, g) * 2);
         op->tmp[3].ensure(4 * (size_t)fb(fp, g) * 2);
         if (eo) {
@@ -218,8 +448,14 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
             const FieldView Z = parity_view(op->tmp[2].ptr, F64, g, 1);
             const FieldView W = parity_view(op->tmp[2].ptr + fb(F64, g), F64, g, 1);
             c.apply(Y, X, false);
-            hop(op, F64, Z, X, 1, false, 0, false, nullptr, 1.0, 0, nullptr, s);
-            hop(op, F64, W, Y, 1, true, 0, false, nullptr, 1.0, 0, nullptr, s);
+            // Z = A_oo^-1 H_oe X, W = A_oo^-1 H_eo^dag Y (A_oo = 1 without clover)
+            hop(op, F64, Z, X, 1, false, 2, true, nullptr, 1.0, 0, nullptr, s);
+            hop(op, F64, W, Y, 1, true, 2, true, nullptr, 1.0, 0, nullptr, s);
+            if (op->has_clover) {
+                ia.a[0] = Y; ia.b[0] = X; ia.c[0] = op->prm.csw * op->prm.kappa / 4;
+                ia.a[1] = W; ia.b[1] = Z;
+                ia.c[1] = op->prm.csw * op->prm.kappa * op->prm.kappa * op->prm.kappa / 4;
+            }
             FieldView Xf = X, Yf = Y, Zf = Z, Wf = W;
             if (fp != F64) {
                 char *b = op->tmp[3].ptr;
@@ -240,6 +476,12 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
             const FieldView X = c.x64;  // full: [parity] slices
             const FieldView Y = c.y64;
             c.apply(Y, X, false);
+            if (op->has_clover)
+                for (int p = 0; p < 2; ++p) {
+                    ia.a[p] = FieldView{Y.base + p * Y.rs, F64, (long)g.vh, Y.rs, 1};
+                    ia.b[p] = FieldView{X.base + p * X.rs, F64, (long)g.vh, X.rs, 1};
+                    ia.c[p] = op->prm.csw * op->prm.kappa / 4;
+                }
             FieldView Xs = X, Ys = Y;
             if (fp != F64) {
                 char *b = op->tmp[3].ptr;
@@ -257,7 +499,21 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
             }
             f.coef = 2.0 * op->prm.kappa;
         }
-        if (dSdU || G) LQ_HIP(launch_force(f, fp, op->nl(fp), s));
+        if (dSdU || G) {
+            LQ_HIP(launch_force(f, fp, op->nl(fp), s));
+            if (op->has_clover) {
+                // the clover part, in FP64 whatever the force precision
+                op->force_ws.ensure(12 * (size_t)Planes<double, 18>::field_bytes(g.vh));
+                ia.gam = op->force_ws.ptr;
+                CloverForceArgs cf{};
+                cf.g = g;
+                cf.links64 = op->links[F64].ptr;
+                cf.gam = ia.gam;
+                cf.M = f.M;
+                cf.G = f.G;
+                LQ_HIP(launch_clover_force(ia, cf, s));
+            }
+        }
         if (X_out) {
             if (eo) LQ_HIP(launch_unpack_spinor(g, 0, 1, c.x64, static_cast<double *>(X_out), s));
             else

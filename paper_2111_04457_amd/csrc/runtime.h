@@ -64,6 +64,7 @@ struct lq_op {
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
     lq::Buf flag;                        // device int: singular clover block
     lq::Buf tmp[6];                      // scratch fields for composite applies
+    lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
     lq::Buf partial;                     // reduction partial sums
     lq::Buf solver_ws;                   // solver work vectors
     lq::Buf solver_sc;                   // solver scalars (device)
