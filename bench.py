@@ -158,7 +158,9 @@ def _extras(lq, torch):
       in one batched solve vs separate solves;
     - time to solution on 16^3x32 clover (kappa 0.13, c_sw 1.0): FP64
       BiCGStab and CGNE vs FP32- and FP16-inner BiCGStab;
-    - the pseudofermion force on 16^4 Wilson (kappa 0.125), FP64 and FP32."""
+    - the pseudofermion force on 16^4 Wilson (kappa 0.125), FP64 and FP32;
+    - the clover pseudofermion force on 16^3x32 (solve to 1e-10), FP64 and
+      FP32 hopping part."""
     from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_parity_spinor, gaussian_spinor,
                                 point_sources, workload_gauge, workload_source)
     out = {}
@@ -241,6 +243,19 @@ def _extras(lq, torch):
         (res, ms) = _timed(torch, lambda: lq.pf_force(op, phi, fp, "eo", prec))
         out["force_16x16x16x16_%s_ms" % prec] = ms
         out["force_16x16x16x16_%s_iters" % prec] = res[4].nconv
+    op.close()
+
+    w = WORKLOADS["clover_16x16x16x32"]
+    d = w["dims"]
+    op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(torch.from_numpy(workload_gauge("clover_16x16x16x32")).cuda())
+    phi = torch.from_numpy(gaussian_parity_spinor(d, 2005)).cuda()
+    for prec, inner in (("f64", "f64"), ("f32", "f32")):
+        fp = lq.SolverParams(solver="cgne", tol=1e-10, inner=inner)
+        lq.pf_force(op, phi, fp, "eo", prec)
+        (res, ms) = _timed(torch, lambda: lq.pf_force(op, phi, fp, "eo", prec))
+        out["force_clover_16x16x16x32_%s_ms" % prec] = ms
+        out["force_clover_16x16x16x32_%s_iters" % prec] = res[4].nconv
     op.close()
     return out
 

@@ -14,14 +14,20 @@ Fhat_{mu nu} with Fhat = (Q - Q^dag)/8 from the four counter-clockwise
 leaves.  torch autograd then gives dS/dU, so the force is the definition of
 the derivative itself, with no hand-derived formula.  Dense N x N matrices
 (N = 12 V): tiny lattices only.
+
+pf_force_clover_mf reaches larger lattices: X comes from the conjugate-
+gradient solve of the C oracle, and only the step that follows from the
+definition is left to autograd: with Y = M X (M the matrix of the action),
+dS = -X^dag d(M^dag M) X = -2 Re[Y^dag dM X], so the gradient is -2 times
+that of the bilinear Re[Y^dag M(U) X] with X, Y held fixed, where M(U) X is
+evaluated matrix-free (neighbour shifts, per-site 12 x 12 blocks).
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from . import dense as _dense
-from . import traceless_antihermitian
+from . import Operator, cg, dense as _dense, from_parity, traceless_antihermitian
 
 _AXIS = {0: 3, 1: 2, 2: 1, 3: 0}  # direction mu -> axis of [t, z, y, x]
 
@@ -156,3 +162,73 @@ def pf_action_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True)
         Ut = torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128))
         ph = torch.from_numpy(np.ascontiguousarray(phi, dtype=np.complex128)).reshape(-1)
         return float(_action(Ut, dims, float(kappa), float(csw), bc, traceless, ph, variant))
+
+
+def _hop_torch(U, psi, bc):
+    """(H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x + mu) + (1 + gamma_mu)
+    U_mu(x - mu)^dag psi(x - mu)], with the boundary phase on links that wrap;
+    psi [Lt, Lz, Ly, Lx, 4, 3]."""
+    g = _gammas()
+    one = torch.eye(4, dtype=torch.complex128)
+    lt, lz, ly, lx = psi.shape[:4]
+    t, z, y, x = torch.meshgrid(torch.arange(lt), torch.arange(lz), torch.arange(ly), torch.arange(lx),
+                                indexing="ij")
+    coord, ext = [x, y, z, t], [lx, ly, lz, lt]
+    out = torch.zeros_like(psi)
+    for mu in range(4):
+        ph = complex(bc[mu])
+        c128 = dict(dtype=torch.complex128)
+        phf = torch.where(coord[mu] == ext[mu] - 1, torch.tensor(ph, **c128), torch.tensor(1.0 + 0j, **c128))
+        phb = torch.where(coord[mu] == 0, torch.tensor(np.conj(ph), **c128), torch.tensor(1.0 + 0j, **c128))
+        u = U[..., mu, :, :]
+        f = torch.einsum("...cd,...sd->...sc", u, _fwd(psi, mu)) * phf[..., None, None]
+        b = torch.einsum("...cd,...sd->...sc", _h(_bwd(u, mu)), _bwd(psi, mu)) * phb[..., None, None]
+        out = out + torch.einsum("st,...tc->...sc", one - g[mu], f) + torch.einsum("st,...tc->...sc", one + g[mu], b)
+    return out
+
+
+def _block_apply(A, psi):
+    shape = psi.shape
+    return torch.einsum("...ij,...j->...i", A, psi.reshape(*shape[:4], 12)).reshape(shape)
+
+
+def pf_force_clover_mf(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True, tol=1e-13):
+    """pf_force_clover without dense matrices: (S, Mraw, G) for the even-odd
+    or full-lattice clover (or, at c_sw = 0, Wilson) action."""
+    dims = tuple(int(v) for v in dims)
+    op = Operator(dims, U, kappa, csw, bc, traceless)
+    if variant == "eo":
+        X, _ = cg(op.schur_normal, np.ascontiguousarray(phi, dtype=np.complex128), tol)
+        Y = op.schur(X)
+        Xf, Yf = from_parity(dims, X, 0), from_parity(dims, Y, 0)
+    else:
+        X, _ = cg(op.DdagD, np.ascontiguousarray(phi, dtype=np.complex128).reshape(op.shape), tol)
+        Y = op.D(X)
+        Xf, Yf = X, Y
+    S = float(np.vdot(np.asarray(phi).reshape(-1), X.reshape(-1)).real)
+    Ut = torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).clone().requires_grad_(True)
+    Xt, Yt = torch.from_numpy(Xf), torch.from_numpy(Yf)
+    A = _site_blocks(Ut, dims, float(kappa), float(csw), traceless)
+    if variant == "eo":
+        # M X = A_ee X - kappa^2 H_eo A_oo^-1 H_oe X with X on the even sites
+        odd = torch.from_numpy(np.ascontiguousarray(_parity_mask(dims)))
+        Aodd = torch.where(odd[..., None, None], A, torch.eye(12, dtype=torch.complex128))
+        t = _hop_torch(Ut, Xt, bc)                  # H_oe X (odd sites)
+        t = torch.linalg.solve(Aodd, t.reshape(*t.shape[:4], 12)).reshape(t.shape)
+        t = _hop_torch(Ut, t * odd[..., None, None], bc)
+        MX = (_block_apply(A, Xt) - float(kappa) ** 2 * t) * (~odd)[..., None, None]
+    else:
+        MX = _block_apply(A, Xt) - float(kappa) * _hop_torch(Ut, Xt, bc)
+    f = (Yt.conj() * MX).real.sum()
+    f.backward()
+    g = -2.0 * Ut.grad.detach().numpy()
+    Mraw = np.conj(np.swapaxes(g, -1, -2))
+    G = -traceless_antihermitian(np.asarray(U) @ Mraw)
+    return S, Mraw, G
+
+
+def _parity_mask(dims):
+    """True on odd sites, [Lt, Lz, Ly, Lx]."""
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    return ((x + y + z + t) % 2) == 1

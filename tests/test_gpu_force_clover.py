@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 import oracle
-from lattice_inputs import gauge_exp, gauge_transform, gaussian_parity_spinor, gaussian_spinor, random_su3_algebra
+from lattice_inputs import (ANTIPERIODIC_T, WORKLOADS, gauge_exp, gauge_transform, gaussian_parity_spinor,
+                            gaussian_spinor, random_su3_algebra, workload_gauge)
 from tests.gpu_common import announce, have_gpu, rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -152,4 +153,67 @@ def test_clover_autograd_function(lq):
     pred = float(np.sum((np.conj(gU) * dU).real) + np.sum((np.conj(gp) * dp).real))
     announce("  clover autograd FD %.10e predicted %.10e" % (fd, pred))
     assert abs(fd - pred) < 1e-6 * max(1.0, abs(pred))
+    op.close()
+
+
+@pytest.mark.parametrize("dims,variant,prec", [
+    ((8, 8, 8, 8), "eo", "f64"),
+    ((8, 8, 8, 8), "eo", "f32"),
+    ((6, 4, 4, 10), "full", "f64"),  # 480 sites per parity: a ragged last workgroup
+])
+def test_clover_force_matrix_free_oracle(lq, dims, variant, prec):
+    """Larger lattices against the matrix-free oracle (C-oracle CG solve,
+    autograd of the bilinear), at the 16^3x32 clover workload's kappa, c_sw
+    and link spread."""
+    fc = _fc()
+    w = WORKLOADS["clover_16x16x16x32"]
+    announce("clover force (matrix-free oracle): dims=%s variant=%s prec=%s" % (dims, variant, prec))
+    key = ("mf", dims, variant)
+    if key not in _REF:
+        U = workload_gauge("clover_16x16x16x32", dims)
+        phi = gaussian_parity_spinor(dims, 3501) if variant == "eo" else gaussian_spinor(dims, 3501)
+        _REF[key] = (U, phi) + fc.pf_force_clover_mf(dims, U, w["kappa"], w["csw"], ANTIPERIODIC_T, phi, variant)
+    U, phi, S_ref, M_ref, G_ref = _REF[key]
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T)
+    op.set_gauge(to_dev(U))
+    prm = lq.SolverParams(solver="cgne", tol=1e-12, inner="f64" if prec == "f64" else "f32")
+    S, grad, G, _, st = lq.pf_force(op, to_dev(phi), prm, variant, prec)
+    grad, G = to_host(grad), to_host(G)
+    tol = 1e-9 if prec == "f64" else 1e-5
+    e_grad = rel_err(grad, np.conj(np.swapaxes(M_ref, -1, -2)))
+    announce("  S %.12e (oracle %.12e) iters %d | grad err %.2e G err %.2e" % (S, S_ref, st.nconv, e_grad,
+                                                                             rel_err(G, G_ref)))
+    assert st.converged
+    assert abs(S - S_ref) < 1e-10 * abs(S_ref)
+    assert e_grad < tol and rel_err(G, G_ref) < tol
+    op.close()
+
+
+def test_clover_force_16x16x16x32_covariance(lq):
+    """The 16^3x32 clover workload: the force of a gauge-rotated field and
+    source is the rotated force (a property that holds at any size)."""
+    name = "clover_16x16x16x32"
+    w = WORKLOADS[name]
+    dims = w["dims"]
+    announce("clover force: %s gauge covariance" % name)
+    U = workload_gauge(name)
+    phi_e = gaussian_parity_spinor(dims, 3601)
+    Om = gauge_transform(dims, 3602)
+    Ut = np.empty_like(U)
+    for mu in range(4):
+        Ut[..., mu, :, :] = Om @ U[..., mu, :, :] @ np.conj(np.swapaxes(np.roll(Om, -1, axis=3 - mu), -1, -2))
+    phit = oracle.to_parity(dims, np.einsum("...ab,...sb->...sa", Om, oracle.from_parity(dims, phi_e, 0)), 0)
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T)
+    prm = lq.SolverParams(solver="cgne", tol=1e-13, inner="f32")
+    op.set_gauge(to_dev(U))
+    S, _, G, _, st = lq.pf_force(op, to_dev(phi_e), prm)
+    op.set_gauge(to_dev(Ut))
+    St, _, Gt, _, st2 = lq.pf_force(op, to_dev(phit), prm)
+    G, Gt = to_host(G), to_host(Gt)
+    expect = Om[..., None, :, :] @ G @ np.conj(np.swapaxes(Om, -1, -2))[..., None, :, :]
+    e = rel_err(Gt, expect)
+    announce("  S %.12e / %.12e iters %d/%d  covariance err %.2e" % (S, St, st.nconv, st2.nconv, e))
+    assert st.converged and st2.converged
+    assert abs(S - St) < 1e-10 * abs(S)
+    assert e < 1e-8
     op.close()
