@@ -232,6 +232,13 @@ def _extras(lq, torch):
     print("bench: 16x16x16x32 ladder %s" % json.dumps({k: v for k, v in out.items() if k.startswith("clover_16")}),
           file=sys.stderr, flush=True)
 
+    out.update(_forces(lq, torch))
+def _forces(lq, torch):
+    """The pseudofermion force (solve + force kernels), each timed once after
+    a warm-up call: 16^4 Wilson (kappa 0.125) and 16^3x32 clover (kappa 0.13,
+    c_sw 1.0), FP64 and FP32."""
+    from lattice_inputs import ANTIPERIODIC_T, WORKLOADS, gaussian_parity_spinor, workload_gauge
+    out = {}
     w = WORKLOADS["wilson_16x16x16x16"]
     d = w["dims"]
     op = lq.Operator(d, w["kappa"], 0.0, ANTIPERIODIC_T)
@@ -278,6 +285,8 @@ def main(argv=None):
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 12-RHS propagator, ragged batch and force measurements")
+    ap.add_argument("--force-only", action="store_true",
+                    help="only the pseudofermion force measurements; prints their JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
     args = ap.parse_args(argv)
@@ -296,6 +305,11 @@ def main(argv=None):
     from paper_2111_04457_amd import build as hip_build
     if not os.path.exists(hip_build.LIB):
         hip_build.build()
+
+    if args.force_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"forces": _forces(lq, torch)}), flush=True)
+        return 0
 
     w = WORKLOADS[args.workload]
     dims = w["dims"]

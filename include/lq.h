@@ -191,7 +191,7 @@ lq_status lq_field_export(const lq_field *f, void *dst, void *stream);
 /* out = K in on packed fields of the same precision and nrhs (K >= LQ_SCHUR). */
 lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_field *in, void *stream);
 
-/* Workgroup size (64, 128 or 256 threads) of the hopping kernels of
+/* Workgroup size (64 (default), 128 or 256 threads) of the hopping kernels of
  * precision prec on this operator.  The result does not depend on it: every
  * site is summed in the same order whatever the launch shape. */
 lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);

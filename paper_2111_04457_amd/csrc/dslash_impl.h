@@ -53,7 +53,7 @@ __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict_
         const char *base = in + rr * a.in_rs;
         load_planes<S, 24>(base, nb, a.in_n, h.sp[r]);
         if constexpr (PT<P>::scaled)
-            h.scale[r] = *reinterpret_cast<const float *>(base + 48 * (size_t)a.in_n + (uint32_t)nb * 4u);
+            h.scale[r] = *reinterpret_cast<const float *>(base + 48 * (size_t)padded_sites(a.in_n) + (uint32_t)nb * 4u);
     }
 }
 

@@ -36,7 +36,7 @@ hipError_t launch_convert_links(const Geom &g, const char *links64, int prec, in
 // (the six field strengths of every site).
 hipError_t launch_clover_build(const Geom &g, const char *links64, double csw, double kappa, int traceless,
                                char *fbuf, char *clov64, hipStream_t s);
-inline size_t clover_fbuf_bytes(long vh) { return (size_t)2 * 6 * 18 * 8 * vh; }
+inline size_t clover_fbuf_bytes(long vh) { return (size_t)2 * 6 * 18 * 8 * padded_sites(vh); }
 // Per-block inverse of the blocks of parity p by Gauss-Jordan with partial
 // pivoting (FP64), into parity p of inv64; sets *flag nonzero if a block is
 // singular.
@@ -49,8 +49,8 @@ hipError_t launch_clover_apply(const Geom &g, const char *clov, FieldView out, F
 
 __host__ __device__ inline long link_bytes(int prec, int nl, long vh)
 {
-    return (long)nl * (prec == F64 ? 8 : prec == F32 ? 4 : 2) * vh;
+    return (long)nl * (prec == F64 ? 8 : prec == F32 ? 4 : 2) * padded_sites(vh);
 }
-__host__ __device__ inline long clover_bytes(int prec, long vh) { return 72L * (prec == F64 ? 8 : prec == F32 ? 4 : 2) * vh; }
+__host__ __device__ inline long clover_bytes(int prec, long vh) { return 72L * (prec == F64 ? 8 : prec == F32 ? 4 : 2) * padded_sites(vh); }
 
 }  // namespace lq

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(INV_T) void clover_invert_kernel(Geom g, int p, con
     auto at = [&](int i, int j) -> cx<double> & { return a[(i * 6 + j) * INV_T]; };
     const char *base = clov64 + (long)p * clover_bytes(F64, g.vh);
     double c[36];
-    load_planes<double, 36>(base + (long)18 * b * 16 * g.vh, cb, g.vh, c);
+    load_planes<double, 36, false, 576>(base + (long)18 * b * 16 * SB, cb, g.vh, c);
     double scale = 0.0;
     for (int i = 0; i < 6; ++i) {
         at(i, i) = cx<double>{c[i], 0.0};
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(INV_T) void clover_invert_kernel(Geom g, int p, con
         }
     // block b owns planes 18b .. 18b + 17 of the site record (72 FP64 reals)
     char *dst = inv64 + (long)p * clover_bytes(F64, g.vh);
-    store_planes<double, 36>(dst + (long)18 * b * 16 * g.vh, cb, g.vh, o);
+    store_planes<double, 36, false, 576>(dst + (long)18 * b * 16 * SB, cb, g.vh, o);
 }
 
 template <int P>

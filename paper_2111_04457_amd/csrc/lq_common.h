@@ -2,15 +2,20 @@
 // geometry of the checkerboarded lattice, precision traits, complex
 // arithmetic, and loads/stores of the structure-of-arrays field layout.
 //
-// Field layout in HBM ("planes"): a field of R reals per site and storage
-// type T over n sites is stored as  floor(R*sizeof(T)/16)  planes of 16-byte
-// elements, followed by at most one narrower tail plane (8 or 4 bytes) for
-// the remainder, each plane holding one element per site:
-//     plane k element of site s at  base + k*16*n + 16*s
-//     tail element of site s    at  base + K16*16*n + TAIL*s
-// so a wavefront of 64 consecutive sites reads 64 consecutive 16-byte
-// elements (1 KiB) per load instruction.  FP16 spinors carry one more plane
-// of FP32 per-site scales.  Several right-hand sides are stacked whole.
+// Field layout in HBM (site blocks of "planes"): the sites of a field are
+// grouped in blocks of SB = 64 consecutive sites (one wavefront; the site
+// count is padded to whole blocks).  Within a block, a field of R reals per
+// site and storage type T is stored as  floor(R*sizeof(T)/16)  planes of
+// 16-byte elements, followed by at most one narrower tail plane (8 or 4
+// bytes) for the remainder, each plane holding one element per site:
+//     plane k element of site s at  base + (s/SB)*REC*SB + k*16*SB + 16*(s%SB)
+//     tail element of site s    at  base + (s/SB)*REC*SB + K16*16*SB + TAIL*(s%SB)
+// with REC = R*sizeof(T) the bytes of one site.  A wavefront of 64
+// consecutive sites reads 64 consecutive 16-byte elements (1 KiB) per load
+// instruction, and its whole record is one contiguous range of REC*64 bytes
+// (fewer DRAM pages open at a time than with whole-field planes).  FP16
+// spinors carry a separate plane of FP32 per-site scales after the blocks.
+// Several right-hand sides are stacked whole.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -78,6 +83,9 @@ template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re 
 
 // --------------------------------------------------------------- planes --
 
+constexpr int SB = 64;  // sites per block
+__host__ __device__ constexpr long padded_sites(long n) { return (n + SB - 1) / SB * SB; }
+
 template <typename T, int N> struct Planes {
     static constexpr int BYTES = N * (int)sizeof(T);
     static constexpr int K16 = BYTES / 16;
@@ -85,13 +93,12 @@ template <typename T, int N> struct Planes {
     static constexpr int PER16 = 16 / (int)sizeof(T);
     static_assert(TAIL == 0 || TAIL == 8 || TAIL == 4, "unsupported tail");
     // bytes of the whole field over n sites
-    __host__ __device__ static constexpr long field_bytes(long n) { return (long)BYTES * n; }
+    __host__ __device__ static constexpr long field_bytes(long n) { return (long)BYTES * padded_sites(n); }
 };
 
-// Addresses are formed as (plane base, uniform across the wavefront) +
-// (32-bit per-lane byte offset), the form the hardware takes as a scalar
-// base plus a vector offset; a plane of n sites is below 2^31 bytes
-// (n <= 2^27 is enforced when an operator is created).
+// REC, the site record's bytes, is the block stride; it differs from
+// N*sizeof(T) only when a caller reads part of a record (the two 36-real
+// halves of a clover block).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -108,47 +115,48 @@ template <typename V, bool NT> __device__ __forceinline__ void st(void *p, V v)
     else *reinterpret_cast<V *>(p) = v;
 }
 
-template <typename T, int N, bool NTL = false>
+template <typename T, int N, bool NTL = false, int REC = N * (int)sizeof(T)>
 __device__ __forceinline__ void load_planes(const char *__restrict__ base, long s, long n, T *__restrict__ out)
 {
     using PL = Planes<T, N>;
-    const uint32_t o16 = (uint32_t)s * 16u;
+    const char *blk = base + (size_t)(s >> 6) * (size_t)(REC * SB);
+    const uint32_t lane = (uint32_t)(s & 63);
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
-        const char *pl = base + (size_t)k * 16 * (size_t)n;
-        const u32x4 q = ld<u32x4, NTL>(pl + o16);
+        const u32x4 q = ld<u32x4, NTL>(blk + k * 16 * SB + lane * 16u);
         __builtin_memcpy(out + k * PL::PER16, &q, 16);
     }
-    const char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
+    const char *tl = blk + PL::K16 * 16 * SB;
     if constexpr (PL::TAIL == 8) {
-        const u32x2 q = ld<u32x2, NTL>(tl + (uint32_t)s * 8u);
+        const u32x2 q = ld<u32x2, NTL>(tl + lane * 8u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 8);
     } else if constexpr (PL::TAIL == 4) {
-        const uint32_t q = ld<uint32_t, NTL>(tl + (uint32_t)s * 4u);
+        const uint32_t q = ld<uint32_t, NTL>(tl + lane * 4u);
         __builtin_memcpy(out + PL::K16 * PL::PER16, &q, 4);
     }
 }
 
-template <typename T, int N, bool NTS = false>
+template <typename T, int N, bool NTS = false, int REC = N * (int)sizeof(T)>
 __device__ __forceinline__ void store_planes(char *__restrict__ base, long s, long n, const T *__restrict__ in)
 {
     using PL = Planes<T, N>;
-    const uint32_t o16 = (uint32_t)s * 16u;
+    char *blk = base + (size_t)(s >> 6) * (size_t)(REC * SB);
+    const uint32_t lane = (uint32_t)(s & 63);
 #pragma unroll
     for (int k = 0; k < PL::K16; ++k) {
         u32x4 q;
         __builtin_memcpy(&q, in + k * PL::PER16, 16);
-        st<u32x4, NTS>(base + (size_t)k * 16 * (size_t)n + o16, q);
+        st<u32x4, NTS>(blk + k * 16 * SB + lane * 16u, q);
     }
-    char *tl = base + (size_t)PL::K16 * 16 * (size_t)n;
+    char *tl = blk + PL::K16 * 16 * SB;
     if constexpr (PL::TAIL == 8) {
         u32x2 q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 8);
-        st<u32x2, NTS>(tl + (uint32_t)s * 8u, q);
+        st<u32x2, NTS>(tl + lane * 8u, q);
     } else if constexpr (PL::TAIL == 4) {
         uint32_t q;
         __builtin_memcpy(&q, in + PL::K16 * PL::PER16, 4);
-        st<uint32_t, NTS>(tl + (uint32_t)s * 4u, q);
+        st<uint32_t, NTS>(tl + lane * 4u, q);
     }
 }
 
@@ -157,10 +165,11 @@ template <typename R> struct Spinor {
     cx<R> c[12];  // index spin*3 + colour
 };
 
-// Bytes of a packed spinor field over n sites (FP16: plus the scale plane).
+// Bytes of a packed spinor field over n sites, padded to whole blocks
+// (FP16: the 48-byte records, then the scale plane).
 __host__ __device__ constexpr long spinor_field_bytes(int p, long n)
 {
-    return p == F64 ? 192 * n : p == F32 ? 96 * n : 52 * n;
+    return (p == F64 ? 192 : p == F32 ? 96 : 52) * padded_sites(n);
 }
 
 template <int P>
@@ -172,7 +181,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__r
     load_planes<S, 24>(base, s, n, raw);
     Spinor<R> o;
     if constexpr (PT<P>::scaled) {
-        const float sc = *reinterpret_cast<const float *>(base + 48 * (size_t)n + (uint32_t)s * 4u);
+        const float sc = *reinterpret_cast<const float *>(base + 48 * (size_t)padded_sites(n) + (uint32_t)s * 4u);
 #pragma unroll
         for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i] * sc, (R)raw[2 * i + 1] * sc};
     } else {
@@ -180,6 +189,17 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__r
         for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i], (R)raw[2 * i + 1]};
     }
     return o;
+}
+
+// binary16 rounding of an FP32 value as a step of its own.  The empty
+// register constraint keeps the compiler from folding the product that
+// feeds the conversion into one mixed-precision multiply-add that rounds to
+// binary16 once: it does so in some instantiations and not in others, and
+// the results would then differ in the last bit between launch shapes.
+__device__ __forceinline__ _Float16 to_f16(float x)
+{
+    asm("" : "+v"(x));
+    return (_Float16)x;
 }
 
 template <int P, bool NTS = false>
@@ -196,10 +216,10 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, long s, lo
         const R inv = m > 0 ? (R)1 / m : (R)0;
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
-            raw[2 * i] = (S)(v.c[i].re * inv);
-            raw[2 * i + 1] = (S)(v.c[i].im * inv);
+            raw[2 * i] = to_f16(v.c[i].re * inv);
+            raw[2 * i + 1] = to_f16(v.c[i].im * inv);
         }
-        st<float, NTS>(base + 48 * (size_t)n + (uint32_t)s * 4u, m);
+        st<float, NTS>(base + 48 * (size_t)padded_sites(n) + (uint32_t)s * 4u, m);
     } else {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
@@ -229,7 +249,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> as_stored(const Spinor<type
         Spinor<R> o;
 #pragma unroll
         for (int i = 0; i < 12; ++i)
-            o.c[i] = cx<R>{(R)(S)(v.c[i].re * inv) * sc, (R)(S)(v.c[i].im * inv) * sc};
+            o.c[i] = cx<R>{(R)to_f16(v.c[i].re * inv) * sc, (R)to_f16(v.c[i].im * inv) * sc};
         return o;
     }
 }

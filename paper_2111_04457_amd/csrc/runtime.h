@@ -52,7 +52,7 @@ struct lq_op {
     int device = 0;
     bool gauge_set = false;
     bool has_clover = false;
-    int hop_block[3] = {256, 256, 256};  // workgroup size of the hop kernel per precision
+    int hop_block[3] = {64, 64, 64};     // workgroup size of the hop kernel per precision
     // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
     // 2 XCD-aware and time slices interleaved
     int xcd_remap[3] = {1, 1, 1};
