@@ -233,6 +233,9 @@ def _extras(lq, torch):
           file=sys.stderr, flush=True)
 
     out.update(_forces(lq, torch))
+    return out
+
+
 def _forces(lq, torch):
     """The pseudofermion force (solve + force kernels), each timed once after
     a warm-up call: 16^4 Wilson (kappa 0.125) and 16^3x32 clover (kappa 0.13,
