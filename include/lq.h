@@ -287,6 +287,68 @@ lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, siz
 lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
                       void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the
+ * solves of the fermion matrix recur at every step of it), read as hybrid
+ * Monte Carlo with the Wilson plaquette gauge action
+ *   S_g = beta sum_x sum_{mu<nu} (1 - Re tr P_{mu nu}(x) / 3)
+ * and the even-odd pseudofermion action of lq_pf_force (variant 0, the
+ * operator's kappa, csw and boundary phases).  Momenta P_mu(x) are traceless
+ * anti-Hermitian, H = 1/2 sum tr(P^dag P) + S_g + S_f, and the equations of
+ * motion dU/dt = P U, dP/dt = -G (G the su(3) force, -TA(U M) as for
+ * lq_pf_force) are integrated with U <- exp(e P) U (FP64).
+ * Random numbers are the caller's: P is distributed as exp(-1/2 tr P^dag P)
+ * (P = i sum_a xi_a lambda_a / sqrt(2) with Gell-Mann lambda_a and standard
+ * normal xi_a), phi = M^dag eta with eta complex Gaussian of density
+ * exp(-eta^dag eta) (real and imaginary parts of variance 1/2), and the
+ * accept/reject draw compares a uniform r with exp(-dH).
+ * ---------------------------------------------------------------------- */
+typedef enum { LQ_LEAPFROG = 0, LQ_OMELYAN = 1 } lq_integrator;
+
+typedef struct {
+    double beta;          /* gauge coupling (0: no gauge action) */
+    double tau;           /* trajectory length */
+    int nsteps;           /* integration steps, >= 1 */
+    int integrator;       /* lq_integrator: leapfrog (P e/2, U e, P e/2 per step) or the
+                             second-order minimum-norm (Omelyan) scheme
+                             (P lambda e, U e/2, P (1 - 2 lambda) e, U e/2, P lambda e) */
+    double lambda;        /* Omelyan parameter (default 0.1931833275037836) */
+    int fermion;          /* 1: with the even-odd pseudofermion action; 0: pure gauge */
+    int force_prec;       /* lq_prec of the hopping-term force kernel (LQ_F64 or LQ_F32) */
+} lq_md_params;
+
+typedef struct {
+    double H0, H1, dH;    /* Hamiltonian at the start and the end, dH = H1 - H0 */
+    double T0, T1;        /* kinetic terms */
+    double Sg0, Sg1;      /* gauge actions */
+    double Sf0, Sf1;      /* pseudofermion actions (0 without fermions) */
+    int n_force;          /* force evaluations */
+    int converged;        /* 1 if every solve reached sp->tol */
+    long iters;           /* inner Krylov iterations of all solves */
+    double t_ms;          /* wall time */
+} lq_md_stats;
+
+/* Defaults: beta 5.6, tau 1, 10 leapfrog steps, lambda 0.1931833275037836,
+ * with fermions, FP64 force kernel. */
+void lq_md_params_default(lq_md_params *p);
+
+/* Wilson gauge action S (may be NULL) and its su(3) force G (device
+ * complex128 [V][4][3][3], may be NULL; G = -TA(U M) with dS = sum Re tr(M dU))
+ * on the operator's gauge field.  Synchronizes the stream when S is asked. */
+lq_status lq_gauge_force(lq_op *op, double beta, void *G, double *S, void *stream);
+
+/* One molecular-dynamics trajectory from (U, P): U (device complex128 gauge
+ * layout) and P (device complex128 [V][4][3][3], traceless anti-Hermitian)
+ * are updated in place; the operator is set to U at the start and holds
+ * the final U at the end.  phi: device complex128 [V/2][4][3] on the even
+ * sites (fermion = 1).  Every force evaluation runs a solve with sp (the
+ * solver of lq_pf_force) at the current U.  The force uses a workspace of
+ * 4 V 144 bytes kept with the operator.  LQ_NOT_CONVERGED if some solve
+ * missed sp->tol (stats are filled).  The caller decides acceptance with
+ * stats->dH. */
+lq_status lq_md_trajectory(lq_op *op, const lq_md_params *mp, const lq_solver_params *sp, void *U, void *P,
+                           const void *phi, lq_md_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,24 @@ class SolveStats(ctypes.Structure):
                 ("hop_bytes", ctypes.c_double), ("n_hop", ctypes.c_int)]
 
 
+LEAPFROG, OMELYAN = 0, 1
+INTEGRATORS = {"leapfrog": LEAPFROG, "omelyan": OMELYAN}
+
+
+class MDParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("tau", ctypes.c_double), ("nsteps", ctypes.c_int),
+                ("integrator", ctypes.c_int), ("lam", ctypes.c_double), ("fermion", ctypes.c_int),
+                ("force_prec", ctypes.c_int)]
+
+
+class MDStats(ctypes.Structure):
+    _fields_ = [("H0", ctypes.c_double), ("H1", ctypes.c_double), ("dH", ctypes.c_double),
+                ("T0", ctypes.c_double), ("T1", ctypes.c_double), ("Sg0", ctypes.c_double),
+                ("Sg1", ctypes.c_double), ("Sf0", ctypes.c_double), ("Sf1", ctypes.c_double),
+                ("n_force", ctypes.c_int), ("converged", ctypes.c_int), ("iters", ctypes.c_long),
+                ("t_ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes)
 P = ctypes.c_void_p
 I = ctypes.c_int
@@ -73,6 +91,10 @@ SIGNATURES = {
     "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),
+    "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),
+    "lq_gauge_force": (I, [P, D, P, ctypes.POINTER(D), P]),
+    "lq_md_trajectory": (I, [P, ctypes.POINTER(MDParams), ctypes.POINTER(SolverParams), P, P, P,
+                             ctypes.POINTER(MDStats), P]),
 }
 
 _LIB = None

@@ -6,6 +6,7 @@ Every computation runs in the HIP library; torch supplies device memory
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 
 import torch
@@ -309,3 +310,97 @@ class Batch:
         out = [SolveStats(s.nconv, s.nouter, s.restarts, bool(s.converged), s.diff, s.t_solve_ms, s.hop_bytes, s.n_hop)
                for s in stats]
         return xs, out
+
+
+@dataclass
+class MDParams:
+    """Molecular-dynamics parameters (lq_md_params)."""
+    beta: float = 5.6
+    tau: float = 1.0
+    nsteps: int = 10
+    integrator: str = "leapfrog"     # or "omelyan"
+    lam: float = 0.1931833275037836
+    fermion: bool = True
+    force_prec: str = "f64"
+
+    def to_c(self):
+        p = _lib.MDParams()
+        p.beta = float(self.beta)
+        p.tau = float(self.tau)
+        p.nsteps = int(self.nsteps)
+        p.integrator = _lib.INTEGRATORS[self.integrator]
+        p.lam = float(self.lam)
+        p.fermion = int(bool(self.fermion))
+        p.force_prec = _lib.PREC[self.force_prec]
+        return p
+
+
+@dataclass
+class MDStats:
+    H0: float
+    H1: float
+    dH: float
+    T0: float
+    T1: float
+    Sg0: float
+    Sg1: float
+    Sf0: float
+    Sf1: float
+    n_force: int
+    converged: bool
+    iters: int
+    t_ms: float
+
+
+def gauge_force(op: Operator, beta: float, want_force: bool = True):
+    """Wilson gauge action S_g and its su(3) force G on the operator's gauge
+    field.  Returns (S_g, G or None)."""
+    G = torch.empty(tuple(op.dims[::-1]) + (4, 3, 3), dtype=torch.complex128, device="cuda") if want_force else None
+    S = ctypes.c_double()
+    check(load().lq_gauge_force(op.handle, float(beta), ctypes.c_void_p(G.data_ptr()) if G is not None else None,
+                                ctypes.byref(S), _stream()))
+    return S.value, G
+
+
+def md_trajectory(op: Operator, U: torch.Tensor, P: torch.Tensor, phi: torch.Tensor | None, md: MDParams,
+                  params: SolverParams | None = None) -> MDStats:
+    """One molecular-dynamics trajectory; U and P (complex128 CUDA tensors
+    [Lt, Lz, Ly, Lx, 4, 3, 3]) are updated in place, and the operator holds
+    the final U.  phi: even-site pseudofermion [V/2, 4, 3] when md.fermion."""
+    gshape = tuple(op.dims[::-1]) + (4, 3, 3)
+    for t, name in ((U, "U"), (P, "P")):
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous() and tuple(t.shape) == gshape):
+            raise ValueError("%s must be a contiguous complex128 CUDA tensor of shape %s" % (name, gshape))
+    if md.fermion:
+        phi = _dev(phi, op.parity_shape, "phi")
+    params = params or SolverParams(tol=1e-10, inner="f32", solver="cgne")
+    cp = params.to_c()
+    mp = md.to_c()
+    st = _lib.MDStats()
+    rc = load().lq_md_trajectory(op.handle, ctypes.byref(mp), ctypes.byref(cp), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(P.data_ptr()),
+                                 ctypes.c_void_p(phi.data_ptr()) if md.fermion else None, ctypes.byref(st), _stream())
+    check(rc, allow_not_converged=True)
+    return MDStats(st.H0, st.H1, st.dH, st.T0, st.T1, st.Sg0, st.Sg1, st.Sf0, st.Sf1, st.n_force, bool(st.converged),
+                   st.iters, st.t_ms)
+
+
+def hmc_step(op: Operator, U: torch.Tensor, P0: torch.Tensor, eta: torch.Tensor | None, r: float, md: MDParams,
+             params: SolverParams | None = None):
+    """One hybrid Monte Carlo update with the caller's random numbers: the
+    momenta P0 (density exp(-1/2 tr P^dag P)), eta (pseudofermion heat bath
+    phi = M^dag eta, density exp(-eta^dag eta)) and a uniform r in [0, 1).
+    Returns (U_next, accepted, MDStats); U itself is not modified, and the
+    operator holds U_next."""
+    phi = None
+    if md.fermion:
+        op.set_gauge(U)
+        phi = op.apply("schur_dag", eta, "f64")
+    U1 = U.clone()
+    P1 = P0.clone()
+    st = md_trajectory(op, U1, P1, phi, md, params)
+    accepted = bool(r < math.exp(min(0.0, -st.dH)))
+    if not accepted:
+        op.set_gauge(U)
+        U1 = U
+    return U1, accepted, st

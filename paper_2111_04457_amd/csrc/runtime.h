@@ -65,6 +65,8 @@ struct lq_op {
     lq::Buf flag;                        // device int: singular clover block
     lq::Buf tmp[6];                      // scratch fields for composite applies
     lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
+    lq::Buf md_G;                        // molecular dynamics: the force on every link
+    lq::Buf md_partial;                  // molecular dynamics: per-wavefront partial sums
     lq::Buf partial;                     // reduction partial sums
     lq::Buf solver_ws;                   // solver work vectors
     lq::Buf solver_sc;                   // solver scalars (device)
