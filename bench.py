@@ -267,6 +267,36 @@ def _forces(lq, torch):
         out["force_clover_16x16x16x32_%s_ms" % prec] = ms
         out["force_clover_16x16x16x32_%s_iters" % prec] = res[4].nconv
     op.close()
+    out.update(_md(lq, torch))
+    return out
+
+
+def _md(lq, torch):
+    """One molecular-dynamics trajectory (tau 1, 10 leapfrog steps, Wilson
+    gauge action at beta 5.6 plus the even-odd pseudofermion; solves to
+    1e-10 with an FP32 inner solve) on 16^4 Wilson and 16^3x32 clover,
+    timed once after a warm-up trajectory from the same start."""
+    from lattice_inputs import (ANTIPERIODIC_T, WORKLOADS, gaussian_parity_spinor, random_su3_algebra,
+                                workload_gauge)
+    out = {}
+    sp = lq.SolverParams(solver="cgne", tol=1e-10, inner="f32")
+    md = lq.MDParams(beta=5.6, tau=1.0, nsteps=10, integrator="leapfrog", fermion=True, force_prec="f32")
+    for name in ("wilson_16x16x16x16", "clover_16x16x16x32"):
+        w = WORKLOADS[name]
+        d = w["dims"]
+        op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+        U0 = torch.from_numpy(workload_gauge(name)).cuda()
+        P0 = torch.from_numpy(random_su3_algebra(d, 2006)).cuda()
+        phi = torch.from_numpy(gaussian_parity_spinor(d, 2007)).cuda()
+        for _ in range(2):
+            U, P = U0.clone(), P0.clone()
+            st, ms = _timed(torch, lambda: lq.md_trajectory(op, U, P, phi, md, sp))
+        out["md_%s_traj_ms" % name] = ms
+        out["md_%s_dH" % name] = st.dH
+        out["md_%s_n_force" % name] = st.n_force
+        out["md_%s_iters" % name] = st.iters
+        op.close()
+    print("bench: md %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
 
 
@@ -289,7 +319,7 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 12-RHS propagator, ragged batch and force measurements")
     ap.add_argument("--force-only", action="store_true",
-                    help="only the pseudofermion force measurements; prints their JSON")
+                    help="only the pseudofermion force and molecular-dynamics measurements; prints their JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
     args = ap.parse_args(argv)
