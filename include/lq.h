@@ -315,6 +315,9 @@ typedef struct {
     double lambda;        /* Omelyan parameter (default 0.1931833275037836) */
     int fermion;          /* 1: with the even-odd pseudofermion action; 0: pure gauge */
     int force_prec;       /* lq_prec of the hopping-term force kernel (LQ_F64 or LQ_F32) */
+    int chrono;           /* initial guess of each force solve from the trajectory's previous
+                             solutions X: 0 zero, 1 the last X, 2 (default) the linear
+                             extrapolation 2 X_last - X_before (solves still run to sp->tol) */
 } lq_md_params;
 
 typedef struct {
@@ -329,7 +332,7 @@ typedef struct {
 } lq_md_stats;
 
 /* Defaults: beta 5.6, tau 1, 10 leapfrog steps, lambda 0.1931833275037836,
- * with fermions, FP64 force kernel. */
+ * with fermions, FP64 force kernel, chrono 2. */
 void lq_md_params_default(lq_md_params *p);
 
 /* Wilson gauge action S (may be NULL) and its su(3) force G (device
@@ -342,8 +345,9 @@ lq_status lq_gauge_force(lq_op *op, double beta, void *G, double *S, void *strea
  * are updated in place; the operator is set to U at the start and holds
  * the final U at the end.  phi: device complex128 [V/2][4][3] on the even
  * sites (fermion = 1).  Every force evaluation runs a solve with sp (the
- * solver of lq_pf_force) at the current U.  The force uses a workspace of
- * 4 V 144 bytes kept with the operator.  LQ_NOT_CONVERGED if some solve
+ * solver of lq_pf_force) at the current U, started from the guess chrono
+ * selects.  The force and the solution history use a workspace of
+ * 4 V 144 + 3 V 96 bytes kept with the operator.  LQ_NOT_CONVERGED if some solve
  * missed sp->tol (stats are filled).  The caller decides acceptance with
  * stats->dH. */
 lq_status lq_md_trajectory(lq_op *op, const lq_md_params *mp, const lq_solver_params *sp, void *U, void *P,

@@ -49,7 +49,7 @@ INTEGRATORS = {"leapfrog": LEAPFROG, "omelyan": OMELYAN}
 class MDParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("tau", ctypes.c_double), ("nsteps", ctypes.c_int),
                 ("integrator", ctypes.c_int), ("lam", ctypes.c_double), ("fermion", ctypes.c_int),
-                ("force_prec", ctypes.c_int)]
+                ("force_prec", ctypes.c_int), ("chrono", ctypes.c_int)]
 
 
 class MDStats(ctypes.Structure):

@@ -322,6 +322,7 @@ class MDParams:
     lam: float = 0.1931833275037836
     fermion: bool = True
     force_prec: str = "f64"
+    chrono: int = 2                  # initial guesses: 0 zero, 1 last solution, 2 linear extrapolation
 
     def to_c(self):
         p = _lib.MDParams()
@@ -332,6 +333,7 @@ class MDParams:
         p.lam = float(self.lam)
         p.fermion = int(bool(self.fermion))
         p.force_prec = _lib.PREC[self.force_prec]
+        p.chrono = int(self.chrono)
         return p
 
 

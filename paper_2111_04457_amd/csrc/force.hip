@@ -365,9 +365,11 @@ static hipError_t launch_force(const ForceArgs &f, int prec, int nl, hipStream_t
 
 using namespace lq;
 
-extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec,
-                                 const void *phi, void *dSdU, void *G, void *X_out, double *S,
-                                 lq_solve_stats *stats, void *stream)
+namespace lq {
+
+lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
+                         void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream,
+                         const void *X0)
 {
     if (!op || !sp || !phi) {
         set_error("lq_pf_force: null argument");
@@ -413,7 +415,9 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
         const std::vector<double> pn2 = norms2(c, phiv, c.sps);
         if (!std::isfinite(pn2[0])) throw Failure{LQ_ERR_NONFINITE, "phi is not finite"};
         // X = (M^dag M)^-1 phi
-        LQ_HIP(launch_zero(c.x64, s));
+        // initial guess: zero, or X0 (the even-odd variant)
+        if (X0 && eo) LQ_HIP(launch_pack_spinor(g, 0, 1, static_cast<const double *>(X0), c.x64, s));
+        else LQ_HIP(launch_zero(c.x64, s));
         lq_solver_params sp2 = *sp;
         const std::vector<double> target2{sp->tol * sp->tol * pn2[0]};
         const OuterStats os = defect_correction(c, sp2, true, phiv, target2);
@@ -546,4 +550,13 @@ extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int vari
         set_error(e.what());
         return LQ_ERR_STATE;
     }
+}
+
+}  // namespace lq
+
+extern "C" lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec,
+                                 const void *phi, void *dSdU, void *G, void *X_out, double *S,
+                                 lq_solve_stats *stats, void *stream)
+{
+    return lq::pf_force_guess(op, sp, variant, force_prec, phi, dSdU, G, X_out, S, stats, stream, nullptr);
 }

@@ -149,6 +149,13 @@ __global__ __launch_bounds__(128) void update_u_kernel(double *U, const double *
     }
 }
 
+// out = 2 a - b over n reals (linear extrapolation of two solutions).
+__global__ __launch_bounds__(256) void extrapolate_kernel(double *out, const double *a, const double *b, long n)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = 2.0 * a[i] - b[i];
+}
+
 // ------------------------------------------------------------------ host --
 
 namespace {
@@ -217,6 +224,11 @@ struct MD {
     int n_force = 0;
     long iters = 0;
     bool converged = true;
+    // solution history: buffer indices of the last and the one before, and
+    // how many of them hold solutions of this trajectory
+    int last = 0, before = 1, nhist = 0;
+
+    double *xbuf(int i) { return reinterpret_cast<double *>(op->md_X[i].ptr); }
 
     // G(U) at the operator's gauge field; the actions when want_s
     void force(bool want_s, double *Sg, double *Sf)
@@ -224,11 +236,28 @@ struct MD {
         ++n_force;
         double sf = 0.0;
         if (mp->fermion) {
+            // initial guess from the previous solutions; the new one goes to
+            // the buffer that is no longer needed
+            const long n = 24L * op->g.vh;
+            const double *x0 = nullptr;
+            if (mp->chrono >= 2 && nhist >= 2) {
+                extrapolate_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xbuf(2), xbuf(last), xbuf(before), n);
+                LQ_HIP(hipGetLastError());
+                x0 = xbuf(2);
+            } else if (mp->chrono >= 1 && nhist >= 1) {
+                x0 = xbuf(last);
+            }
+            const int out = nhist >= 1 ? before : last;
             lq_solve_stats st{};
-            const lq_status rc = lq_pf_force(op, sp, 0, (lq_prec)mp->force_prec, phi, nullptr, G, nullptr, &sf, &st, s);
+            const lq_status rc = pf_force_guess(op, sp, 0, (lq_prec)mp->force_prec, phi, nullptr, G,
+                                                mp->chrono ? xbuf(out) : nullptr, &sf, &st, s, x0);
             if (rc < 0) throw Failure{rc, std::string("pseudofermion force: ") + lq_last_error()};
             if (rc == LQ_NOT_CONVERGED) converged = false;
             iters += st.nconv;
+            if (mp->chrono) {
+                if (nhist >= 1) std::swap(last, before);
+                nhist = std::min(nhist + 1, 2);
+            }
         }
         const double sg = gauge_part(op, mp->beta, G, mp->fermion != 0, want_s, s);
         if (want_s) {
@@ -253,6 +282,7 @@ extern "C" void lq_md_params_default(lq_md_params *p)
     p->lambda = 0.1931833275037836;
     p->fermion = 1;
     p->force_prec = LQ_F64;
+    p->chrono = 2;
 }
 
 extern "C" lq_status lq_gauge_force(lq_op *op, double beta, void *G, double *S, void *stream)
@@ -293,9 +323,10 @@ extern "C" lq_status lq_md_trajectory(lq_op *op, const lq_md_params *mp, const l
         return LQ_ERR_ARG;
     }
     if (mp->nsteps < 1 || !std::isfinite(mp->tau) || !std::isfinite(mp->beta) || !std::isfinite(mp->lambda) ||
-        (mp->integrator != LQ_LEAPFROG && mp->integrator != LQ_OMELYAN) || (mp->fermion != 0 && mp->fermion != 1)) {
+        (mp->integrator != LQ_LEAPFROG && mp->integrator != LQ_OMELYAN) || (mp->fermion != 0 && mp->fermion != 1) ||
+        mp->chrono < 0 || mp->chrono > 2) {
         set_error("lq_md_trajectory: invalid parameters (nsteps >= 1, finite tau, beta and lambda, "
-                  "integrator LQ_LEAPFROG or LQ_OMELYAN, fermion 0 or 1)");
+                  "integrator LQ_LEAPFROG or LQ_OMELYAN, fermion 0 or 1, chrono 0, 1 or 2)");
         return LQ_ERR_ARG;
     }
     if (mp->fermion && (!sp || !phi)) {
@@ -314,6 +345,8 @@ extern "C" lq_status lq_md_trajectory(lq_op *op, const lq_md_params *mp, const l
         double *Ud = static_cast<double *>(U);
         double *Pd = static_cast<double *>(P);
         op->md_G.ensure(sizeof(double) * 18 * (size_t)nlinks(op->g));
+        if (mp->fermion && mp->chrono)
+            for (int i = 0; i < 3; ++i) op->md_X[i].ensure(sizeof(double) * 24 * (size_t)op->g.vh);
         MD md{op, mp, sp, phi, reinterpret_cast<double *>(op->md_G.ptr), s};
         {
             const lq_status st = lq_op_set_gauge(op, U, s);

@@ -67,6 +67,7 @@ struct lq_op {
     lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
     lq::Buf md_G;                        // molecular dynamics: the force on every link
     lq::Buf md_partial;                  // molecular dynamics: per-wavefront partial sums
+    lq::Buf md_X[3];                     // molecular dynamics: previous solutions and the next guess
     lq::Buf partial;                     // reduction partial sums
     lq::Buf solver_ws;                   // solver work vectors
     lq::Buf solver_sc;                   // solver scalars (device)

@@ -161,4 +161,11 @@ bool valid_solver_params(const lq_solver_params *sp, std::string &why);
 // |v|^2 per system of a field with sps slices per system.
 std::vector<double> norms2(SolveCtx &c, const FieldView &v, int sps);
 
+
+// The pseudofermion force of lq_pf_force with an initial guess X0 for the
+// even-odd solve (device complex128 [V/2][4][3], or null for zero).
+lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
+                         void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream,
+                         const void *X0);
+
 }  // namespace lq

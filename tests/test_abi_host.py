@@ -121,7 +121,7 @@ def test_md_entry_points_reject_bad_arguments(lib):
     from paper_2111_04457_amd import _lib
     mp = _lib.MDParams()
     lib.lq_md_params_default(ctypes.byref(mp))
-    assert mp.integrator == _lib.LEAPFROG and mp.nsteps == 10 and mp.fermion == 1
+    assert mp.integrator == _lib.LEAPFROG and mp.nsteps == 10 and mp.fermion == 1 and mp.chrono == 2
     assert abs(mp.lam - 0.1931833275037836) < 1e-16
     sp = _lib.SolverParams()
     lib.lq_solver_params_default(ctypes.byref(sp))
@@ -138,7 +138,7 @@ def test_md_entry_points_reject_bad_arguments(lib):
     if rc != 0:
         pytest.skip("no device: operator-level argument checks need a GPU")
     try:
-        for field, value in (("nsteps", 0), ("integrator", 7), ("beta", math.inf), ("fermion", 2)):
+        for field, value in (("nsteps", 0), ("integrator", 7), ("beta", math.inf), ("fermion", 2), ("chrono", 3)):
             bad = _lib.MDParams()
             lib.lq_md_params_default(ctypes.byref(bad))
             setattr(bad, field, value)

@@ -166,7 +166,7 @@ def test_md_operator_level_argument_checks(lq):
     sp = lq.SolverParams().to_c()
     st = _lib.MDStats()
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
-    for field, value in (("nsteps", 0), ("integrator", 7), ("beta", float("inf")), ("fermion", 2)):
+    for field, value in (("nsteps", 0), ("integrator", 7), ("beta", float("inf")), ("fermion", 2), ("chrono", 3)):
         bad = lq.MDParams().to_c()
         setattr(bad, field, value)
         assert lib.lq_md_trajectory(op.handle, ctypes.byref(bad), ctypes.byref(sp), dummy, dummy, dummy,
@@ -177,3 +177,24 @@ def test_md_operator_level_argument_checks(lq):
     assert lib.lq_gauge_force(op.handle, float("nan"), dummy, None, None) == -1
     assert lib.lq_gauge_force(op.handle, 5.5, dummy, None, None) == -2  # gauge field not set
     op.close()
+
+
+def test_chronological_guesses_same_trajectory_fewer_iterations(lq):
+    """Starting each force solve from the previous solution (chrono 1) or
+    the linear extrapolation of the last two (chrono 2) changes only the
+    solver's starting point: the trajectory agrees with zero starts to the
+    solver tolerance, with fewer iterations."""
+    dims = (8, 8, 8, 8)
+    U0 = gauge_exp(dims, 0.3, 5601)
+    P0 = random_su3_algebra(dims, 5602)
+    phi = gaussian_parity_spinor(dims, 5603)
+    res = {}
+    for chrono in (0, 1, 2):
+        md = lq.MDParams(beta=BETA, tau=0.3, nsteps=6, integrator="leapfrog", fermion=True, chrono=chrono)
+        res[chrono] = _run(lq, dims, U0, P0, phi, md, fermion=(0.12, 0.0))
+    announce("  iterations %s, dH %s" % ({c: r[2].iters for c, r in res.items()},
+                                         {c: r[2].dH for c, r in res.items()}))
+    for c in (1, 2):
+        assert rel_err(res[c][0], res[0][0]) < 1e-10 and rel_err(res[c][1], res[0][1]) < 1e-10
+        assert abs(res[c][2].dH - res[0][2].dH) < 1e-7
+    assert res[2][2].iters < res[1][2].iters < res[0][2].iters
