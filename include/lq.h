@@ -205,12 +205,16 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *                    of workgroups, else as 1); all precisions;
  *                    "xcd_remap_f64" / "_f32" / "_f16" per precision;
  *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
- *   "rhs_per_thread" 1|2  right-hand sides one thread of the hopping kernel
- *                    handles when several are applied together (each loaded
- *                    link is used for both; default 1, where the right-hand
- *                    sides of one site block run in adjacent workgroups and
- *                    share the links through the L2); per precision
- *                    "rhs_per_thread_f64" / "_f32" / "_f16".
+ *   "rhs_per_thread" 1|2|4  how the hopping kernel shares links between
+ *                    right-hand sides applied together: 1 (default) one per
+ *                    thread, the right-hand sides of one site block in
+ *                    adjacent workgroups sharing the links through the L2;
+ *                    2 two per thread (each loaded link used for both; not
+ *                    with the fused dot products, where 1 is used); 4 four
+ *                    per workgroup of 64 sites, one wavefront each, the
+ *                    links and clover blocks staged once in LDS (FP16 and
+ *                    FP32 storage with at least 4 right-hand sides, else 1);
+ *                    per precision "rhs_per_thread_f64" / "_f32" / "_f16".
  * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16".
  * LQ_ERR_ARG for an unknown name or value. */
 lq_status lq_op_set_option(lq_op *op, const char *name, int value);

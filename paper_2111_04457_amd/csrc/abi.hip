@@ -348,11 +348,11 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
     else if (n == "xcd_remap_f64" && order_ok) op->xcd_remap[F64] = value;
     else if (n == "xcd_remap_f32" && order_ok) op->xcd_remap[F32] = value;
     else if (n == "xcd_remap_f16" && order_ok) op->xcd_remap[F16] = value;
-    else if (n == "rhs_per_thread" && (value == 1 || value == 2))
+    else if (n == "rhs_per_thread" && (value == 1 || value == 2 || value == 4))
         op->rhs_per_thread[0] = op->rhs_per_thread[1] = op->rhs_per_thread[2] = value;
-    else if (n == "rhs_per_thread_f64" && (value == 1 || value == 2)) op->rhs_per_thread[F64] = value;
-    else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2)) op->rhs_per_thread[F32] = value;
-    else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2)) op->rhs_per_thread[F16] = value;
+    else if (n == "rhs_per_thread_f64" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F64] = value;
+    else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F32] = value;
+    else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F16] = value;
     else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
     else return arg_error("lq_op_set_option: unknown option or value: " + n);
     op->clear_graphs();

@@ -24,28 +24,44 @@ template <int P, int NL, int NR> struct HalfRaw {
     bool wrap;
 };
 
-template <int P, int NL, int NR, int K, bool NTL = false>
+// The link of half K of site cb (parity p_out): U_mu(x) forward, U_mu(x - mu) backward.
+template <int P, int NL, int K, bool NTL>
+__device__ __forceinline__ void load_half_link(const HopArgs &a, int cb, int nb, typename PT<P>::S *link)
+{
+    using S = typename PT<P>::S;
+    constexpr int MU = K / 2;
+    if constexpr ((K % 2) == 0)
+        load_planes<S, NL, NTL>(a.links + (long)(a.p_out * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), cb, a.g.vh,
+                                link);
+    else
+        load_planes<S, NL, NTL>(a.links + (long)((1 - a.p_out) * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), nb,
+                                a.g.vh, link);
+}
+
+// Neighbour index and wrap flag of half K.
+template <int K>
+__device__ __forceinline__ int half_neighbour(const HopArgs &a, const int c[4], bool &wrap)
+{
+    constexpr int MU = K / 2;
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    if constexpr ((K % 2) == 0) {
+        wrap = (d[MU] == a.g.L[MU] - 1);
+        d[MU] = wrap ? 0 : d[MU] + 1;
+    } else {
+        wrap = (d[MU] == 0);
+        d[MU] = wrap ? a.g.L[MU] - 1 : d[MU] - 1;
+    }
+    return cb_index(a.g, d);
+}
+
+// LINK = false: the link is not loaded (the caller reads it from LDS).
+template <int P, int NL, int NR, int K, bool NTL = false, bool LINK = true>
 __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict__ in, int nr, int cb, const int c[4],
                                        HalfRaw<P, NL, NR> &h)
 {
     using S = typename PT<P>::S;
-    constexpr int MU = K / 2;
-    constexpr bool FWD = (K % 2) == 0;
-    int d[4] = {c[0], c[1], c[2], c[3]};
-    int nb;
-    if constexpr (FWD) {
-        h.wrap = (d[MU] == a.g.L[MU] - 1);
-        d[MU] = h.wrap ? 0 : d[MU] + 1;
-        nb = cb_index(a.g, d);
-        load_planes<S, NL, NTL>(a.links + (long)(a.p_out * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), cb,
-                                a.g.vh, h.link);
-    } else {
-        h.wrap = (d[MU] == 0);
-        d[MU] = h.wrap ? a.g.L[MU] - 1 : d[MU] - 1;
-        nb = cb_index(a.g, d);
-        load_planes<S, NL, NTL>(a.links + (long)((1 - a.p_out) * 4 + MU) * Planes<S, NL>::field_bytes(a.g.vh), nb,
-                                a.g.vh, h.link);
-    }
+    const int nb = half_neighbour<K>(a, c, h.wrap);
+    if constexpr (LINK) load_half_link<P, NL, K, NTL>(a, cb, nb, h.link);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         // right-hand sides past the group's end re-read the last one (discarded)
@@ -57,9 +73,10 @@ __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict_
     }
 }
 
-template <int P, int NL, bool DAG, int NR, int K>
-__device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, NR> &h,
-                                        cx<typename PT<P>::R> (&acc)[NR][12])
+// Half K on the link at lnk[i * LS] (i = 0 .. NL - 1).
+template <int P, int NL, bool DAG, int NR, int K, int LS>
+__device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT<P>::S *lnk,
+                                             const HalfRaw<P, NL, NR> &h, cx<typename PT<P>::R> (&acc)[NR][12])
 {
     using R = typename PT<P>::R;
     constexpr int MU = K / 2;
@@ -68,7 +85,7 @@ __device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, N
     constexpr int SG = (FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1));
     cx<R> u[9];
 #pragma unroll
-    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)h.link[2 * i], (R)h.link[2 * i + 1]};
+    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)lnk[(2 * i) * LS], (R)lnk[(2 * i + 1) * LS]};
     if constexpr (NL == 12) {
         u[6] = conj(u[1] * u[5] - u[2] * u[4]);
         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -93,6 +110,13 @@ __device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, N
         su3_mul<!FWD>(u, hh, o);
         reconstruct<MU, SG>(acc[r], o);
     }
+}
+
+template <int P, int NL, bool DAG, int NR, int K>
+__device__ __forceinline__ void consume(const HopArgs &a, const HalfRaw<P, NL, NR> &h,
+                                        cx<typename PT<P>::R> (&acc)[NR][12])
+{
+    consume_link<P, NL, DAG, NR, K, 1>(a, h.link, h, acc);
 }
 
 // Pipeline step K: compute half K from slot K % PF, then refill that slot
@@ -151,6 +175,72 @@ template <int P, int CLOV> struct CachePolicy {
     static constexpr int value = (P == F16 && CLOV == 0) ? 2 : 3;
 };
 
+// The epilogue of one site: res = coef * acc, then the axpy / clover terms,
+// the store, and the fused dot products of the values as stored.
+template <int P, int CLOV, bool XPAY, int RED, int NR, int CACHE>
+__device__ __forceinline__ void epilogue(const HopArgs &a, int cb, int rhs0, int nr, const typename PT<P>::S *craw,
+                                         const cx<typename PT<P>::R> (&acc)[NR][12], double (&red0)[NR],
+                                         double (&red1)[NR], double (&red2)[NR])
+{
+    using R = typename PT<P>::R;
+    const R coef = (R)a.coef;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+            const int rhs = rhs0 + r;
+            Spinor<R> res;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[r][i];
+            if constexpr (XPAY) {
+                Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
+                if constexpr (CLOV == 1) clover_mul_raw(craw, yv);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
+            }
+            if constexpr (CLOV == 2) clover_mul_raw(craw, res);
+            store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
+            if constexpr (RED != 0) {
+                // <w, out> (and |out|^2) of the values as stored
+                const Spinor<R> sv = as_stored<P>(res);
+                const Spinor<R> wv = load_spinor<P>(a.w + rhs * a.w_rs, cb, a.w_n);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    const cx<R> q = cmulc(wv.c[i], sv.c[i]);
+                    red0[r] += (double)q.re;
+                    red1[r] += (double)q.im;
+                    if constexpr (RED == 3) red2[r] += (double)norm2(sv.c[i]);
+                }
+            }
+        }
+    }
+    }
+
+// One partial per wavefront of 64 consecutive sites, indexed by its first
+// site (wave = that site / 64): the sums depend neither on the workgroup
+// size nor on the order in which workgroups run.
+template <int RED, int NR>
+__device__ __forceinline__ void write_partials(const HopArgs &a, long wave, int rhs0, int nr, double (&red0)[NR],
+                                               double (&red1)[NR], double (&red2)[NR])
+{
+    constexpr int K = RED == 2 ? 2 : 3;
+    const long nw = ((long)a.g.vh + 63) / 64;
+    const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+            const double s0 = wave_sum(red0[r]);
+            const double s1 = wave_sum(red1[r]);
+            const double s2 = RED == 3 ? wave_sum(red2[r]) : 0.0;
+            if (lead && wave < nw) {
+                double *o = a.partial + ((long)(rhs0 + r) * nw + wave) * K;
+                o[0] = s0;
+                o[1] = s1;
+                if constexpr (K == 3) o[2] = s2;
+            }
+        }
+    }
+}
+
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR, int PF = Prefetch<P, NR>::value,
           int CACHE = CachePolicy<P, CLOV>::value>
 __device__ __forceinline__ void hop_body(const HopArgs &a)
@@ -200,59 +290,11 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
         pipeline<P, NL, DAG, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot, acc);
         S craw[CLOV ? 72 : 1];
         if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
-        const R coef = (R)a.coef;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r < nr) {
-                const int rhs = rhs0 + r;
-                Spinor<R> res;
-#pragma unroll
-                for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[r][i];
-                if constexpr (XPAY) {
-                    Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
-                    if constexpr (CLOV == 1) clover_mul_raw(craw, yv);
-#pragma unroll
-                    for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
-                }
-                if constexpr (CLOV == 2) clover_mul_raw(craw, res);
-                store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
-                if constexpr (RED != 0) {
-                    // <w, out> (and |out|^2) of the values as stored
-                    const Spinor<R> sv = as_stored<P>(res);
-                    const Spinor<R> wv = load_spinor<P>(a.w + rhs * a.w_rs, cb, a.w_n);
-#pragma unroll
-                    for (int i = 0; i < 12; ++i) {
-                        const cx<R> q = cmulc(wv.c[i], sv.c[i]);
-                        red0[r] += (double)q.re;
-                        red1[r] += (double)q.im;
-                        if constexpr (RED == 3) red2[r] += (double)norm2(sv.c[i]);
-                    }
-                }
-            }
-        }
+        epilogue<P, CLOV, XPAY, RED, NR, CACHE>(a, cb, rhs0, nr, craw, acc, red0, red1, red2);
     }
     if constexpr (RED != 0) {
-        // one partial per wavefront of 64 consecutive sites, indexed by its
-        // first site: the sums depend neither on the workgroup size nor on
-        // the order in which workgroups run
-        constexpr int K = RED == 2 ? 2 : 3;
-        const long nw = ((long)a.g.vh + 63) / 64;
         const long wave = ((long)sblk * NT + (threadIdx.x & ~63)) / 64;
-        const bool lead = (threadIdx.x & 63) == 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r < nr) {
-                const double s0 = wave_sum(red0[r]);
-                const double s1 = wave_sum(red1[r]);
-                const double s2 = RED == 3 ? wave_sum(red2[r]) : 0.0;
-                if (lead && wave < nw) {
-                    double *o = a.partial + ((long)(rhs0 + r) * nw + wave) * K;
-                    o[0] = s0;
-                    o[1] = s1;
-                    if constexpr (K == 3) o[2] = s2;
-                }
-            }
-        }
+        write_partials<RED, NR>(a, wave, rhs0, nr, red0, red1, red2);
     }
 }
 
@@ -260,6 +302,134 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR>
 __global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
 {
     hop_body<P, NL, DAG, CLOV, XPAY, RED, NT, NR>(a);
+}
+
+// ------------------------------------------- right-hand sides sharing LDS --
+//
+// Several right-hand sides per workgroup: 64 sites x R right-hand sides, one
+// wavefront per right-hand side.  The waves load the eight links of the 64
+// sites (the directions split between them) and the sites' clover blocks
+// into LDS once; every wave then runs the pipeline of hop_body on its own
+// right-hand side's neighbour spinors, with the links read from LDS.  The
+// operations are those of hop_body, so the results are the same bits; the
+// links and clover blocks are read from memory once per R right-hand sides.
+
+template <int P, int NL, int K, int R, bool NTL>
+__device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, int cb, const int c[4],
+                                            typename PT<P>::S (*lk)[NL][64])
+{
+    using S = typename PT<P>::S;
+    if constexpr (K < 8) {
+        if (K % R == w) {
+            bool wrap;
+            const int nb = half_neighbour<K>(a, c, wrap);
+            S raw[NL];
+            load_half_link<P, NL, K, NTL>(a, cb, nb, raw);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) lk[K][i][lane] = raw[i];
+        }
+        stage_links<P, NL, K + 1, R, NTL>(a, w, lane, cb, c, lk);
+    }
+}
+
+template <int P, int NL, int PF, int K>
+__device__ __forceinline__ void prologue_sp(const HopArgs &a, const char *__restrict__ in, int cb, const int c[4],
+                                            HalfRaw<P, NL, 1> (&slot)[PF])
+{
+    if constexpr (K < PF) {
+        gather<P, NL, 1, K, false, false>(a, in, 1, cb, c, slot[K]);
+        prologue_sp<P, NL, PF, K + 1>(a, in, cb, c, slot);
+    }
+}
+
+template <int P, int NL, bool DAG, int PF, int K>
+__device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__restrict__ in, int lane, int cb,
+                                            const int c[4], typename PT<P>::S (*lk)[NL][64],
+                                            HalfRaw<P, NL, 1> (&slot)[PF], cx<typename PT<P>::R> (&acc)[1][12])
+{
+    if constexpr (K < 8) {
+        consume_link<P, NL, DAG, 1, K, 64>(a, &lk[K][0][lane], slot[K % PF], acc);
+        if constexpr (K + PF < 8) gather<P, NL, 1, K + PF, false, false>(a, in, 1, cb, c, slot[K % PF]);
+        pipeline_sp<P, NL, DAG, PF, K + 1>(a, in, lane, cb, c, lk, slot, acc);
+    }
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R, int PF = Prefetch<P, 1>::value,
+          int CACHE = CachePolicy<P, CLOV>::value>
+__global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
+{
+    using Rt = typename PT<P>::R;
+    using S = typename PT<P>::S;
+    __shared__ S lk[8][NL][64];
+    __shared__ S lc[CLOV ? 72 : 1][64];
+    // tiles (site block of 64, group of R right-hand sides), XCD-aware as in hop_body
+    const int nbs = (a.g.vh + 63) / 64;
+    const int ngr = (a.nrhs + R - 1) / R;
+    const int total = nbs * ngr;
+    const int full = a.xcd_remap ? (total / 8) * 8 : 0;
+    const int id = blockIdx.x;
+    const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
+    const int k = t / ngr;
+    const int rhs0 = (t - k * ngr) * R;
+    const int nrg = min(R, a.nrhs - rhs0);
+    // a group whose right-hand sides are all frozen exits at once (uniformly)
+    if (a.mask) {
+        bool any = false;
+        for (int r = 0; r < nrg; ++r) {
+            const double *m = a.mask + (long)(rhs0 + r) * a.mask_stride;
+            any = any || (m[a.mask_off0] == 0.0 && m[a.mask_off1] == 0.0);
+        }
+        if (!any) return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int cb = k * 64 + lane;
+    const bool site_ok = cb < a.g.vh;
+    const bool rhs_ok = w < nrg;
+    const int rhs = rhs0 + w;
+    int c[4] = {0, 0, 0, 0};
+    if (site_ok) cb_coords(a.g, a.p_out, cb, c);
+    const char *in = a.in + (long)(rhs_ok ? rhs : rhs0) * a.in_rs;
+    HalfRaw<P, NL, 1> slot[PF];
+    // the first neighbour spinors are requested before the staging barrier
+    if (site_ok && rhs_ok) prologue_sp<P, NL, PF, 0>(a, in, cb, c, slot);
+    if (site_ok) {
+        stage_links<P, NL, 0, R, (CACHE & 1) != 0>(a, w, lane, cb, c, lk);
+        if constexpr (CLOV != 0) {
+            if (w == R - 1) {
+                S raw[72];
+                load_planes<S, 72>(a.clov, cb, a.g.vh, raw);
+#pragma unroll
+                for (int i = 0; i < 72; ++i) lc[i][lane] = raw[i];
+            }
+        }
+    }
+    __syncthreads();
+    double red0[1] = {0.0}, red1[1] = {0.0}, red2[1] = {0.0};
+    if (site_ok && rhs_ok) {
+        cx<Rt> acc[1][12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc[0][i] = cx<Rt>{0, 0};
+        pipeline_sp<P, NL, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
+        S craw[CLOV ? 72 : 1];
+        if constexpr (CLOV != 0) {
+#pragma unroll
+            for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
+        }
+        epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, rhs, 1, craw, acc, red0, red1, red2);
+    }
+    if constexpr (RED != 0) {
+        if (rhs_ok) write_partials<RED, 1>(a, k, rhs, 1, red0, red1, red2);
+    }
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
+static hipError_t launch_shared(const HopArgs &a, hipStream_t s)
+{
+    const int ngr = (a.nrhs + R - 1) / R;
+    const dim3 grid(hop_blocks(a.g.vh, 64) * ngr);
+    hop_shared_kernel<P, NL, DAG, CLOV, XPAY, RED, R><<<grid, 64 * R, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NR>
@@ -281,6 +451,11 @@ static hipError_t launch_nt(const HopArgs &a, int block, hipStream_t s)
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
 static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 {
+    // nr == 4: four right-hand sides per workgroup sharing links in LDS
+    // (binary16 and FP32 storage; the FP64 blocks would not fit)
+    if constexpr (P != F64) {
+        if (nr == 4) return launch_shared<P, NL, DAG, CLOV, XPAY, RED, 4>(a, s);
+    }
     if constexpr (RED == 0) {
         if (nr == 2) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 2>(a, block, s);
     }

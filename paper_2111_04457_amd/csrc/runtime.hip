@@ -87,7 +87,14 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         op->partial.ensure((size_t)((g.vh + 63) / 64) * in.nrhs * 3 * sizeof(double));
         a.partial = reinterpret_cast<double *>(op->partial.ptr);
     }
-    const int nr = (red == 0 && in.nrhs > 1) ? op->rhs_per_thread[prec] : 1;
+    // right-hand sides per thread (2, no reductions), or 4 per workgroup
+    // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)
+    int nr = 1;
+    if (in.nrhs > 1) {
+        const int want = op->rhs_per_thread[prec];
+        if (want == 2 && red == 0) nr = 2;
+        else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;
+    }
     LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, nr, block, s));
 }
 

@@ -169,10 +169,13 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
                 const int save_nr = op->rhs_per_thread[prec];
-                const std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2} : std::vector<int>{save_nr};
+                std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2} : std::vector<int>{save_nr};
+                if (nrhs >= 4 && prec != F64) nrs.push_back(4);
                 for (int nrt : nrs)
                 for (int block : {256, 128, 64}) {
                     for (int remap : {2, 1, 0}) {
+                        // four right-hand sides per workgroup: 256 threads, plain or XCD order
+                        if (nrt == 4 && (block != 64 || remap == 2)) continue;
                         op->hop_block[prec] = block;
                         op->xcd_remap[prec] = remap;
                         op->rhs_per_thread[prec] = nrt;
@@ -213,7 +216,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             }
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
-            if (nrhs > 1 && (best.nr == 1 || best.nr == 2)) op->rhs_per_thread[prec] = best.nr;
+            if (nrhs > 1 && (best.nr == 1 || best.nr == 2 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
                 << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";
