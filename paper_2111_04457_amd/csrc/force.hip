@@ -240,17 +240,34 @@ __device__ __forceinline__ M3 gamma_at(const Geom &g, const char *gam, const int
 // R = G0 A B C + A G1 B C + A B G2 C + A B C G3: the loop product that follows
 // a link (A, B, C the other three factors in loop order), with the insertion
 // of each corner after the link (G0 first, G3 at the link's own start).
-__device__ __forceinline__ M3 loop_insert(const M3 &A, const M3 &B, const M3 &C, const M3 &G0, const M3 &G1,
-                                          const M3 &G2, const M3 &G3)
+// A factor of a loop: the link U_dir(c), conjugate-transposed when dg.
+struct LoopFactor {
+    const int *c;
+    int dir;
+    bool dg;
+};
+
+__device__ __forceinline__ M3 factor_at(const Geom &g, const char *links64, const LoopFactor &f)
 {
-    const M3 AB = mul(A, B);
-    const M3 ABC = mul(AB, C);
-    const M3 BC = mul(B, C);
-    M3 r = mul(G0, ABC);
-    r = add(r, mul(A, mul(G1, BC)));
-    r = add(r, mul(AB, mul(G2, C)));
-    r = add(r, mul(ABC, G3));
-    return r;
+    const M3 u = link_at(g, links64, f.c, f.dir);
+    return f.dg ? dag(u) : u;
+}
+
+// In Horner form, S = G0 A + A G1;  S = S B + (A B) G2;  S = S C + (A B C) G3,
+// each factor and insertion loaded when it is needed (few matrices live).
+__device__ __forceinline__ M3 loop_insert(const Geom &g, const char *links64, const char *gam, int pid,
+                                          const LoopFactor &fa, const LoopFactor &fb, const LoopFactor &fc,
+                                          const int *c0, const int *c1, const int *c2, const int *c3)
+{
+    const M3 A = factor_at(g, links64, fa);
+    M3 S = add(mul(gamma_at(g, gam, c0, pid), A), mul(A, gamma_at(g, gam, c1, pid)));
+    const M3 B = factor_at(g, links64, fb);
+    M3 Q = mul(A, B);
+    S = add(mul(S, B), mul(Q, gamma_at(g, gam, c2, pid)));
+    const M3 C = factor_at(g, links64, fc);
+    Q = mul(Q, C);
+    S = add(mul(S, C), mul(Q, gamma_at(g, gam, c3, pid)));
+    return S;
 }
 
 struct CloverForceArgs {
@@ -274,6 +291,9 @@ __global__ __launch_bounds__(128) void clover_force_kernel(CloverForceArgs f)
     const long lex = y[0] + (long)g.L[0] * (y[1] + (long)g.L[1] * (y[2] + (long)g.L[2] * y[3]));
     M3 m;
     for (int i = 0; i < 9; ++i) m.e[i] = cx<double>{0, 0};
+    // one plane at a time: unrolled, the compiler would hoist the loads of all
+    // three planes and run out of registers
+#pragma unroll 1
     for (int sg = 0; sg < 4; ++sg) {
         if (sg == rho) continue;
         const int a = rho < sg ? rho : sg, b = rho < sg ? sg : rho;
@@ -284,37 +304,29 @@ __global__ __launch_bounds__(128) void clover_force_kernel(CloverForceArgs f)
             shift(g, y, a, 1, b, 0, c2);
             shift(g, y, a, 1, b, 1, c3);
             shift(g, y, a, 0, b, 1, c4);
-            m = add(m, loop_insert(link_at(g, f.links64, c2, b), dag(link_at(g, f.links64, c4, a)),
-                                   dag(link_at(g, f.links64, y, b)), gamma_at(g, f.gam, c2, pid),
-                                   gamma_at(g, f.gam, c3, pid), gamma_at(g, f.gam, c4, pid),
-                                   gamma_at(g, f.gam, y, pid)));
+            m = add(m, loop_insert(g, f.links64, f.gam, pid, {c2, b, false}, {c4, a, true}, {y, b, true}, c2, c3, c4,
+                                   y));
             // plaquette based at z = y - b, walking the link backwards:
             // U_a(z) U_b(z+a) U_a(y)^dag U_b(z)^dag
             shift(g, y, a, 0, b, -1, c1);  // z
             shift(g, y, a, 1, b, -1, c2);  // z + a
             shift(g, y, a, 1, b, 0, c3);   // y + a
-            m = add(m, dag(loop_insert(dag(link_at(g, f.links64, c1, b)), link_at(g, f.links64, c1, a),
-                                       link_at(g, f.links64, c2, b), gamma_at(g, f.gam, y, pid),
-                                       gamma_at(g, f.gam, c1, pid), gamma_at(g, f.gam, c2, pid),
-                                       gamma_at(g, f.gam, c3, pid))));
+            m = add(m, dag(loop_insert(g, f.links64, f.gam, pid, {c1, b, true}, {c1, a, false}, {c2, b, false}, y,
+                                       c1, c2, c3)));
         } else {
             // plaquette based at y, walking the link backwards:
             // U_a(y) U_b(y+a) U_a(y+b)^dag U_b(y)^dag
             shift(g, y, a, 1, b, 0, c2);
             shift(g, y, a, 1, b, 1, c3);
             shift(g, y, a, 0, b, 1, c4);
-            m = add(m, dag(loop_insert(link_at(g, f.links64, y, a), link_at(g, f.links64, c2, b),
-                                       dag(link_at(g, f.links64, c4, a)), gamma_at(g, f.gam, y, pid),
-                                       gamma_at(g, f.gam, c2, pid), gamma_at(g, f.gam, c3, pid),
-                                       gamma_at(g, f.gam, c4, pid))));
+            m = add(m, dag(loop_insert(g, f.links64, f.gam, pid, {y, a, false}, {c2, b, false}, {c4, a, true}, y,
+                                       c2, c3, c4)));
             // plaquette based at z = y - a: U_a(z) U_b(y) [the link] U_a(z+b)^dag U_b(z)^dag
             shift(g, y, a, -1, b, 0, c1);  // z
             shift(g, y, a, 0, b, 1, c3);   // y + b
             shift(g, y, a, -1, b, 1, c4);  // z + b
-            m = add(m, loop_insert(dag(link_at(g, f.links64, c4, a)), dag(link_at(g, f.links64, c1, b)),
-                                   link_at(g, f.links64, c1, a), gamma_at(g, f.gam, c3, pid),
-                                   gamma_at(g, f.gam, c4, pid), gamma_at(g, f.gam, c1, pid),
-                                   gamma_at(g, f.gam, y, pid)));
+            m = add(m, loop_insert(g, f.links64, f.gam, pid, {c4, a, true}, {c1, b, true}, {c1, a, false}, c3, c4,
+                                   c1, y));
         }
     }
     if (f.M) {

@@ -50,22 +50,24 @@ __device__ __forceinline__ void store_minus_ta(const M3 &bm, double scale, doubl
         }
 }
 
-// One site per thread (grid: site blocks x parity), all four directions.
-// G (lex, [V][4][18], may be null) receives (or is added) the gauge force;
-// partial[p * nw + wave] the wavefront's sum of Re tr(U_mu(x) A_mu(x)).
+// One link per thread (grid: site blocks x parity x direction).  G (lex,
+// [V][4][18], may be null) receives (or is added) the gauge force;
+// partial[(mu * 2 + p) * nw + wave] the wavefront's sum of Re tr(U_mu(x) A_mu(x)).
 __global__ __launch_bounds__(128) void gauge_force_kernel(Geom g, const char *links64, double beta, double *G,
                                                           int accumulate, double *partial)
 {
     const int cb = blockIdx.x * 128 + threadIdx.x;
     const int p = blockIdx.y;
+    const int mu = blockIdx.z;
     double retr = 0.0;
     if (cb < g.vh) {
         int x[4];
         cb_coords(g, p, cb, x);
         const long lex = x[0] + (long)g.L[0] * (x[1] + (long)g.L[1] * (x[2] + (long)g.L[2] * x[3]));
-        for (int mu = 0; mu < 4; ++mu) {
+        {
             M3 A;
             for (int i = 0; i < 9; ++i) A.e[i] = cx<double>{0, 0};
+#pragma unroll 1
             for (int nu = 0; nu < 4; ++nu) {
                 if (nu == mu) continue;
                 int xm[4], xn[4], xmn[4];
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(128) void gauge_force_kernel(Geom g, const char *li
         }
     }
     const double s = wave_sum(retr);
-    if ((threadIdx.x & 63) == 0 && cb < g.vh) partial[(long)p * ((g.vh + 63) / 64) + (cb >> 6)] = s;
+    if ((threadIdx.x & 63) == 0 && cb < g.vh) partial[(long)(mu * 2 + p) * ((g.vh + 63) / 64) + (cb >> 6)] = s;
 }
 
 // 1/2 sum |P|^2 per wavefront of 64 links (P: [nlinks][18] reals).
@@ -178,20 +180,20 @@ double gauge_part(lq_op *op, double beta, double *G, bool accumulate, bool want_
 {
     const Geom &g = op->g;
     const long nw = (g.vh + 63) / 64;
-    op->md_partial.ensure(sizeof(double) * (size_t)std::max<long>(2 * nw, (nlinks(g) + 63) / 64));
+    op->md_partial.ensure(sizeof(double) * (size_t)std::max<long>(8 * nw, (nlinks(g) + 63) / 64));
     double *part = reinterpret_cast<double *>(op->md_partial.ptr);
-    gauge_force_kernel<<<dim3((unsigned)((g.vh + 127) / 128), 2), 128, 0, s>>>(g, op->links[F64].ptr, beta, G,
-                                                                                 accumulate ? 1 : 0, part);
+    gauge_force_kernel<<<dim3((unsigned)((g.vh + 127) / 128), 2, 4), 128, 0, s>>>(g, op->links[F64].ptr, beta, G,
+                                                                                    accumulate ? 1 : 0, part);
     LQ_HIP(hipGetLastError());
     if (!want_s) return 0.0;
-    const double retr = host_sum(part, 2 * nw, s);
+    const double retr = host_sum(part, 8 * nw, s);
     return beta * (6.0 * 2.0 * g.vh - retr / 12.0);
 }
 
 double kinetic(lq_op *op, const double *P, hipStream_t s)
 {
     const long n = nlinks(op->g);
-    op->md_partial.ensure(sizeof(double) * (size_t)std::max<long>(2 * ((op->g.vh + 63) / 64), (n + 63) / 64));
+    op->md_partial.ensure(sizeof(double) * (size_t)std::max<long>(8 * ((op->g.vh + 63) / 64), (n + 63) / 64));
     double *part = reinterpret_cast<double *>(op->md_partial.ptr);
     kinetic_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, n, part);
     LQ_HIP(hipGetLastError());
