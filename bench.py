@@ -3,8 +3,9 @@
 One step = one complete solve D x = b to a true FP64 residual of 1e-10 on
 the 32^3 x 64 Wilson-clover lattice (links exp(i 0.5 H), kappa 0.1355,
 c_sw 1.7, antiperiodic in time): FP16-stored links and spinors with FP32
-arithmetic in the inner BiCGStab, FP64 defect correction outside, even-odd
-prepare / reconstruct and the final full-lattice residual included.
+arithmetic in the inner BiCGStab (on the A_ee^-1-preconditioned Schur
+operator by default), FP64 defect correction of M x = b outside, even-odd
+prepare / reconstruct and the final residual included.
 
 Printed: one JSON line.  `value` is the whole-step dslash throughput: the
 algorithmic bytes of every hopping-term apply the solve performed (links,
@@ -89,11 +90,13 @@ def _graph_time_us(torch, fn, reps):
     return 1e3 * e0.elapsed_time(e1) / reps
 
 
-def _kernels(lq, torch, op, b_d, V, recon, reps):
+def _kernels(lq, torch, op, b_d, V, recon, reps, left):
     """Per-kernel figures on resident packed fields (no host work inside the
-    timed region): the Schur operator of the solver (two fused hop kernels)
-    in FP16 / FP32 / FP64 at the tuned launch shape, and the plain hopping
-    term (even -> odd) at each workgroup size."""
+    timed region): the Schur operator of the solver (two fused hop kernels;
+    its A_ee^-1-preconditioned form when left) in FP16 / FP32 / FP64 at the
+    tuned launch shape, and the plain hopping term (even -> odd) at each
+    workgroup size."""
+    kind = "schur_left" if left else "schur"
     kern = {}
     roof = None
     bps_schur = {}
@@ -101,10 +104,11 @@ def _kernels(lq, torch, op, b_d, V, recon, reps):
         fin = lq.Field(op, prec)
         fout = lq.Field(op, prec)
         fin.load(b_d.reshape(-1, 4, 3)[: V // 2].contiguous())
-        us = _graph_time_us(torch, lambda: lq.apply_field(op, "schur", fout, fin), reps)
+        us = _graph_time_us(torch, lambda: lq.apply_field(op, kind, fout, fin), reps)
         b1, f1 = op.traffic(prec, 1, clover=False)
         b2, f2 = op.traffic(prec, 1, clover=True)
-        # kernel 1: clover-inverse epilogue (+ clover block); kernel 2: clover on y, axpy (+ clover, + y)
+        # kernel 1: clover-inverse epilogue (+ clover block); kernel 2: clover on y (or, preconditioned,
+        # A_ee^-1 on the hopping term) and the axpy (+ clover block, + y)
         spinor = {"f16": 52.0, "f32": 96.0, "f64": 192.0}[prec]
         bps = (b2) + (b2 + spinor)
         bps_schur[prec] = bps
@@ -116,8 +120,11 @@ def _kernels(lq, torch, op, b_d, V, recon, reps):
             gbs = kern["schur_f16_GBs"]
             roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                     "traffic": None,
-                    "kernel": "Schur operator, FP16 storage, %d-real links: hop_kernel<f16,%d,clov=inv> + "
-                              "hop_kernel<f16,%d,clov=y,xpay> (%d threads)" % (recon, recon, recon, blk),
+                    "kernel": ("A_ee^-1-preconditioned Schur operator, FP16 storage, %d-real links: "
+                               "hop_kernel<f16,%d,clov=inv> + hop_kernel<f16,%d,clov=inv on H,xpay> (%d threads)"
+                               if left else
+                               "Schur operator, FP16 storage, %d-real links: hop_kernel<f16,%d,clov=inv> + "
+                               "hop_kernel<f16,%d,clov=y,xpay> (%d threads)") % (recon, recon, recon, blk),
                     "bytes_per_launch": bps * (V // 2), "avg_launch_us": us}
         tuned_blk = op.get_option("hop_block_" + prec)
         best = None
@@ -151,7 +158,8 @@ def _kernels(lq, torch, op, b_d, V, recon, reps):
 
 
 def _extras(lq, torch):
-    """The other workloads, each timed once after a warm-up call:
+    """The other workloads, each timed once after a warm-up call (mixed solves
+    with the A_ee^-1-preconditioned inner system):
     - the 12 spin-colour point sources of one propagator on 24^3x48 (clover,
       kappa 0.135, c_sw 1.7) as one 12-RHS solve vs 12 single solves;
     - a ragged batch 8^4, 12^4, 16^3x32, 20^3x40 (4 Gaussian sources each)
@@ -164,7 +172,7 @@ def _extras(lq, torch):
     from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_parity_spinor, gaussian_spinor,
                                 point_sources, workload_gauge, workload_source)
     out = {}
-    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=10)
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=10, left_precond=True)
     w = WORKLOADS["clover_24x24x24x48"]
     d = w["dims"]
     op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
@@ -217,7 +225,8 @@ def _extras(lq, torch):
     x64 = None
     for name, solver, inner, itol in (("fp64", "bicgstab", "f64", 1e-5), ("fp64_cgne", "cgne", "f64", 1e-5),
                                       ("mixed_f32", "bicgstab", "f32", 1e-5), ("mixed_f16", "bicgstab", "f16", 5e-3)):
-        p1 = lq.SolverParams(solver=solver, tol=1e-10, inner=inner, inner_tol=itol, check_every=10)
+        p1 = lq.SolverParams(solver=solver, tol=1e-10, inner=inner, inner_tol=itol, check_every=10,
+                             left_precond=inner != "f64")
         op.solve(b1, "D", p1)
         (xs, st1), ms = _timed(torch, lambda: op.solve(b1, "D", p1))
         out["clover_16x16x16x32_%s_ms" % name] = ms
@@ -312,6 +321,9 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="relative residual of each inner solve (default 5e-3 for f16, 1e-5 otherwise)")
+    ap.add_argument("--left-precond", action=argparse.BooleanOptionalAction, default=True,
+                    help="inner BiCGStab on A_ee^-1 M, the A_ee^-1-preconditioned Schur form (default on; "
+                         "the plain form is timed beside it)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32-inner reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -370,13 +382,14 @@ def main(argv=None):
         print("bench: tuned in %.1f s: %s" % (time.time() - t_tune, json.dumps(tune)), file=sys.stderr, flush=True)
 
     if args.kernels_only:
-        kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps)
+        kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps, args.left_precond)
         print(json.dumps({"kernels": kern, "roofline": roof}), flush=True)
         op.close()
         return 0
 
     inner_tol = args.inner_tol or {"f16": 5e-3, "f32": 1e-5, "f64": 1e-5}[args.inner]
-    prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10)
+    prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10,
+                          left_precond=args.left_precond)
 
     for _ in range(args.warmup):
         op.solve(b_d, "D", prm)
@@ -406,13 +419,18 @@ def main(argv=None):
            "mixed_%s_outer" % args.inner: stats[-1].nouter, "mixed_%s_diff" % args.inner: stats[-1].diff}
     if not args.no_compare:
         refs = {}
-        runs = [("f64", args.solver, "fp64"), ("f32", args.solver, "mixed_f32")]
+        runs = [("f64", args.solver, "fp64", False), ("f32", args.solver, "mixed_f32", False)]
         if args.solver == "bicgstab":
-            runs.append(("f64", "cgne", "fp64_cgne"))
-        for inner, solver, name in runs:
-            if inner == args.inner and solver == args.solver:
+            runs.append(("f64", "cgne", "fp64_cgne", False))
+            # the same mixed solve with inner BiCGStab on A_ee^-1 M (or without, if the main run used it)
+            runs.append((args.inner, "bicgstab", "mixed_%s_%s" % (args.inner, "plain" if args.left_precond else "left"),
+                         not args.left_precond))
+        for inner, solver, name, left in runs:
+            if inner == args.inner and solver == args.solver and left == args.left_precond:
                 continue
-            p2 = lq.SolverParams(solver=solver, tol=args.tol, inner=inner, inner_tol=1e-5, check_every=10)
+            p2 = lq.SolverParams(solver=solver, tol=args.tol, inner=inner,
+                                 inner_tol=inner_tol if inner == args.inner else 1e-5, check_every=10,
+                                 left_precond=left)
             op.solve(b_d, "D", p2)  # captures this solver's graphs
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -421,7 +439,7 @@ def main(argv=None):
             tts["%s_ms" % name] = 1e3 * (time.perf_counter() - ta)
             tts["%s_iters" % name] = sr[0].nconv
             tts["%s_diff" % name] = sr[0].diff
-            if solver == args.solver:
+            if solver == args.solver and not left:
                 refs[inner] = xr
         if "f64" in refs:
             x64 = refs["f64"]
@@ -429,7 +447,7 @@ def main(argv=None):
             tts["speedup_vs_fp64"] = tts["fp64_ms"] / ms_per_step
         print("bench: reference solves %s" % json.dumps(tts), file=sys.stderr, flush=True)
 
-    kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps)
+    kern, roof = _kernels(lq, torch, op, b_d, V, args.recon, args.kernel_reps, args.left_precond)
     if roof is not None:
         roof["traffic"] = _traffic_from_profile(roof["kernel"])
     print("bench: kernels %s" % json.dumps(kern), file=sys.stderr, flush=True)
@@ -485,7 +503,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "kappa": w["kappa"], "csw": w["csw"],
                    "links": "exp(i*%.1f*H)" % w["eps"], "solver": args.solver, "inner": args.inner,
-                   "link_recon": args.recon, "tol": args.tol, "parallelism": "single-gpu"},
+                   "link_recon": args.recon, "tol": args.tol, "left_precond": bool(args.left_precond),
+                   "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_solution": tts,

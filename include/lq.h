@@ -99,7 +99,8 @@ typedef enum {
     LQ_HOP_OE_DAG = 9,    /* (H_eo)^dag (even -> odd)              */
     LQ_CLOVER_E = 10,     /* A_ee                                  even -> even */
     LQ_CLOVER_O = 11,     /* A_oo                                  odd -> odd */
-    LQ_CLOVER_INV_O = 12  /* A_oo^-1                               odd -> odd */
+    LQ_CLOVER_INV_O = 12, /* A_oo^-1                               odd -> odd */
+    LQ_SCHUR_LEFT = 13    /* A_ee^-1 M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe  even -> even */
 } lq_kind;
 
 typedef enum { LQ_CGNE = 0, LQ_BICGSTAB = 1 } lq_solver_kind;
@@ -126,6 +127,9 @@ typedef struct {
     int max_outer;        /* cap on FP64 defect-correction steps */
     int check_every;      /* inner iterations between host convergence checks */
     int even_odd;         /* 1: solve the Schur system (default); 0: full lattice (CGNE only) */
+    int left_precond;     /* 1: each inner BiCGStab solve of the even-odd system runs on
+                             A_ee^-1 M with the source A_ee^-1 r (clover only; the outer
+                             FP64 loop keeps the residual of M x = b); default 0 */
 } lq_solver_params;
 
 /* Per-system solve statistics (nconv and diff of Fig. 1's invert). */

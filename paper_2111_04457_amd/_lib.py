@@ -19,7 +19,8 @@ F64, F32, F16 = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16": F16}
 
 KINDS = {"D": 0, "Ddag": 1, "DdagD": 2, "schur": 3, "schur_dag": 4, "schur_normal": 5, "hop_eo": 6,
-         "hop_oe": 7, "hop_eo_dag": 8, "hop_oe_dag": 9, "clover_e": 10, "clover_o": 11, "clover_inv_o": 12}
+         "hop_oe": 7, "hop_eo_dag": 8, "hop_oe_dag": 9, "clover_e": 10, "clover_o": 11, "clover_inv_o": 12,
+         "schur_left": 13}
 FULL_KINDS = ("D", "Ddag", "DdagD")
 
 CGNE, BICGSTAB = 0, 1
@@ -33,7 +34,7 @@ class OpParams(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("even_odd", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("even_odd", ctypes.c_int), ("left_precond", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

@@ -49,6 +49,7 @@ class SolverParams:
     max_outer: int = 100
     check_every: int = 8
     even_odd: bool = True
+    left_precond: bool = False   # inner BiCGStab on A_ee^-1 M (clover, even-odd)
 
     def to_c(self) -> _lib.SolverParams:
         p = _lib.SolverParams()
@@ -61,6 +62,7 @@ class SolverParams:
         p.max_outer = self.max_outer
         p.check_every = self.check_every
         p.even_odd = int(bool(self.even_odd))
+        p.left_precond = int(bool(self.left_precond))
         return p
 
 

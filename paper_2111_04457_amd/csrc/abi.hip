@@ -66,6 +66,7 @@ void lq_solver_params_default(lq_solver_params *p)
     p->max_outer = 100;
     p->check_every = 8;
     p->even_odd = 1;
+    p->left_precond = 0;
 }
 
 const char *lq_version(void) { return LQ_VERSION_STRING; }
@@ -145,6 +146,7 @@ void lq_op_destroy(lq_op *op)
 static void build_clover(lq_op *op, hipStream_t s)
 {
     const Geom &g = op->g;
+    op->even_inverted = false;
     if (!op->has_clover) return;
     for (int p = 0; p < 3; ++p) {
         op->clov[p].ensure(2 * clover_bytes(p, g.vh));
@@ -222,7 +224,7 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
 lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs, void *stream)
 {
     if (!op || !out || !in) return arg_error("lq_op_apply: null argument");
-    if (kind < LQ_D || kind > LQ_CLOVER_INV_O) return arg_error("lq_op_apply: unknown kind");
+    if (kind < LQ_D || kind > LQ_SCHUR_LEFT) return arg_error("lq_op_apply: unknown kind");
     if (!valid_prec(prec)) return arg_error("lq_op_apply: unknown precision");
     if (nrhs < 1) return arg_error("lq_op_apply: nrhs must be >= 1");
     if (out == in) return arg_error("lq_op_apply: out and in must differ");
@@ -314,7 +316,7 @@ lq_status lq_field_export(const lq_field *f, void *dst, void *stream)
 lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_field *in, void *stream)
 {
     if (!op || !out || !in) return arg_error("lq_op_apply_field: null argument");
-    if (kind < LQ_SCHUR || kind > LQ_CLOVER_INV_O) return arg_error("lq_op_apply_field: kind must act on parity fields");
+    if (kind < LQ_SCHUR || kind > LQ_SCHUR_LEFT) return arg_error("lq_op_apply_field: kind must act on parity fields");
     if (out->op != op || in->op != op) return arg_error("lq_op_apply_field: fields belong to another operator");
     if (out->prec != in->prec || out->nrhs != in->nrhs) return arg_error("lq_op_apply_field: precision or nrhs differ");
     if (out == in) return arg_error("lq_op_apply_field: out and in must differ");

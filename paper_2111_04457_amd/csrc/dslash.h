@@ -16,6 +16,7 @@
 namespace lq {
 
 // Epilogue applied to res = coef * (H in):
+//   CLOV == 3: res = C res (before the axpy)
 //   XPAY:      res = (CLOV == 1 ? C y : y) + res
 //   CLOV == 2: res = C res
 // where C is the packed clover block field of the output parity (A or A^-1).
@@ -52,7 +53,8 @@ struct HopArgs {
 };
 
 // Launch the hopping kernel.  prec: storage precision; recon: 18 or 12;
-// dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result;
+// dag: hop with the signs of H^dag; clov: 0 none, 1 on y, 2 on the result,
+// 3 on the hopping term before the axpy (with xpay, not with dag);
 // xpay: add y; red: 0 none, 2 <w, out>, 3 <w, out> and |out|^2 per
 // right-hand side (of the values as stored), written as one partial per
 // 64-site wavefront to partial[((rhs * nw) + cb / 64) * K + k], K = 2 or 3,

@@ -220,6 +220,7 @@ __device__ __forceinline__ void epilogue(const HopArgs &a, int cb, int rhs0, int
             Spinor<R> res;
 #pragma unroll
             for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[r][i];
+            if constexpr (CLOV == 3) clover_mul_raw(craw, res);
             if constexpr (XPAY) {
                 Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
                 if constexpr (CLOV == 1) clover_mul_raw(craw, yv);
@@ -494,7 +495,7 @@ static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 
 // The epilogue combinations the operators use:
 //   (clov, xpay, red) in {(0,0,0) plain hop, (2,0,0) C H x, (1,1,*) C y + c H x,
-//                         (0,1,*) y + c H x, (2,1,0) C (y + c H x)}
+//                         (0,1,*) y + c H x, (2,1,0) C (y + c H x), (3,1,*) y + C (c H x)}
 template <int P, int NL, bool DAG>
 static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
@@ -509,6 +510,12 @@ static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int
         if (clov == 1 && red == 2) return launch_nr<P, NL, DAG, 1, true, 2>(a, nr, block, s);
         if (clov == 1 && red == 3) return launch_nr<P, NL, DAG, 1, true, 3>(a, nr, block, s);
         if (clov == 2 && red == 0) return launch_nr<P, NL, DAG, 2, true, 0>(a, nr, block, s);
+        // y + C (c H x): the A_ee^-1-preconditioned Schur operator (no dagger form)
+        if constexpr (!DAG) {
+            if (clov == 3 && red == 0) return launch_nr<P, NL, DAG, 3, true, 0>(a, nr, block, s);
+            if (clov == 3 && red == 2) return launch_nr<P, NL, DAG, 3, true, 2>(a, nr, block, s);
+            if (clov == 3 && red == 3) return launch_nr<P, NL, DAG, 3, true, 3>(a, nr, block, s);
+        }
     }
     return hipErrorInvalidValue;
 }

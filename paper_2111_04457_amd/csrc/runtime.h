@@ -52,6 +52,7 @@ struct lq_op {
     int device = 0;
     bool gauge_set = false;
     bool has_clover = false;
+    bool even_inverted = false;          // A_ee^-1 computed for the current gauge field
     int hop_block[3] = {64, 64, 64};     // workgroup size of the hop kernel per precision
     // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
     // 2 XCD-aware and time slices interleaved
@@ -159,6 +160,12 @@ bool kind_is_full(lq_kind k);
 // red / w: reduction fused into the second kernel (as for hop).
 void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, bool dag,
            hipStream_t s, int red = 0, const FieldView *w = nullptr);
+// The A_ee^-1-preconditioned Schur operator 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe
+// (ensure_even_inverse first; no dagger form).
+void schur_left(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, hipStream_t s,
+                int red = 0, const FieldView *w = nullptr);
+// Invert the even clover blocks (once per gauge field); LQ_ERR_SINGULAR if one is singular.
+void ensure_even_inverse(lq_op *op, hipStream_t s);
 // Full-lattice D (or D^dag) on full packed fields of nrhs systems.
 void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool dag, hipStream_t s);
 

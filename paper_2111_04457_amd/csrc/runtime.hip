@@ -121,6 +121,34 @@ void schur(lq_op *op, int prec, const FieldView &out, const FieldView &in, const
     hop(op, prec, out, t, 0, dag, 1, false, &in, -k * k, red, w, s);
 }
 
+// The A_ee^-1-preconditioned Schur operator A_ee^-1 M = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe
+// (needs ensure_even_inverse first).
+void schur_left(lq_op *op, int prec, const FieldView &out, const FieldView &in, const FieldView &t, hipStream_t s,
+                int red, const FieldView *w)
+{
+    const double k = op->prm.kappa;
+    hop(op, prec, t, in, 1, false, 2, true, nullptr, 1.0, 0, nullptr, s);
+    hop(op, prec, out, t, 0, false, 3, true, &in, -k * k, red, w, s);
+}
+
+// A_ee^-1 (the even blocks; the odd ones are inverted with the clover
+// build), in FP64 and converted to every precision, on first use.
+void ensure_even_inverse(lq_op *op, hipStream_t s)
+{
+    if (!op->has_clover || op->even_inverted) return;
+    const Geom &g = op->g;
+    LQ_HIP(hipMemsetAsync(op->flag.ptr, 0, sizeof(int), s));
+    LQ_HIP(launch_clover_invert(g, 0, op->clov[F64].ptr, op->clovinv[F64].ptr, reinterpret_cast<int *>(op->flag.ptr),
+                                s));
+    for (int p = F32; p <= F16; ++p)
+        LQ_HIP(launch_convert_clover(g, op->clovinv[F64].ptr, p, op->clovinv[p].ptr, s, 0, 1));
+    int flag = 0;
+    LQ_HIP(hipMemcpyAsync(&flag, op->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    LQ_HIP(hipStreamSynchronize(s));
+    if (flag) throw Failure{LQ_ERR_SINGULAR, "a clover block A_ee = 1 + F on an even site is singular"};
+    op->even_inverted = true;
+}
+
 // Full-lattice D (or D^dag): out_p = A_pp in_p - kappa H_{p,1-p} in_{1-p}.
 void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool dag, hipStream_t s)
 {
@@ -169,6 +197,12 @@ void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, 
     case LQ_CLOVER_E: clover_apply(op, prec, 0, false, o, i, s); break;
     case LQ_CLOVER_O: clover_apply(op, prec, 1, false, o, i, s); break;
     case LQ_CLOVER_INV_O: clover_apply(op, prec, 1, true, o, i, s); break;
+    case LQ_SCHUR_LEFT: {
+        ensure_even_inverse(op, s);
+        op->tmp[0].ensure(fb(prec, g) * nrhs);
+        schur_left(op, prec, o, i, parity_view(op->tmp[0].ptr, prec, g, nrhs), s);
+        break;
+    }
     default: throw Failure{LQ_ERR_ARG, "unknown operator kind"};
     }
 }

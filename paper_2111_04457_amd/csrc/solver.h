@@ -29,6 +29,7 @@ struct SolveCtx {
     // inside an inner-iteration chunk: kernels skip frozen systems and hop
     // applies are counted afterwards from the systems' iteration counters
     bool masked = false;
+    bool left = false;   // inner applies use the A_ee^-1-preconditioned Schur operator
     // FP64 vectors of the solve space
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
@@ -100,7 +101,7 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
                                    (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
                                    (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
                                    (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1],
-                                   (long)op->rhs_per_thread[2], (long)(void *)s, masked_key};
+                                   (long)op->rhs_per_thread[2], (long)(void *)s, masked_key, left ? 1L : 0L};
     lq_op::GraphEntry *e = nullptr;
     for (auto &g : op->graphs)
         if (g.key == key) e = &g;

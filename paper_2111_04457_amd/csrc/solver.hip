@@ -179,8 +179,15 @@ void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
     const int p = in.prec;
     op->hop_mask = masked ? sc : nullptr;
     try {
-        if (eo) schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, dag, s);
-        else dirac_full(op, p, out.base, in.base, nsys, dag, s);
+        const FieldView t{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys};
+        if (eo && left) {
+            if (dag) throw Failure{LQ_ERR_STATE, "the preconditioned Schur operator has no dagger form here"};
+            schur_left(op, p, out, in, t, s);
+        } else if (eo) {
+            schur(op, p, out, in, t, dag, s);
+        } else {
+            dirac_full(op, p, out.base, in.base, nsys, dag, s);
+        }
     } catch (...) {
         op->hop_mask = nullptr;
         throw;
@@ -201,7 +208,9 @@ void SolveCtx::apply_reduce_finish(const FieldView &out, const FieldView &in, co
     const int red = mode == RED_DOT ? 2 : 3;
     op->hop_mask = masked ? sc : nullptr;
     try {
-        schur(op, p, out, in, FieldView{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys}, false, s, red, &w);
+        const FieldView t{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys};
+        if (left) schur_left(op, p, out, in, t, s, red, &w);
+        else schur(op, p, out, in, t, false, s, red, &w);
     } catch (...) {
         op->hop_mask = nullptr;
         throw;
@@ -339,6 +348,11 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         }
         c.push();
         LQ_HIP(launch_copy(c.irin, c.r64, c.sc, c.sps, true, c.s));
+        // left preconditioning of the inner system: A_ee^-1 M e = A_ee^-1 r
+        // (the outer loop keeps the true residual of M x = b)
+        const bool left = sp.left_precond && c.eo && !normal && sp.solver == LQ_BICGSTAB && c.op->has_clover;
+        if (left) clover_apply(c.op, c.pin, 0, true, c.irin, c.irin, c.s);
+        c.left = left;
         // a stagnating inner solve hands back to the outer loop after
         // kInnerCap iterations (a restart from the current FP64 iterate)
         constexpr int kInnerCap = 1000;
@@ -348,6 +362,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         if (normal) it = inner_cg(c, true, budget, plan);
         else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, plan);
         else it = inner_bicgstab(c, budget, plan);
+        c.left = false;
         total_inner += it;
         for (int i = 0; i < nsys; ++i) {
             const double *h = c.hsc + i * NSC;
@@ -455,6 +470,10 @@ bool valid_solver_params(const lq_solver_params *sp, std::string &why)
         why = "the full-lattice solve is CGNE only";
         return false;
     }
+    if (sp->left_precond != 0 && sp->left_precond != 1) {
+        why = "left_precond must be 0 or 1";
+        return false;
+    }
     return true;
 }
 
@@ -492,6 +511,7 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
         LQ_HIP(hipStreamWaitEvent(op->stream, op->ev_in, 0));
         hipStream_t s = op->stream;
         const Geom &g = op->g;
+        if (sp->left_precond && sp->even_odd && sp->solver == LQ_BICGSTAB) ensure_even_inverse(op, s);
         const size_t full = 2 * (size_t)fb(F64, g) * nrhs;
         op->tmp[4].ensure(full);
         op->tmp[5].ensure(full);

@@ -81,11 +81,14 @@ def _reference(op, kind, psi):
         return op.clover_apply(1, psi)
     if kind == "clover_inv_o":
         return op.clover_apply(1, psi, inverse=True)
+    if kind == "schur_left":
+        # A_ee^-1 M (A = 1 for Wilson)
+        return op.clover_apply(0, op.schur(psi), inverse=True)
     raise ValueError(kind)
 
 
 KINDS = ["D", "Ddag", "DdagD", "schur", "schur_dag", "schur_normal", "hop_eo", "hop_oe", "hop_eo_dag",
-         "hop_oe_dag", "clover_e", "clover_o", "clover_inv_o"]
+         "hop_oe_dag", "clover_e", "clover_o", "clover_inv_o", "schur_left"]
 
 
 @pytest.mark.parametrize("case", list(CASES))

@@ -113,7 +113,7 @@ def test_lds_shared_rhs_bitwise(lq, dims, nrhs):
     op.set_gauge(to_dev(U))
     xe = to_dev(np.stack([gaussian_parity_spinor(dims, 2620 + i) for i in range(nrhs)]))
     for p in ("f16", "f32"):
-        for kind in ("hop_eo", "hop_oe_dag", "clover_inv_o", "schur", "schur_dag", "schur_normal"):
+        for kind in ("hop_eo", "hop_oe_dag", "clover_inv_o", "schur", "schur_dag", "schur_normal", "schur_left"):
             op.set_option("rhs_per_thread_" + p, 1)
             ref = to_host(op.apply(kind, xe, p))
             op.set_option("rhs_per_thread_" + p, 4)

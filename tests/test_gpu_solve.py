@@ -156,3 +156,28 @@ def test_singular_clover_block_reported(lq):
         op.set_gauge(to_dev(U))
     assert e.value.status == -5
     op.close()
+
+
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 12), ("f16", 12)])
+def test_left_preconditioned_inner_solves(lq, clover_case, inner, recon):
+    """Inner BiCGStab on A_ee^-1 M with the source A_ee^-1 r: the outer
+    FP64 loop keeps the residual of M x = b, so the solve reaches the same
+    true residual and solution; the iteration counts are reported."""
+    U, b, ref, xr = clover_case
+    announce("solve: left-preconditioned inner=%s recon=%d" % (inner, recon))
+    op = lq.Operator(CLOVER["dims"], CLOVER["kappa"], CLOVER["csw"], ANTIPERIODIC_T, link_recon=recon)
+    op.set_gauge(to_dev(U))
+    tol = 1e-10
+    iters = {}
+    for left in (False, True):
+        prm = lq.SolverParams(solver="bicgstab", tol=tol, inner=inner, inner_tol=1e-5 if inner != "f16" else 1e-2,
+                              left_precond=left)
+        x, st = op.solve(to_dev(b), "D", prm)
+        x = to_host(x)
+        iters[left] = [s.nconv for s in st]
+        for i in range(2):
+            res = oracle.true_residual(ref, x[i], b[i])
+            assert st[i].converged and res <= tol * 1.01, (left, i, res)
+            assert rel_err(x[i], xr[i]) < 50 * tol
+    announce("  iterations: plain %s, A_ee^-1-preconditioned %s" % (iters[False], iters[True]))
+    op.close()
