@@ -295,6 +295,22 @@ lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, siz
 lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_prec force_prec, const void *phi,
                       void *dSdU, void *G, void *X_out, double *S, lq_solve_stats *stats, void *stream);
 
+/* Lowest eigenpairs of the Hermitian positive even-odd normal operator
+ * A = M^dag M (M the Schur operator, kind LQ_SCHUR_NORMAL, in FP64): an
+ * eigenvalue solver of the kind the paper's conclusion lists among the
+ * framework's algorithms.  Lanczos with full reorthogonalisation for m
+ * steps from the start vector v0 (device complex128 [V/2][4][3], nonzero),
+ * then the Ritz pairs of the tridiagonal matrix.  evals[nev] receive the
+ * nev smallest Ritz values (ascending), resid[nev] (may be NULL) their
+ * residual norms |A x - theta x| / |x| computed on the GPU, evecs (may be
+ * NULL; device complex128 [nev][V/2][4][3]) the unit Ritz vectors, *nconv
+ * (may be NULL) how many have resid <= tol * theta.  nev >= 1,
+ * nev + 1 <= m <= 1024; a workspace of about (m + 5) V/2 192 bytes is
+ * allocated for the call and freed before it returns.  LQ_NOT_CONVERGED if fewer than nev pairs met tol (the
+ * outputs are filled).  Synchronizes the stream. */
+lq_status lq_eigs(lq_op *op, int nev, int m, const void *v0, double *evals, double *resid, void *evecs, int *nconv,
+                  double tol, void *stream);
+
 /* ------------------------------------------------------------------------
  * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the
  * solves of the fermion matrix recur at every step of it), read as hybrid

@@ -92,6 +92,7 @@ SIGNATURES = {
     "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),
+    "lq_eigs": (I, [P, I, I, P, ctypes.POINTER(D), ctypes.POINTER(D), P, ctypes.POINTER(I), D, P]),
     "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),
     "lq_gauge_force": (I, [P, D, P, ctypes.POINTER(D), P]),
     "lq_md_trajectory": (I, [P, ctypes.POINTER(MDParams), ctypes.POINTER(SolverParams), P, P, P,

@@ -1,0 +1,121 @@
+"""The lowest eigenpairs of M^dag M (lq_eigs, Lanczos with full
+reorthogonalisation on the GPU) against the oracle: the eigenvalues of the
+dense even-odd normal matrix built entry by entry from eq. (1)
+(oracle/dense.py) on 4^4, the free-field closed form of the lowest one,
+and the oracle's own M^dag M applied to the returned vectors.
+
+Tolerances: the Ritz values of converged pairs are within |r|^2 / gap of
+the eigenvalues; with residuals below 1e-9 relative, 1e-10 relative is
+asserted on the eigenvalues and 1e-8 on the oracle residual of the vectors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from lattice_inputs import gauge_exp, gauge_unit, gaussian_parity_spinor
+from tests.gpu_common import announce, have_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+BC = (1.0, np.exp(0.3j), 1.0, -1.0)
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    import paper_2111_04457_amd as lq
+    return lq
+
+
+def _dense_normal_eigs(dims, U, kappa, csw, bc):
+    from oracle.dense import dense_dirac, parity_index
+    D = dense_dirac(dims, U, kappa, csw, bc)
+    ie, io = parity_index(dims, 0), parity_index(dims, 1)
+    M = D[np.ix_(ie, ie)] - D[np.ix_(ie, io)] @ np.linalg.solve(D[np.ix_(io, io)], D[np.ix_(io, ie)])
+    return np.linalg.eigvalsh(M.conj().T @ M)
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.7])
+def test_lowest_eigenvalues_match_dense_oracle(lq, csw):
+    dims = (4, 4, 4, 4)
+    kappa = 0.12
+    U = gauge_exp(dims, 0.4, 7101)
+    announce("eigs 4^4 csw=%g" % csw)
+    want = _dense_normal_eigs(dims, U, kappa, csw, BC)
+    op = lq.Operator(dims, kappa, csw, BC)
+    op.set_gauge(to_dev(U))
+    nev = 6
+    ev, res, X, nconv = op.eigs(nev, 200, v0=to_dev(gaussian_parity_spinor(dims, 7102)), tol=1e-9, vectors=True)
+    announce("  evals %s\n  dense %s\n  resid %s" % (np.array(ev), want[:nev], np.array(res)))
+    assert nconv == nev
+    assert np.allclose(ev, want[:nev], rtol=1e-10, atol=0)
+    # the vectors: orthonormal, and eigenvectors of the oracle's M^dag M
+    Xh = to_host(X).reshape(nev, -1)
+    gram = Xh.conj() @ Xh.T
+    assert np.abs(gram - np.eye(nev)).max() < 1e-10
+    ref = oracle.Operator(dims, U, kappa, csw, BC)
+    for k in range(nev):
+        xk = to_host(X[k])
+        r = ref.schur_normal(xk) - ev[k] * xk
+        assert np.linalg.norm(r) / (ev[k] * np.linalg.norm(xk)) < 1e-8
+    op.close()
+
+
+def test_free_field_lowest_eigenvalue(lq):
+    """At U = 1 the even-odd operator is diagonal in momentum: its
+    eigenvalues are 1 - kappa^2 w^2 with w the eigenvalues of
+    2 sum cos p - 2i sum gamma_mu sin p, so the smallest eigenvalue of
+    M^dag M is the smallest |1 - kappa^2 w^2|^2 over the momenta."""
+    dims = (4, 4, 4, 8)
+    theta = (0.0, 0.0, 0.0, np.pi)
+    kappa = 0.115
+    g = [oracle.gamma(mu) for mu in range(4)]
+    best = np.inf
+    for n0 in range(dims[0]):
+        for n1 in range(dims[1]):
+            for n2 in range(dims[2]):
+                for n3 in range(dims[3]):
+                    p = [(2 * np.pi * n + th) / L for n, th, L in zip((n0, n1, n2, n3), theta, dims)]
+                    Hp = 2 * sum(np.cos(p)) * np.eye(4) - 2j * sum(g[m] * np.sin(p[m]) for m in range(4))
+                    w = np.linalg.eigvals(Hp)
+                    best = min(best, float(np.min(np.abs(1 - kappa ** 2 * w ** 2) ** 2)))
+    op = lq.Operator(dims, kappa, 0.0, (1, 1, 1, -1))
+    op.set_gauge(to_dev(gauge_unit(dims)))
+    ev, res, _, nconv = op.eigs(1, 60, v0=to_dev(gaussian_parity_spinor(dims, 7201)), tol=1e-10)
+    announce("  free field: lowest %.15e, closed form %.15e, resid %.1e" % (ev[0], best, res[0]))
+    assert nconv == 1 and abs(ev[0] - best) < 1e-10 * best
+    op.close()
+
+
+def test_eigs_8x8x8x8_properties(lq):
+    """Larger lattice: converged residuals, ascending values, and the
+    smallest below the Rayleigh quotient of random vectors."""
+    import torch
+    dims = (8, 8, 8, 8)
+    U = gauge_exp(dims, 0.3, 7301)
+    op = lq.Operator(dims, 0.125, 1.0, (1, 1, 1, -1))
+    op.set_gauge(to_dev(U))
+    ev, res, X, nconv = op.eigs(8, 350, v0=to_dev(gaussian_parity_spinor(dims, 7302)), tol=1e-8, vectors=True)
+    announce("  8^4 evals %s resid %s" % (np.array(ev), np.array(res)))
+    assert nconv == 8 and all(ev[i] <= ev[i + 1] for i in range(7))
+    for seed in (7303, 7304):
+        v = to_dev(gaussian_parity_spinor(dims, seed))
+        Av = op.apply("schur_normal", v, "f64")
+        rq = float(torch.vdot(v.reshape(-1), Av.reshape(-1)).real / torch.vdot(v.reshape(-1), v.reshape(-1)).real)
+        assert ev[0] < rq
+    op.close()
+
+
+def test_eigs_argument_checks(lq):
+    import ctypes
+    from paper_2111_04457_amd import _lib
+    lib = _lib.load()
+    op = lq.Operator((4, 4, 4, 4), 0.12, 0.0, (1, 1, 1, -1))
+    ev = (ctypes.c_double * 4)()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
+    assert lib.lq_eigs(op.handle, 4, 4, dummy, ev, None, None, None, 1e-8, None) == -1   # m < nev + 1
+    assert lib.lq_eigs(op.handle, 0, 10, dummy, ev, None, None, None, 1e-8, None) == -1  # nev < 1
+    assert lib.lq_eigs(op.handle, 2, 10, dummy, ev, None, None, None, 0.0, None) == -1   # tol
+    assert lib.lq_eigs(op.handle, 2, 10, dummy, ev, None, None, None, 1e-8, None) == -2  # no gauge field
+    op.close()
