@@ -242,6 +242,7 @@ def _extras(lq, torch):
           file=sys.stderr, flush=True)
 
     out.update(_forces(lq, torch))
+    out.update(_eigs(lq, torch))
     return out
 
 
@@ -309,6 +310,33 @@ def _md(lq, torch):
     return out
 
 
+def _eigs(lq, torch):
+    """The 8 lowest eigenpairs of M^dag M on the 16^3x32 clover workload
+    (FP64, residuals to 1e-8): thick-restart Lanczos with 64 basis vectors
+    per cycle on the degree-8 Chebyshev filter (interval picked
+    automatically), and without the filter; each timed once after a
+    warm-up call."""
+    from lattice_inputs import ANTIPERIODIC_T, WORKLOADS, gaussian_parity_spinor, workload_gauge
+    name = "clover_16x16x16x32"
+    w = WORKLOADS[name]
+    d = w["dims"]
+    op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(torch.from_numpy(workload_gauge(name)).cuda())
+    v0 = torch.from_numpy(gaussian_parity_spinor(d, 2008)).cuda()
+    out = {}
+    for tag, degree in (("", 8), ("_plain", 0)):
+        for _ in range(2):
+            (ev, res, _, st), ms = _timed(torch, lambda: op.eigs(8, 64, v0=v0, tol=1e-8, cheb_degree=degree))
+        out["eigs_%s%s_ms" % (name, tag)] = ms
+        out["eigs_%s%s_stats" % (name, tag)] = st
+        out["eigs_%s%s_max_resid" % (name, tag)] = float(max(res))
+        if not tag:
+            out["eigs_%s_lowest" % name] = [float(e) for e in ev]
+    op.close()
+    print("bench: eigs %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +360,8 @@ def main(argv=None):
                     help="skip the 12-RHS propagator, ragged batch and force measurements")
     ap.add_argument("--force-only", action="store_true",
                     help="only the pseudofermion force and molecular-dynamics measurements; prints their JSON")
+    ap.add_argument("--eigs-only", action="store_true",
+                    help="only the eigensolver measurement; prints its JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
     args = ap.parse_args(argv)
@@ -354,6 +384,10 @@ def main(argv=None):
     if args.force_only:
         torch.cuda.set_device(0)
         print(json.dumps({"forces": _forces(lq, torch)}), flush=True)
+        return 0
+    if args.eigs_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"eigs": _eigs(lq, torch)}), flush=True)
         return 0
 
     w = WORKLOADS[args.workload]

@@ -298,18 +298,48 @@ lq_status lq_pf_force(lq_op *op, const lq_solver_params *sp, int variant, lq_pre
 /* Lowest eigenpairs of the Hermitian positive even-odd normal operator
  * A = M^dag M (M the Schur operator, kind LQ_SCHUR_NORMAL, in FP64): an
  * eigenvalue solver of the kind the paper's conclusion lists among the
- * framework's algorithms.  Lanczos with full reorthogonalisation for m
- * steps from the start vector v0 (device complex128 [V/2][4][3], nonzero),
- * then the Ritz pairs of the tridiagonal matrix.  evals[nev] receive the
- * nev smallest Ritz values (ascending), resid[nev] (may be NULL) their
- * residual norms |A x - theta x| / |x| computed on the GPU, evecs (may be
- * NULL; device complex128 [nev][V/2][4][3]) the unit Ritz vectors, *nconv
- * (may be NULL) how many have resid <= tol * theta.  nev >= 1,
- * nev + 1 <= m <= 1024; a workspace of about (m + 5) V/2 192 bytes is
- * allocated for the call and freed before it returns.  LQ_NOT_CONVERGED if fewer than nev pairs met tol (the
- * outputs are filled).  Synchronizes the stream. */
-lq_status lq_eigs(lq_op *op, int nev, int m, const void *v0, double *evals, double *resid, void *evecs, int *nconv,
-                  double tol, void *stream);
+ * framework's algorithms.  Thick-restart Lanczos with full
+ * reorthogonalisation on B = A, or (cheb_degree d >= 1) on the Chebyshev
+ * filter B = T_d(((lo + hi) - 2A) / (hi - lo)), which maps the spectrum
+ * below lo to the largest values of B and [lo, hi] into [-1, 1]. */
+typedef struct {
+    int nev;           /* wanted eigenpairs, >= 1 */
+    int m;             /* basis vectors per cycle, nev + 1 <= m <= 1024 */
+    int max_restarts;  /* thick restarts after the first cycle, >= 0 */
+    int cheb_degree;   /* 0: Lanczos on A; d in [1, 10000]: on T_d(L(A)) */
+    double cheb_lo;    /* filter interval [lo, hi]: lo > 0 should lie above the */
+    double cheb_hi;    /* wanted eigenvalues, hi at or above the largest; 0 picks each
+                          from one plain Lanczos cycle of m steps (hi: 1.01 (largest
+                          Ritz value + its residual bound); lo: the (nev+1)-th
+                          smallest Ritz value, never below the (nev+1)-th eigenvalue) */
+    double tol;        /* converged when |A x - lambda x| <= tol lambda |x| */
+} lq_eig_params;
+
+typedef struct {
+    int nconv;       /* pairs that met tol */
+    int restarts;    /* thick restarts performed */
+    long applies;    /* applications of A (each d per application of the filter) */
+    double cheb_lo;  /* the filter interval used (0, 0 without the filter) */
+    double cheb_hi;
+} lq_eig_stats;
+
+/* nev 8, m 64, max_restarts 100, cheb_degree 8 with the interval picked
+ * automatically (cheb_lo = cheb_hi = 0), tol 1e-8 */
+void lq_eig_params_default(lq_eig_params *p);
+
+/* v0: start vector (device complex128 [V/2][4][3], nonzero).  evals[nev]
+ * receive the eigenvalue estimates x^dag A x / x^dag x of the nev Ritz
+ * vectors x at the wanted end of B (ascending), resid[nev] (may be NULL)
+ * the residual norms |A x - lambda x| / |x| computed on the GPU, evecs (may
+ * be NULL; device complex128 [nev][V/2][4][3]) the unit Ritz vectors, stats
+ * (may be NULL) the counts above.  A workspace of about (2m + 2) V/2 192
+ * bytes plus four packed fields is allocated for the call and freed before
+ * it returns.  LQ_ERR_ARG for invalid parameters, a zero start vector or a
+ * degree with d arccosh((hi + lo) / (hi - lo)) > 600 (T_d would overflow);
+ * LQ_NOT_CONVERGED if fewer than nev pairs met tol after max_restarts (the
+ * outputs hold the last estimates).  Synchronizes the stream. */
+lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *evals, double *resid, void *evecs,
+                  lq_eig_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------------
  * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the

@@ -61,6 +61,17 @@ class MDStats(ctypes.Structure):
                 ("t_ms", ctypes.c_double)]
 
 
+class EigParams(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int), ("m", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("cheb_degree", ctypes.c_int), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+                ("tol", ctypes.c_double)]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [("nconv", ctypes.c_int), ("restarts", ctypes.c_int), ("applies", ctypes.c_long),
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double)]
+
+
 # name -> (restype, argtypes)
 P = ctypes.c_void_p
 I = ctypes.c_int
@@ -92,7 +103,9 @@ SIGNATURES = {
     "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),
-    "lq_eigs": (I, [P, I, I, P, ctypes.POINTER(D), ctypes.POINTER(D), P, ctypes.POINTER(I), D, P]),
+    "lq_eig_params_default": (None, [ctypes.POINTER(EigParams)]),
+    "lq_eigs": (I, [P, ctypes.POINTER(EigParams), P, ctypes.POINTER(D), ctypes.POINTER(D), P,
+                    ctypes.POINTER(EigStats), P]),
     "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),
     "lq_gauge_force": (I, [P, D, P, ctypes.POINTER(D), P]),
     "lq_md_trajectory": (I, [P, ctypes.POINTER(MDParams), ctypes.POINTER(SolverParams), P, P, P,

@@ -154,25 +154,33 @@ class Operator:
     def set_block(self, prec: str, block: int):
         check(load().lq_op_set_block(self._h, _lib.PREC[prec], int(block)))
 
-    def eigs(self, nev: int, m: int, v0: torch.Tensor | None = None, tol: float = 1e-8, vectors: bool = False,
-             seed: int = 0):
-        """The nev smallest eigenvalues of M^dag M (lq_eigs: Lanczos with full
-        reorthogonalisation, m steps).  Returns (evals, resid, evecs or None,
-        nconv); v0 defaults to a seeded Gaussian even field."""
+    def eigs(self, nev: int = 8, m: int = 64, v0: torch.Tensor | None = None, tol: float = 1e-8,
+             vectors: bool = False, seed: int = 0, max_restarts: int = 100, cheb_degree: int = 8,
+             cheb_lo: float = 0.0, cheb_hi: float = 0.0):
+        """The nev smallest eigenvalues of M^dag M (lq_eigs: thick-restart
+        Lanczos with full reorthogonalisation, m basis vectors per cycle, on
+        M^dag M or on its Chebyshev filter of degree cheb_degree over
+        [cheb_lo, cheb_hi], 0 = automatic).  Returns (evals, resid, evecs or
+        None, stats dict); v0 defaults to a seeded Gaussian even field."""
         if v0 is None:
             gen = torch.Generator(device="cpu").manual_seed(seed)
             v0 = torch.randn(self.parity_shape + (2,), generator=gen, dtype=torch.float64)
             v0 = torch.view_as_complex(v0).cuda()
         v0 = _dev(v0, self.parity_shape, "v0")
+        p = _lib.EigParams()
+        load().lq_eig_params_default(ctypes.byref(p))
+        p.nev, p.m, p.max_restarts, p.cheb_degree = int(nev), int(m), int(max_restarts), int(cheb_degree)
+        p.cheb_lo, p.cheb_hi, p.tol = float(cheb_lo), float(cheb_hi), float(tol)
         ev = (ctypes.c_double * nev)()
         rs = (ctypes.c_double * nev)()
-        nconv = ctypes.c_int()
+        st = _lib.EigStats()
         X = torch.empty((nev,) + self.parity_shape, dtype=torch.complex128, device="cuda") if vectors else None
-        rc = load().lq_eigs(self._h, int(nev), int(m), ctypes.c_void_p(v0.data_ptr()), ev, rs,
-                            ctypes.c_void_p(X.data_ptr()) if X is not None else None, ctypes.byref(nconv),
-                            float(tol), _stream())
+        rc = load().lq_eigs(self._h, ctypes.byref(p), ctypes.c_void_p(v0.data_ptr()), ev, rs,
+                            ctypes.c_void_p(X.data_ptr()) if X is not None else None, ctypes.byref(st), _stream())
         check(rc, allow_not_converged=True)
-        return list(ev), list(rs), X, nconv.value
+        stats = {"nconv": st.nconv, "restarts": st.restarts, "applies": st.applies, "cheb_lo": st.cheb_lo,
+                 "cheb_hi": st.cheb_hi}
+        return list(ev), list(rs), X, stats
 
     def tune(self, nrhs: int = 1, cache: str | None = None) -> dict:
         """Autotune the hopping kernels (lq_tune); returns the JSON report."""

@@ -1,8 +1,9 @@
-"""The lowest eigenpairs of M^dag M (lq_eigs, Lanczos with full
-reorthogonalisation on the GPU) against the oracle: the eigenvalues of the
-dense even-odd normal matrix built entry by entry from eq. (1)
-(oracle/dense.py) on 4^4, the free-field closed form of the lowest one,
-and the oracle's own M^dag M applied to the returned vectors.
+"""The lowest eigenpairs of M^dag M (lq_eigs: thick-restart Lanczos with
+full reorthogonalisation on the GPU, plain or on a Chebyshev filter)
+against the oracle: the eigenvalues of the dense even-odd normal matrix
+built entry by entry from eq. (1) (oracle/dense.py) on 4^4, the
+free-field closed form of the lowest one, and the oracle's own M^dag M
+applied to the returned vectors.
 
 Tolerances: the Ritz values of converged pairs are within |r|^2 / gap of
 the eigenvalues; with residuals below 1e-9 relative, 1e-10 relative is
@@ -36,20 +37,34 @@ def _dense_normal_eigs(dims, U, kappa, csw, bc):
     return np.linalg.eigvalsh(M.conj().T @ M)
 
 
+# (m, restarts allowed, Chebyshev degree): one long cycle; short cycles
+# with thick restarts; the filter with its interval picked automatically
+CASES = [(200, 0, 0), (20, 200, 0), (24, 50, 12)]
+
+
 @pytest.mark.parametrize("csw", [0.0, 1.7])
-def test_lowest_eigenvalues_match_dense_oracle(lq, csw):
+@pytest.mark.parametrize("m,restarts,degree", CASES)
+def test_lowest_eigenvalues_match_dense_oracle(lq, csw, m, restarts, degree):
     dims = (4, 4, 4, 4)
     kappa = 0.12
     U = gauge_exp(dims, 0.4, 7101)
-    announce("eigs 4^4 csw=%g" % csw)
+    announce("eigs 4^4 csw=%g m=%d restarts<=%d degree=%d" % (csw, m, restarts, degree))
     want = _dense_normal_eigs(dims, U, kappa, csw, BC)
     op = lq.Operator(dims, kappa, csw, BC)
     op.set_gauge(to_dev(U))
     nev = 6
-    ev, res, X, nconv = op.eigs(nev, 200, v0=to_dev(gaussian_parity_spinor(dims, 7102)), tol=1e-9, vectors=True)
-    announce("  evals %s\n  dense %s\n  resid %s" % (np.array(ev), want[:nev], np.array(res)))
-    assert nconv == nev
+    ev, res, X, st = op.eigs(nev, m, v0=to_dev(gaussian_parity_spinor(dims, 7102)), tol=1e-9, vectors=True,
+                             max_restarts=restarts, cheb_degree=degree)
+    announce("  evals %s\n  dense %s\n  resid %s\n  %s" % (np.array(ev), want[:nev], np.array(res), st))
+    assert st["nconv"] == nev
     assert np.allclose(ev, want[:nev], rtol=1e-10, atol=0)
+    if restarts == 0:
+        assert st["restarts"] == 0
+    if degree:
+        # the automatic interval brackets the spectrum above the wanted values
+        # (lo is a Ritz value of a plain cycle, not below the (nev+1)-th
+        # eigenvalue by interlacing; hi estimates the largest eigenvalue)
+        assert want[nev] <= st["cheb_lo"] < st["cheb_hi"] and st["cheb_hi"] >= 0.9 * want[-1]
     # the vectors: orthonormal, and eigenvectors of the oracle's M^dag M
     Xh = to_host(X).reshape(nev, -1)
     gram = Xh.conj() @ Xh.T
@@ -82,28 +97,36 @@ def test_free_field_lowest_eigenvalue(lq):
                     best = min(best, float(np.min(np.abs(1 - kappa ** 2 * w ** 2) ** 2)))
     op = lq.Operator(dims, kappa, 0.0, (1, 1, 1, -1))
     op.set_gauge(to_dev(gauge_unit(dims)))
-    ev, res, _, nconv = op.eigs(1, 60, v0=to_dev(gaussian_parity_spinor(dims, 7201)), tol=1e-10)
+    ev, res, _, st = op.eigs(1, 60, v0=to_dev(gaussian_parity_spinor(dims, 7201)), tol=1e-10, cheb_degree=0)
     announce("  free field: lowest %.15e, closed form %.15e, resid %.1e" % (ev[0], best, res[0]))
-    assert nconv == 1 and abs(ev[0] - best) < 1e-10 * best
+    assert st["nconv"] == 1 and abs(ev[0] - best) < 1e-10 * best
     op.close()
 
 
-def test_eigs_8x8x8x8_properties(lq):
-    """Larger lattice: converged residuals, ascending values, and the
-    smallest below the Rayleigh quotient of random vectors."""
+@pytest.mark.parametrize("degree", [0, 16])
+def test_eigs_8x8x8x8_properties(lq, degree):
+    """Larger lattice, short cycles with thick restarts, plain and filtered:
+    converged residuals, ascending values, the same eigenvalues both ways,
+    and the smallest below the Rayleigh quotient of random vectors."""
     import torch
     dims = (8, 8, 8, 8)
     U = gauge_exp(dims, 0.3, 7301)
     op = lq.Operator(dims, 0.125, 1.0, (1, 1, 1, -1))
     op.set_gauge(to_dev(U))
-    ev, res, X, nconv = op.eigs(8, 350, v0=to_dev(gaussian_parity_spinor(dims, 7302)), tol=1e-8, vectors=True)
-    announce("  8^4 evals %s resid %s" % (np.array(ev), np.array(res)))
-    assert nconv == 8 and all(ev[i] <= ev[i + 1] for i in range(7))
+    ev, res, X, st = op.eigs(8, 40, v0=to_dev(gaussian_parity_spinor(dims, 7302)), tol=1e-8, vectors=True,
+                             cheb_degree=degree)
+    announce("  8^4 degree %d evals %s resid %s %s" % (degree, np.array(ev), np.array(res), st))
+    assert st["nconv"] == 8 and all(ev[i] <= ev[i + 1] for i in range(7))
+    assert all(r <= 1e-8 * e for r, e in zip(res, ev))
     for seed in (7303, 7304):
         v = to_dev(gaussian_parity_spinor(dims, seed))
         Av = op.apply("schur_normal", v, "f64")
         rq = float(torch.vdot(v.reshape(-1), Av.reshape(-1)).real / torch.vdot(v.reshape(-1), v.reshape(-1)).real)
         assert ev[0] < rq
+    # the other variant agrees on the eigenvalues
+    ev2, _, _, st2 = op.eigs(8, 40, v0=to_dev(gaussian_parity_spinor(dims, 7305)), tol=1e-8,
+                             cheb_degree=16 - degree)
+    assert st2["nconv"] == 8 and np.allclose(ev, ev2, rtol=1e-12, atol=0)
     op.close()
 
 
@@ -112,10 +135,28 @@ def test_eigs_argument_checks(lq):
     from paper_2111_04457_amd import _lib
     lib = _lib.load()
     op = lq.Operator((4, 4, 4, 4), 0.12, 0.0, (1, 1, 1, -1))
-    ev = (ctypes.c_double * 4)()
+    ev = (ctypes.c_double * 16)()
     dummy = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
-    assert lib.lq_eigs(op.handle, 4, 4, dummy, ev, None, None, None, 1e-8, None) == -1   # m < nev + 1
-    assert lib.lq_eigs(op.handle, 0, 10, dummy, ev, None, None, None, 1e-8, None) == -1  # nev < 1
-    assert lib.lq_eigs(op.handle, 2, 10, dummy, ev, None, None, None, 0.0, None) == -1   # tol
-    assert lib.lq_eigs(op.handle, 2, 10, dummy, ev, None, None, None, 1e-8, None) == -2  # no gauge field
+
+    def params(**kw):
+        p = _lib.EigParams()
+        lib.lq_eig_params_default(ctypes.byref(p))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    for bad in (dict(nev=4, m=4), dict(nev=0), dict(m=1025), dict(tol=0.0), dict(max_restarts=-1),
+                dict(cheb_degree=-1), dict(cheb_degree=10001), dict(cheb_lo=-1.0), dict(cheb_lo=2.0, cheb_hi=1.0),
+                dict(cheb_hi=float("inf"))):
+        p = params(**bad)
+        assert lib.lq_eigs(op.handle, ctypes.byref(p), dummy, ev, None, None, None, None) == -1, bad
+    assert lib.lq_eigs(op.handle, None, dummy, ev, None, None, None, None) == -1
+    p = params()
+    assert lib.lq_eigs(op.handle, ctypes.byref(p), dummy, ev, None, None, None, None) == -2  # no gauge field
+    op.set_gauge(to_dev(gauge_unit((4, 4, 4, 4))))
+    # a degree whose T_d would overflow on the interval
+    p = params(cheb_degree=5000, cheb_lo=1.0, cheb_hi=2.0)
+    v0 = to_dev(gaussian_parity_spinor((4, 4, 4, 4), 7401))
+    assert lib.lq_eigs(op.handle, ctypes.byref(p), ctypes.c_void_p(v0.data_ptr()), ev, None, None, None,
+                       None) == -1
     op.close()
