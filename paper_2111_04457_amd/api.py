@@ -199,7 +199,7 @@ class Operator:
         if x0 is not None:
             x = _dev(x0, self.full_shape, "x0").clone()
         else:
-            x = torch.zeros_like(b)
+            x = torch.empty_like(b)  # not read without a guess; every entry is written
         stats = (_lib.SolveStats * nrhs)()
         cp = params.to_c()
         st = load().lq_solve(self._h, ctypes.byref(cp), _lib.KINDS[mode], nrhs, ctypes.c_void_p(x.data_ptr()),

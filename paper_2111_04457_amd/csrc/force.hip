@@ -432,7 +432,7 @@ lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_
         else LQ_HIP(launch_zero(c.x64, s));
         lq_solver_params sp2 = *sp;
         const std::vector<double> target2{sp->tol * sp->tol * pn2[0]};
-        const OuterStats os = defect_correction(c, sp2, true, phiv, target2);
+        const OuterStats os = defect_correction(c, sp2, true, phiv, target2, !(X0 && eo));
         // final normal-system residual
         c.apply(c.t64, c.x64, false);
         c.apply(c.y64, c.t64, true);

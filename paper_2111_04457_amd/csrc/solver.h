@@ -144,9 +144,10 @@ struct OuterStats {
 
 // Solve A x = rhs on the solve space to |rhs - A x|^2 <= target2[i] for
 // each system, A = M (normal = false; BiCGStab on M or CG on M^dag M) or
-// A = M^dag M (normal = true; CG).  x (c.x64) holds the initial guess.
+// A = M^dag M (normal = true; CG).  x (c.x64) holds the initial guess;
+// x_zero says it is zero (the first residual is then rhs, no apply).
 OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool normal, const FieldView &rhs,
-                             const std::vector<double> &target2);
+                             const std::vector<double> &target2, bool x_zero);
 
 // Inner Krylov pieces: initialisation from e = 0 and one iteration,
 // launched on c.s (used by the single solve and by the batched solve).

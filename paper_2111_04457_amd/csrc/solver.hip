@@ -302,7 +302,7 @@ std::vector<double> norms2(SolveCtx &c, const FieldView &v, int sps)
 }
 
 OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool normal, const FieldView &rhs,
-                             const std::vector<double> &target2)
+                             const std::vector<double> &target2, bool x_zero)
 {
     const int nsys = c.nsys;
     OuterStats os;
@@ -317,8 +317,10 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
     c.push();
     for (int step = 0; step <= sp.max_outer; ++step) {
-        // r = rhs - A x, |r|^2
-        if (normal) {
+        // r = rhs - A x, |r|^2 (A x = 0 for a zero initial guess)
+        if (step == 0 && x_zero) {
+            LQ_HIP(launch_zero(c.y64, c.s));
+        } else if (normal) {
             c.apply(c.t64, c.x64, false);
             c.apply(c.y64, c.t64, true);
         } else {
@@ -412,7 +414,7 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
     }
     std::vector<double> target2(nsys);
     for (int i = 0; i < nsys; ++i) target2[i] = sp.tol * sp.tol * bn2[i];
-    const OuterStats os = defect_correction(c, sp, false, rhs, target2);
+    const OuterStats os = defect_correction(c, sp, false, rhs, target2, !use_x0);
 
     // Full solution.  The reported residual is the FP64 residual the last
     // outer step computed at the final iterate: on the full lattice it is
