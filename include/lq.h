@@ -334,8 +334,11 @@ void lq_eig_params_default(lq_eig_params *p);
  * be NULL; device complex128 [nev][V/2][4][3]) the unit Ritz vectors, stats
  * (may be NULL) the counts above.  A workspace of about (2m + 2) V/2 192
  * bytes plus four packed fields is allocated for the call and freed before
- * it returns.  LQ_ERR_ARG for invalid parameters, a zero start vector or a
- * degree with d arccosh((hi + lo) / (hi - lo)) > 600 (T_d would overflow);
+ * it returns.  When the Krylov space of v0 is invariant with fewer than nev
+ * dimensions, the missing pairs are NaN in evals and resid and their evecs
+ * slots are not written.  LQ_ERR_ARG for invalid parameters, a zero start
+ * vector or a degree with d arccosh((hi + lo) / (hi - lo)) > 600 (T_d would
+ * overflow);
  * LQ_NOT_CONVERGED if fewer than nev pairs met tol after max_restarts (the
  * outputs hold the last estimates).  Synchronizes the stream. */
 lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *evals, double *resid, void *evecs,
