@@ -344,6 +344,21 @@ void lq_eig_params_default(lq_eig_params *p);
 lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *evals, double *resid, void *evecs,
                   lq_eig_stats *stats, void *stream);
 
+/* Deflated initial guess for D x = b from eigenpairs (lambda_k, v_k) of
+ * A = M^dag M, k < nvec (evals on the host, each finite and > 0; evecs
+ * device complex128 [nvec][V/2][4][3], orthonormal, as lq_eigs returns
+ * them): the even half x_e = sum_k v_k (v_k^dag M^dag b_hat) / lambda_k is
+ * the component of the even-odd solution M^-1 b_hat = A^-1 M^dag b_hat in
+ * their span (b_hat = b_e + kappa H_eo A_oo^-1 b_o, the even-odd right-hand
+ * side), and the odd half x_o = A_oo^-1 (b_o + kappa H_oe x_e) satisfies the
+ * odd rows of D x = b.  b and x0: device complex128 [V][4][3], one
+ * right-hand side; x0 is written in full and can be passed to lq_solve with
+ * use_x0 = 1, whose residual then lacks those eigenvectors' components.
+ * Buffers for 7 packed FP64 fields and 2 even fields are allocated for the
+ * call.  Synchronizes the stream. */
+lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals, const void *evecs, const void *b, void *x0,
+                            void *stream);
+
 /* ------------------------------------------------------------------------
  * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the
  * solves of the fermion matrix recur at every step of it), read as hybrid

@@ -104,6 +104,7 @@ SIGNATURES = {
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),
     "lq_eig_params_default": (None, [ctypes.POINTER(EigParams)]),
+    "lq_deflated_guess": (I, [P, I, ctypes.POINTER(D), P, P, P, P]),
     "lq_eigs": (I, [P, ctypes.POINTER(EigParams), P, ctypes.POINTER(D), ctypes.POINTER(D), P,
                     ctypes.POINTER(EigStats), P]),
     "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),

@@ -182,6 +182,23 @@ class Operator:
                  "cheb_hi": st.cheb_hi}
         return list(ev), list(rs), X, stats
 
+    def deflated_guess(self, b: torch.Tensor, evals, evecs: torch.Tensor) -> torch.Tensor:
+        """The initial guess of lq_deflated_guess for D x = b: the even-odd
+        solution's component in the span of the eigenvectors evecs
+        ([nvec, Lt/2.., 4, 3] even fields, as eigs returns them) of M^dag M
+        with eigenvalues evals, and the odd half that satisfies the odd
+        rows.  Pass it to solve(..., x0=...)."""
+        b = _dev(b, self.full_shape, "b")
+        nvec = len(evals)
+        evecs = _dev(evecs, self.parity_shape, "evecs")
+        if b.numel() != 12 * self.V or evecs.numel() != nvec * 6 * self.V:
+            raise ValueError("deflated_guess takes one right-hand side and one even field per eigenvalue")
+        ev = (ctypes.c_double * nvec)(*[float(e) for e in evals])
+        x0 = torch.empty_like(b)
+        check(load().lq_deflated_guess(self._h, nvec, ev, ctypes.c_void_p(evecs.data_ptr()),
+                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x0.data_ptr()), _stream()))
+        return x0
+
     def tune(self, nrhs: int = 1, cache: str | None = None) -> dict:
         """Autotune the hopping kernels (lq_tune); returns the JSON report."""
         import json

@@ -633,3 +633,81 @@ extern "C" lq_status lq_eigs(lq_op *op, const lq_eig_params *prm, const void *v0
         return LQ_ERR_STATE;
     }
 }
+
+extern "C" lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals, const void *evecs, const void *b,
+                                       void *x0, void *stream)
+{
+    if (!op || nvec < 1 || nvec > 4096 || !evals || !evecs || !b || !x0) {
+        set_error("lq_deflated_guess: null argument or nvec outside [1, 4096]");
+        return LQ_ERR_ARG;
+    }
+    for (int k = 0; k < nvec; ++k)
+        if (!(evals[k] > 0) || !std::isfinite(evals[k])) {
+            set_error("lq_deflated_guess: eigenvalues must be finite and positive");
+            return LQ_ERR_ARG;
+        }
+    if (!op->gauge_set) {
+        set_error("lq_deflated_guess: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    try {
+        set_error("");
+        LQ_HIP(hipSetDevice(op->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const Geom &g = op->g;
+        const long n = 12L * g.vh;
+        const double kappa = op->prm.kappa;
+        const long f = fb(F64, g);
+        // packed: b (both parities), x (both parities), t, b_hat, y; then the
+        // boundary-layout y and x_e, and the reduction scratch
+        Buf packed, bnd, part;
+        packed.ensure(7 * (size_t)f);
+        bnd.ensure(2 * sizeof(double) * 2 * (size_t)n);
+        part.ensure(sizeof(double) * 2 * (DOT_WG * (size_t)nvec + nvec));
+        char *bp = packed.ptr, *xp = packed.ptr + 2 * f, *tp = packed.ptr + 4 * f, *bh = packed.ptr + 5 * f,
+             *yp = packed.ptr + 6 * f;
+        double *ybd = reinterpret_cast<double *>(bnd.ptr), *xbd = ybd + 2 * n;
+        double *mp = reinterpret_cast<double *>(part.ptr), *cdev = mp + 2 * DOT_WG * (size_t)nvec;
+        for (int p = 0; p < 2; ++p)
+            LQ_HIP(launch_pack_spinor(g, p, 0, static_cast<const double *>(b), full_parity_view(bp, F64, g, 1, p), s));
+        const FieldView be = full_parity_view(bp, F64, g, 1, 0), bo = full_parity_view(bp, F64, g, 1, 1);
+        // b_hat = b_e + kappa H_eo A_oo^-1 b_o, y = M^dag b_hat
+        clover_apply(op, F64, 1, true, parity_view(tp, F64, g, 1), bo, s);
+        hop(op, F64, parity_view(bh, F64, g, 1), parity_view(tp, F64, g, 1), 0, false, 0, false, &be, kappa, 0, nullptr,
+            s);
+        apply_packed(op, LQ_SCHUR_DAG, F64, yp, bh, 1, s);
+        LQ_HIP(launch_unpack_spinor(g, 0, 1, parity_view(yp, F64, g, 1), ybd, s));
+        // c_k = v_k^dag y
+        const double *Vv = static_cast<const double *>(evecs);
+        mdot_kernel<<<dim3(DOT_WG, (unsigned)nvec), 256, 0, s>>>(Vv, ybd, n, mp);
+        LQ_HIP(hipGetLastError());
+        msum_kernel<<<(unsigned)nvec, 64, 0, s>>>(mp, cdev);
+        LQ_HIP(hipGetLastError());
+        std::vector<double> c(2 * (size_t)nvec);
+        LQ_HIP(hipMemcpyAsync(c.data(), cdev, sizeof(double) * c.size(), hipMemcpyDeviceToHost, s));
+        LQ_HIP(hipStreamSynchronize(s));
+        // x_e = sum_k (c_k / lambda_k) v_k, the solution's component in the
+        // span of the eigenvectors
+        LQ_HIP(hipMemsetAsync(xbd, 0, sizeof(double) * 2 * (size_t)n, s));
+        const unsigned nb = (unsigned)((n + 255) / 256);
+        for (int k = 0; k < nvec; ++k) {
+            caxpy_kernel<<<nb, 256, 0, s>>>(xbd, Vv + (size_t)k * 2 * n, c[2 * k] / evals[k], c[2 * k + 1] / evals[k],
+                                            n);
+            LQ_HIP(hipGetLastError());
+        }
+        // x_o = A_oo^-1 (b_o + kappa H_oe x_e), then the full field
+        const FieldView xe = full_parity_view(xp, F64, g, 1, 0);
+        LQ_HIP(launch_pack_spinor(g, 0, 1, xbd, xe, s));
+        hop(op, F64, full_parity_view(xp, F64, g, 1, 1), xe, 1, false, 2, true, &bo, kappa, 0, nullptr, s);
+        for (int p = 0; p < 2; ++p)
+            LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(xp, F64, g, 1, p), static_cast<double *>(x0), s));
+        LQ_HIP(hipStreamSynchronize(s));
+        return LQ_OK;
+    } catch (const Failure &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return LQ_ERR_STATE;
+    }
+}

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from lattice_inputs import gauge_exp, gauge_unit, gaussian_parity_spinor
-from tests.gpu_common import announce, have_gpu, to_dev, to_host
+from tests.gpu_common import announce, have_gpu, rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -159,4 +159,78 @@ def test_eigs_argument_checks(lq):
     v0 = to_dev(gaussian_parity_spinor((4, 4, 4, 4), 7401))
     assert lib.lq_eigs(op.handle, ctypes.byref(p), ctypes.c_void_p(v0.data_ptr()), ev, None, None, None,
                        None) == -1
+    op.close()
+
+
+def test_deflated_guess_matches_oracle(lq):
+    """lq_deflated_guess against the oracle: eigenvectors of the dense
+    M^dag M (oracle/dense.py) as input, the guess composed from the oracle's
+    prepare, M^dag and reconstruct; the even residual of the guess has no
+    component along M^dag of the eigenvectors' span."""
+    from oracle.dense import dense_dirac, parity_index
+    from lattice_inputs import gaussian_spinor
+    dims = (4, 4, 4, 4)
+    kappa, csw = 0.12, 1.7
+    U = gauge_exp(dims, 0.4, 7501)
+    D = dense_dirac(dims, U, kappa, csw, BC)
+    ie, io = parity_index(dims, 0), parity_index(dims, 1)
+    M = D[np.ix_(ie, ie)] - D[np.ix_(ie, io)] @ np.linalg.solve(D[np.ix_(io, io)], D[np.ix_(io, ie)])
+    w, Z = np.linalg.eigh(M.conj().T @ M)
+    nvec = 6
+    Vh = np.ascontiguousarray(Z[:, :nvec].T).reshape((nvec,) + (dims[0] * dims[1] * dims[2] * dims[3] // 2, 4, 3))
+    ref = oracle.Operator(dims, U, kappa, csw, BC)
+    for k in range(nvec):  # the dense ordering is the parity fields' ordering
+        assert np.linalg.norm(ref.schur_normal(Vh[k]) - w[k] * Vh[k]) < 1e-10 * w[k]
+    b = gaussian_spinor(dims, 7502)
+    bh = ref.prepare(b)
+    y = ref.schur_dag(bh)
+    xe = sum(np.vdot(Vh[k], y) / w[k] * Vh[k] for k in range(nvec))
+    want = ref.reconstruct(b, xe)
+    op = lq.Operator(dims, kappa, csw, BC)
+    op.set_gauge(to_dev(U))
+    x0 = to_host(op.deflated_guess(to_dev(b), list(w[:nvec]), to_dev(Vh)))
+    err = np.linalg.norm(x0.reshape(-1) - want.reshape(-1)) / np.linalg.norm(want)
+    announce("  deflated guess vs oracle %.2e" % err)
+    assert err < 1e-12
+    from oracle import to_parity
+    r = bh - ref.schur(to_parity(dims, x0, 0))
+    g = ref.schur_dag(r)
+    proj = max(abs(np.vdot(Vh[k], g)) for k in range(nvec))
+    assert proj < 1e-10 * max(abs(np.vdot(Vh[k], y)) for k in range(nvec))
+    # the odd rows of D x0 = b hold
+    assert np.linalg.norm(to_parity(dims, ref.D(x0) - b, 1)) < 1e-12 * np.linalg.norm(b)
+    op.close()
+
+
+def test_deflated_solve_8x8x8x8(lq):
+    """Eigenvectors from lq_eigs deflate the start of a mixed solve: both
+    starts reach the tolerance and the same solution."""
+    from lattice_inputs import gaussian_spinor
+    dims = (8, 8, 8, 8)
+    op = lq.Operator(dims, 0.125, 1.0, (1, 1, 1, -1))
+    op.set_gauge(to_dev(gauge_exp(dims, 0.3, 7601)))
+    ev, res, X, st = op.eigs(16, 64, v0=to_dev(gaussian_parity_spinor(dims, 7602)), tol=1e-10, vectors=True)
+    assert st["nconv"] == 16
+    b = to_dev(gaussian_spinor(dims, 7603))
+    prm = lq.SolverParams(solver="bicgstab", tol=1e-10, inner="f32")
+    x_plain, s_plain = op.solve(b, "D", prm)
+    x0 = op.deflated_guess(b, ev, X)
+    x_defl, s_defl = op.solve(b, "D", prm, x0=x0)
+    announce("  inner iterations: zero start %d, deflated start %d" % (s_plain[0].nconv, s_defl[0].nconv))
+    assert s_plain[0].converged and s_defl[0].converged
+    assert rel_err(to_host(x_defl), to_host(x_plain)) < 1e-8
+
+
+def test_deflated_guess_argument_checks(lq):
+    import ctypes
+    from paper_2111_04457_amd import _lib
+    lib = _lib.load()
+    op = lq.Operator((4, 4, 4, 4), 0.12, 0.0, (1, 1, 1, -1))
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
+    ev = (ctypes.c_double * 2)(0.5, 0.7)
+    bad = (ctypes.c_double * 2)(0.5, -0.7)
+    assert lib.lq_deflated_guess(op.handle, 0, ev, dummy, dummy, dummy, None) == -1
+    assert lib.lq_deflated_guess(op.handle, 2, bad, dummy, dummy, dummy, None) == -1
+    assert lib.lq_deflated_guess(op.handle, 2, ev, None, dummy, dummy, None) == -1
+    assert lib.lq_deflated_guess(op.handle, 2, ev, dummy, dummy, dummy, None) == -2  # no gauge field
     op.close()
