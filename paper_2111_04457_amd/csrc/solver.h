@@ -34,6 +34,7 @@ struct SolveCtx {
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
     FieldView ix, ir, ip, iv, is, it, irhat, iw, irin;
+    FieldView ex;  // M applied to the inner solution (its precision)
 
     FieldView space(char *base, int p) const;
     size_t space_bytes(int p) const;

@@ -254,7 +254,7 @@ void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t 
     c.px = inner == F64 ? F64 : F32;
     const size_t f64b = c.space_bytes(F64), finb = c.space_bytes(c.pin), fxb = c.space_bytes(c.px);
     const size_t odd = (size_t)fb(F64, g) * nsys;
-    const size_t need = 5 * (f64b + 256) + 9 * (finb + 256) + (fxb + 256) + 3 * (odd + 256);
+    const size_t need = 5 * (f64b + 256) + 9 * (finb + 256) + 2 * (fxb + 256) + 3 * (odd + 256);
     op->solver_ws.ensure(need);
     Arena A;
     A.base = op->solver_ws.ptr;
@@ -265,6 +265,7 @@ void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t 
     c.aux64 = c.space(A.take(f64b), F64);
     for (int p = 0; p < 3; ++p) c.odd_tmp[p] = A.take(odd);
     c.ix = c.space(A.take(fxb), c.px);
+    c.ex = c.space(A.take(fxb), c.px);
     c.ir = c.space(A.take(finb), c.pin);
     c.ip = c.space(A.take(finb), c.pin);
     c.iv = c.space(A.take(finb), c.pin);
@@ -316,9 +317,9 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     c.pull();
     for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
     c.push();
-    for (int step = 0; step <= sp.max_outer; ++step) {
-        // r = rhs - A x, |r|^2 (A x = 0 for a zero initial guess)
-        if (step == 0 && x_zero) {
+    // r = rhs - A x in FP64, |r|^2 (A x = 0 for a zero initial guess)
+    auto true_residual = [&](bool zero_x) {
+        if (zero_x) {
             LQ_HIP(launch_zero(c.y64, c.s));
         } else if (normal) {
             c.apply(c.t64, c.x64, false);
@@ -328,8 +329,11 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         }
         LQ_HIP(launch_xmy_norm(c.r64, rhs, c.y64, c.partial, c.s));
         c.finish(1, FIN_NORM, c.r64.n);
+    };
+    bool all = true;
+    auto read_norms = [&]() {
         c.pull();
-        bool all = true;
+        all = true;
         os.r2.assign(nsys, 0.0);
         for (int i = 0; i < nsys; ++i) {
             const double n2 = c.hsc[i * NSC + SC_NORM2];
@@ -337,14 +341,48 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
             if (!std::isfinite(n2)) throw Failure{LQ_ERR_NONFINITE, "residual is not finite"};
             if (c.hsc[i * NSC + SC_ODONE] == 0.0) all = false;
         }
-        if (all || step == sp.max_outer || total_inner >= sp.max_iter) break;
+    };
+    // After an FP64 residual r, the next one may be updated as r - |r| M e
+    // with M applied to the inner solution e in e's precision: that apply
+    // rounds at ~1e-7 of |r|, a small fraction of the updated residual when
+    // the inner solve reduced it by a modest factor (relative target at
+    // least 1e-3, as with binary16 storage).  The next residual is FP64
+    // again, so the rounding never accumulates, and every convergence
+    // decision is taken on an FP64 residual.  It pays only where the FP64
+    // apply is bandwidth-bound (at least 2^19 sites per parity): on smaller
+    // lattices its extra launches and the FP64 check of a converged update
+    // cost more than the FP64 apply they replace.
+    const bool can_update = !normal && c.eo && c.px != F64 && c.op->g.vh >= (1L << 19);
+    bool last_fp64 = true;
+    double last_rel = 0.0;  // smallest relative target of the last inner solve
+    for (int step = 0; step <= sp.max_outer; ++step) {
+        const bool update = can_update && step > 0 && last_fp64 && last_rel >= 1e-3;
+        if (update) {
+            c.apply(c.ex, c.ix, false);
+            LQ_HIP(launch_zero(c.y64, c.s));
+            LQ_HIP(launch_accum(c.y64, c.ex, c.sc, c.sps, true, c.s));  // |r| M e; converged systems keep 0
+            LQ_HIP(launch_xmy_norm(c.r64, c.r64, c.y64, c.partial, c.s));
+            c.finish(1, FIN_NORM, c.r64.n);
+        } else {
+            true_residual(step == 0 && x_zero);
+        }
+        read_norms();
+        const bool last_step = step == sp.max_outer || total_inner >= sp.max_iter;
+        if (update && (all || last_step)) {
+            true_residual(false);
+            read_norms();
+        }
+        last_fp64 = !update || all || last_step;
+        if (all || last_step) break;
         // relative target of this inner solve, per system
+        last_rel = 1.0;
         for (int i = 0; i < nsys; ++i) {
             double *h = c.hsc + i * NSC;
             const double rn = std::sqrt(h[SC_NORM2]);
             double rel = 0.5 * std::sqrt(target2[i]) / (rn > 0 ? rn : 1.0);
             if (c.pin != F64) rel = std::max(rel, sp.inner_tol);
             rel = std::min(rel, 0.5);
+            if (h[SC_ODONE] == 0.0) last_rel = std::min(last_rel, rel);
             h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT_* makes it absolute
             if (h[SC_ODONE] == 0.0) os.outer[i]++;
         }
