@@ -234,3 +234,32 @@ def test_deflated_guess_argument_checks(lq):
     assert lib.lq_deflated_guess(op.handle, 2, ev, None, dummy, dummy, None) == -1
     assert lib.lq_deflated_guess(op.handle, 2, ev, dummy, dummy, dummy, None) == -2  # no gauge field
     op.close()
+
+
+def test_eigs_16x16x16x32_workload_against_oracle(lq):
+    """The timed configuration (16^3x32 clover workload, 8 lowest modes,
+    64 basis vectors per cycle, degree-8 filter with the automatic
+    interval): the returned vectors are checked with the oracle's own
+    M^dag M, pair by pair, and for orthonormality."""
+    from lattice_inputs import ANTIPERIODIC_T, WORKLOADS, workload_gauge
+    name = "clover_16x16x16x32"
+    w = WORKLOADS[name]
+    dims = w["dims"]
+    U = workload_gauge(name)
+    op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(to_dev(U))
+    ev, res, X, st = op.eigs(8, 64, v0=to_dev(gaussian_parity_spinor(dims, 2008)), tol=1e-8, vectors=True)
+    announce("  %s: %s, lowest %.6e, largest resid %.1e" % (name, st, ev[0], max(res)))
+    assert st["nconv"] == 8
+    Xh = to_host(X).reshape(8, -1)
+    assert np.abs(Xh.conj() @ Xh.T - np.eye(8)).max() < 1e-10
+    ref = oracle.Operator(dims, U, w["kappa"], w["csw"], ANTIPERIODIC_T)
+    for k in (0, 3, 7):
+        xk = to_host(X[k])
+        Ax = ref.schur_normal(xk)
+        lam = float(np.vdot(xk.reshape(-1), Ax.reshape(-1)).real)
+        r = np.linalg.norm(Ax - ev[k] * xk)
+        announce("    pair %d: GPU %.15e oracle Rayleigh %.15e, oracle residual %.1e" % (k, ev[k], lam, r / ev[k]))
+        assert abs(lam - ev[k]) < 1e-12 * ev[k]
+        assert r < 2e-8 * ev[k]
+    op.close()
