@@ -354,8 +354,8 @@ lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *eva
  * odd rows of D x = b.  b and x0: device complex128 [V][4][3], one
  * right-hand side; x0 is written in full and can be passed to lq_solve with
  * use_x0 = 1, whose residual then lacks those eigenvectors' components.
- * Buffers for 7 packed FP64 fields and 2 even fields are allocated for the
- * call.  Synchronizes the stream. */
+ * A workspace of 7 packed FP64 fields and 2 even fields stays with the
+ * operator (freed with it).  Synchronizes the stream. */
 lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals, const void *evecs, const void *b, void *x0,
                             void *stream);
 

@@ -659,8 +659,9 @@ extern "C" lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals,
         const double kappa = op->prm.kappa;
         const long f = fb(F64, g);
         // packed: b (both parities), x (both parities), t, b_hat, y; then the
-        // boundary-layout y and x_e, and the reduction scratch
-        Buf packed, bnd, part;
+        // boundary-layout y and x_e, and the reduction scratch (kept with
+        // the operator for the next call)
+        Buf &packed = op->defl_ws[0], &bnd = op->defl_ws[1], &part = op->defl_ws[2];
         packed.ensure(7 * (size_t)f);
         bnd.ensure(2 * sizeof(double) * 2 * (size_t)n);
         part.ensure(sizeof(double) * 2 * (DOT_WG * (size_t)nvec + nvec));

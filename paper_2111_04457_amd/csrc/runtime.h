@@ -66,6 +66,7 @@ struct lq_op {
     lq::Buf flag;                        // device int: singular clover block
     lq::Buf tmp[6];                      // scratch fields for composite applies
     lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
+    lq::Buf defl_ws[3];                  // deflated guess: packed fields, even fields, partial sums
     lq::Buf md_G;                        // molecular dynamics: the force on every link
     lq::Buf md_partial;                  // molecular dynamics: per-wavefront partial sums
     lq::Buf md_X[3];                     // molecular dynamics: previous solutions and the next guess
