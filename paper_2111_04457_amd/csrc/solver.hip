@@ -349,10 +349,10 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     // least 1e-3, as with binary16 storage).  The next residual is FP64
     // again, so the rounding never accumulates, and every convergence
     // decision is taken on an FP64 residual.  It pays only where the FP64
-    // apply is bandwidth-bound (at least 2^19 sites per parity): on smaller
-    // lattices its extra launches and the FP64 check of a converged update
-    // cost more than the FP64 apply they replace.
-    const bool can_update = !normal && c.eo && c.px != F64 && c.op->g.vh >= (1L << 19);
+    // apply is bandwidth-bound (at least 2^19 sites per parity over all
+    // systems): on less work its extra launches and the FP64 check of a
+    // converged update cost more than the FP64 apply they replace.
+    const bool can_update = !normal && c.eo && c.px != F64 && (long)c.op->g.vh * nsys >= (1L << 19);
     bool last_fp64 = true;
     double last_rel = 0.0;  // smallest relative target of the last inner solve
     for (int step = 0; step <= sp.max_outer; ++step) {
