@@ -150,3 +150,17 @@ def test_md_entry_points_reject_bad_arguments(lib):
         assert lib.lq_gauge_force(h, math.nan, dummy, None, None) == -1
     finally:
         lib.lq_op_destroy(h)
+
+
+def test_eigensolver_entry_points_on_host(lib):
+    """lq_eigs / lq_deflated_guess validate on the host: null operator and
+    parameters, and the documented defaults."""
+    from paper_2111_04457_amd import _lib
+    p = _lib.EigParams()
+    lib.lq_eig_params_default(ctypes.byref(p))
+    assert (p.nev, p.m, p.max_restarts, p.cheb_degree) == (8, 64, 100, 8)
+    assert p.cheb_lo == 0.0 and p.cheb_hi == 0.0 and p.tol == 1e-8
+    ev = (ctypes.c_double * 8)()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.lq_eigs(None, ctypes.byref(p), dummy, ev, None, None, None, None) == -1
+    assert lib.lq_deflated_guess(None, 1, ev, dummy, dummy, dummy, None) == -1
