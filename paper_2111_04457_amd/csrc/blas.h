@@ -66,6 +66,9 @@ hipError_t launch_copy(FieldView y, FieldView x, const double *sc, int sps, bool
 hipError_t launch_accum(FieldView x64, FieldView e, const double *sc, int sps, bool scaled, hipStream_t s);
 // r = b - y and partial |r|^2
 hipError_t launch_xmy_norm(FieldView r, FieldView b, FieldView y, double *partial, hipStream_t s);
+// r64 -= sc[SC_SCALE] e (systems with SC_ODONE set keep r) and partial |r|^2
+hipError_t launch_sub_scaled_norm(FieldView r64, FieldView e, const double *sc, int sps, double *partial,
+                                  hipStream_t s);
 // CG: x += alpha p; r -= alpha q; partial |r|^2
 hipError_t launch_cg_xr(FieldView x, FieldView r, FieldView p, FieldView q, const double *sc, int sps,
                         double *partial, hipStream_t s);

@@ -301,6 +301,33 @@ __global__ __launch_bounds__(BT) void xmy_norm_kernel(FieldView r, FieldView b, 
     if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
 }
 
+// r -= sc[SC_SCALE] e (systems with SC_ODONE set keep r) and partial |r|^2
+template <int PE>
+__global__ __launch_bounds__(BT) void sub_scaled_norm_kernel(FieldView r, FieldView e, const double *sc, int sps,
+                                                            double *partial)
+{
+    using RE = typename PT<PE>::R;
+    const long i = (long)blockIdx.x * BT + threadIdx.x;
+    const int slice = blockIdx.y;
+    const double *s = sc + (slice / sps) * NSC;
+    const double f = s[SC_ODONE] != 0.0 ? 0.0 : s[SC_SCALE];
+    double a = 0;
+    if (i < r.n) {
+        Spinor<double> rv = load_spinor<F64>(r.base + slice * r.rs, i, r.n);
+        const Spinor<RE> ev = load_spinor<PE>(e.base + slice * e.rs, i, e.n);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            rv.c[k].re -= f * (double)ev.c[k].re;
+            rv.c[k].im -= f * (double)ev.c[k].im;
+            a += norm2(rv.c[k]);
+        }
+        store_spinor<F64>(r.base + slice * r.rs, i, r.n, rv);
+    }
+    __shared__ double lds[BT / 64];
+    const double t = block_sum<BT>(a, lds);
+    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+}
+
 template <int P, int PX>
 __global__ __launch_bounds__(BT) void cg_xr_kernel(FieldView x, FieldView r, FieldView p, FieldView q,
                                                   const double *sc, int sps, double *partial)
@@ -480,6 +507,13 @@ hipError_t launch_accum(FieldView x64, FieldView e, const double *sc, int sps, b
 {
     FieldView &x = x64;
     LQ_BY_PREC(e.prec, accum_kernel, x64, e, sc, sps, scaled)
+}
+
+hipError_t launch_sub_scaled_norm(FieldView r, FieldView e, const double *sc, int sps, double *partial,
+                                  hipStream_t s)
+{
+    FieldView &x = r;
+    LQ_BY_PREC(e.prec, sub_scaled_norm_kernel, r, e, sc, sps, partial)
 }
 
 hipError_t launch_xmy_norm(FieldView r, FieldView b, FieldView y, double *partial, hipStream_t s)

@@ -359,9 +359,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         const bool update = can_update && step > 0 && last_fp64 && last_rel >= 1e-3;
         if (update) {
             c.apply(c.ex, c.ix, false);
-            LQ_HIP(launch_zero(c.y64, c.s));
-            LQ_HIP(launch_accum(c.y64, c.ex, c.sc, c.sps, true, c.s));  // |r| M e; converged systems keep 0
-            LQ_HIP(launch_xmy_norm(c.r64, c.r64, c.y64, c.partial, c.s));
+            LQ_HIP(launch_sub_scaled_norm(c.r64, c.ex, c.sc, c.sps, c.partial, c.s));  // r -= |r| M e
             c.finish(1, FIN_NORM, c.r64.n);
         } else {
             true_residual(step == 0 && x_zero);
