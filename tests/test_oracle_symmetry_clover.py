@@ -154,3 +154,19 @@ def test_sites_variants_match_full():
     assert np.array_equal(got, full[sites])
     Fs = oracle.clover_sites(dims, U, 1.1, 0.12, sites)
     assert np.array_equal(Fs, op.F[sites])
+    # the per-site hopping sum, both signs, against the full-lattice one
+    for dag in (False, True):
+        hfull = op.H(psi, dagger=dag).reshape(-1, 4, 3)
+        hs = oracle.hop_sites(dims, U, BC, psi, sites, dagger=dag)
+        assert np.array_equal(hs, hfull[sites])
+    # and on a lattice with extent-2 directions (coincident neighbours summed),
+    # every site, against D = A - kappa H rearranged: H = (A psi - D psi) / kappa
+    dims2 = (2, 4, 2, 4)
+    U2 = gauge_haar(dims2, 63)
+    psi2 = gaussian_spinor(dims2, 64)
+    op2 = oracle.Operator(dims2, U2, 0.2, 0.0, BC)
+    all_sites = np.arange(oracle.volume(dims2))
+    for dag in (False, True):
+        d = (op2.Ddag if dag else op2.D)(psi2).reshape(-1, 4, 3)
+        hs = oracle.hop_sites(dims2, U2, BC, psi2, all_sites, dagger=dag)
+        assert np.allclose(hs, (psi2.reshape(-1, 4, 3) - d) / 0.2, rtol=0, atol=1e-13)
