@@ -184,6 +184,28 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
 lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
                       void *stream);
 
+/* lq_op_apply without any device allocation, for callers that cannot
+ * allocate: code being captured into a HIP graph, tight serving loops,
+ * hosts that forbid hipMalloc.  Same arguments, kinds and results as
+ * lq_op_apply (the same kernels run, so the outputs are the same bits); the
+ * packed copies of in and out and the temporaries of the composite kinds
+ * live in a fixed 64 MiB device array inside the library (one per GPU, held
+ * until the process ends), not in memory the call allocates.
+ * Limit: the packed fields must fit in 64 MiB, i.e.
+ *   2 F + T <= 64 MiB,  F = (full kind ? 2 : 1) * nrhs * V/2 * s,
+ *   T = nrhs * V/2 * s for LQ_SCHUR, LQ_SCHUR_DAG and LQ_SCHUR_LEFT, 2 nrhs V/2 s
+ *   for LQ_SCHUR_NORMAL and LQ_DDAGD, else 0, with s = 192, 96 or 52 bytes for
+ *   FP64, FP32 and FP16 (V/2 rounded up to a multiple of 64, each part to
+ *   256 bytes); larger calls return LQ_ERR_ARG before any device work (e.g.
+ *   16^3 x 32 fits every kind in FP64 with nrhs = 1).
+ * Every call on one GPU shares that array: calls that overlap in time on the
+ * same GPU (other streams, other threads, other operators) race and must be
+ * ordered by the caller.  No part of the array needs to start at zero.
+ * LQ_SCHUR_LEFT computes A_ee^-1 on its first use after a gauge update
+ * (allocation-free, but it synchronizes the stream). */
+lq_status lq_op_apply_noalloc(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
+                              void *stream);
+
 /* Device-resident parity spinor fields in the library's packed layout
  * (structure of arrays over checkerboard sites, nrhs stacked), for applying
  * kinds >= LQ_SCHUR without packing at every call. */
@@ -219,7 +241,10 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *                    links and clover blocks staged once in LDS (FP16 and
  *                    FP32 storage with at least 4 right-hand sides, else 1);
  *                    per precision "rhs_per_thread_f64" / "_f32" / "_f16".
- * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16".
+ * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16", and
+ * "work_kib": the KiB of device work buffers the operator has allocated on
+ * demand so far (temporaries, reduction partials, solver, force, eigensolver
+ * and molecular-dynamics workspaces; not the packed links and clover).
  * LQ_ERR_ARG for an unknown name or value. */
 lq_status lq_op_set_option(lq_op *op, const char *name, int value);
 lq_status lq_op_get_option(const lq_op *op, const char *name, int *value);

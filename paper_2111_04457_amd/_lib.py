@@ -86,6 +86,7 @@ SIGNATURES = {
     "lq_op_set_gauge": (I, [P, P, P]),
     "lq_op_set_params": (I, [P, D, D, P, P]),
     "lq_op_apply": (I, [P, I, I, P, P, I, P]),
+    "lq_op_apply_noalloc": (I, [P, I, I, P, P, I, P]),
     "lq_field_create": (I, [P, I, I, ctypes.POINTER(P)]),
     "lq_field_destroy": (None, [P]),
     "lq_field_import": (I, [P, P, P]),

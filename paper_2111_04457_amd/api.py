@@ -136,6 +136,21 @@ class Operator:
                                  ctypes.c_void_p(psi.data_ptr()), nrhs, _stream()))
         return out
 
+    def apply_noalloc(self, kind: str, psi: torch.Tensor, out: torch.Tensor, prec: str = "f64") -> torch.Tensor:
+        """out = K psi like apply(), through lq_op_apply_noalloc: the library
+        allocates nothing (its packed fields use a fixed per-GPU array); out
+        is the caller's tensor of psi's shape."""
+        full = kind in _lib.FULL_KINDS
+        shape = self.full_shape if full else self.parity_shape
+        psi = _dev(psi, shape, "psi")
+        if not (isinstance(out, torch.Tensor) and out.dtype == torch.complex128 and out.is_cuda
+                and out.is_contiguous() and out.shape == psi.shape):
+            raise ValueError("out must be a contiguous complex128 CUDA tensor of psi's shape")
+        nrhs = psi.numel() // (12 * (self.V if full else self.V // 2))
+        check(load().lq_op_apply_noalloc(self._h, _lib.KINDS[kind], _lib.PREC[prec], ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(psi.data_ptr()), nrhs, _stream()))
+        return out
+
     def traffic(self, prec="f32", nrhs=1, clover=False):
         b = ctypes.c_double()
         f = ctypes.c_double()

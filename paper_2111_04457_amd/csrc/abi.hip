@@ -1,10 +1,45 @@
 // abi.hip -- the extern "C" entry points declared in include/lq.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "runtime.h"
 
 using namespace lq;
+
+// Device memory of lq_op_apply_noalloc: a fixed array in the code object, so
+// that the call needs no allocation.  Each GPU the library runs on holds its
+// own copy (at its own address) until the process ends; every call on that
+// GPU shares it.  Host code never passes the array's name to a kernel or a
+// copy: it uses the device address looked up once per device.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call on that device, with that device current).
+char *scratch_on_device(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) throw Failure{LQ_ERR_STATE, "device index out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        LQ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Failure{LQ_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array"};
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
 
 #define LQ_VERSION_STRING "lq-mi355x 0.1 (gfx950)"
 
@@ -259,6 +294,54 @@ lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const vo
     });
 }
 
+lq_status lq_op_apply_noalloc(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
+                              void *stream)
+{
+    if (!op || !out || !in) return arg_error("lq_op_apply_noalloc: null argument");
+    if (kind < LQ_D || kind > LQ_SCHUR_LEFT) return arg_error("lq_op_apply_noalloc: unknown kind");
+    if (!valid_prec(prec)) return arg_error("lq_op_apply_noalloc: unknown precision");
+    if (nrhs < 1) return arg_error("lq_op_apply_noalloc: nrhs must be >= 1");
+    if (out == in) return arg_error("lq_op_apply_noalloc: out and in must differ");
+    if (!op->gauge_set) {
+        set_error("lq_op_apply_noalloc: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    const Geom &g = op->g;
+    const bool full = kind_is_full(kind);
+    const size_t field = round256((size_t)(full ? 2 : 1) * fb(prec, g) * nrhs);
+    size_t t0b, t1b;
+    apply_temp_bytes(kind, prec, g, nrhs, t0b, t1b);
+    const size_t need = 2 * field + round256(t0b) + round256(t1b);
+    if (need > kNoallocScratchBytes)
+        return arg_error("lq_op_apply_noalloc: the packed fields of this call need " + std::to_string(need) +
+                         " bytes, above the fixed scratch of " + std::to_string(kNoallocScratchBytes) +
+                         " bytes (use lq_op_apply)");
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        char *base = scratch_on_device(op->device);
+        char *pin = base, *pout = base + field;
+        char *t0 = t0b ? pout + field : nullptr;
+        char *t1 = t1b ? t0 + round256(t0b) : nullptr;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const double *src = static_cast<const double *>(in);
+        double *dst = static_cast<double *>(out);
+        if (full) {
+            for (int p = 0; p < 2; ++p)
+                LQ_HIP(launch_pack_spinor(g, p, 0, src, full_parity_view(pin, prec, g, nrhs, p), s));
+        } else {
+            LQ_HIP(launch_pack_spinor(g, 0, 1, src, parity_view(pin, prec, g, nrhs), s));
+        }
+        apply_packed(op, kind, prec, pout, pin, nrhs, s, t0, t1);
+        if (full) {
+            for (int p = 0; p < 2; ++p)
+                LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(pout, prec, g, nrhs, p), dst, s));
+        } else {
+            LQ_HIP(launch_unpack_spinor(g, 0, 1, parity_view(pout, prec, g, nrhs), dst, s));
+        }
+        return LQ_OK;
+    });
+}
+
 lq_status lq_field_create(lq_op *op, lq_prec prec, int nrhs, lq_field **out)
 {
     if (!op || !out) return arg_error("lq_field_create: null argument");
@@ -375,6 +458,7 @@ lq_status lq_op_get_option(const lq_op *op, const char *name, int *value)
     else if (n == "hop_block_f64") *value = op->hop_block[F64];
     else if (n == "hop_block_f32") *value = op->hop_block[F32];
     else if (n == "hop_block_f16") *value = op->hop_block[F16];
+    else if (n == "work_kib") *value = (int)std::min<size_t>(op->work_bytes() >> 10, 0x7fffffff);
     else return arg_error("lq_op_get_option: unknown option: " + n);
     return LQ_OK;
 }

@@ -106,6 +106,16 @@ struct lq_op {
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (stream) (void)hipStreamDestroy(stream);
     }
+    // device bytes of the work buffers allocated on demand (temporaries,
+    // reduction partials, solver, force, eigensolver and MD workspaces)
+    size_t work_bytes() const
+    {
+        size_t n = force_ws.bytes + md_G.bytes + md_partial.bytes + partial.bytes + solver_ws.bytes + solver_sc.bytes;
+        for (const auto &b : tmp) n += b.bytes;
+        for (const auto &b : defl_ws) n += b.bytes;
+        for (const auto &b : md_X) n += b.bytes;
+        return n;
+    }
     // link format of the hop kernels (the clover build and the force use the
     // 18-real FP64 links)
     int nl(int) const { return prm.link_recon; }
@@ -150,7 +160,13 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
 
 // Apply kind on packed fields of precision prec.  Full kinds take full
 // packed fields ([rhs][parity][planes]); the others parity fields.
-void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s);
+// t0, t1: temporaries of apply_temp_bytes(kind, ...) bytes each, or null
+// for the operator's own (allocated on first use).
+void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s,
+                  char *t0 = nullptr, char *t1 = nullptr);
+// Bytes of each of the temporaries t0 / t1 apply_packed needs for kind
+// (0 if that temporary is not used).
+void apply_temp_bytes(lq_kind kind, int prec, const Geom &g, int nrhs, size_t &t0, size_t &t1);
 
 // Clover of parity p (inverse if inv) applied site-locally.
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s);

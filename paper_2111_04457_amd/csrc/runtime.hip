@@ -161,31 +161,51 @@ void dirac_full(lq_op *op, int prec, char *out, const char *in, int nrhs, bool d
     }
 }
 
-void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s)
+void apply_temp_bytes(lq_kind kind, int prec, const Geom &g, int nrhs, size_t &t0, size_t &t1)
+{
+    t0 = t1 = 0;
+    switch (kind) {
+    case LQ_DDAGD: t0 = 2 * (size_t)fb(prec, g) * nrhs; break;
+    case LQ_SCHUR:
+    case LQ_SCHUR_DAG:
+    case LQ_SCHUR_LEFT: t0 = (size_t)fb(prec, g) * nrhs; break;
+    case LQ_SCHUR_NORMAL: t0 = t1 = (size_t)fb(prec, g) * nrhs; break;
+    default: break;
+    }
+}
+
+void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, int nrhs, hipStream_t s, char *t0,
+                  char *t1)
 {
     const Geom &g = op->g;
     const FieldView o = parity_view(out, prec, g, nrhs);
     const FieldView i = parity_view(const_cast<char *>(in), prec, g, nrhs);
+    size_t b0, b1;
+    apply_temp_bytes(kind, prec, g, nrhs, b0, b1);
+    if (b0 && !t0) {
+        op->tmp[0].ensure(b0);
+        t0 = op->tmp[0].ptr;
+    }
+    if (b1 && !t1) {
+        op->tmp[1].ensure(b1);
+        t1 = op->tmp[1].ptr;
+    }
     switch (kind) {
     case LQ_D: dirac_full(op, prec, out, in, nrhs, false, s); break;
     case LQ_DDAG: dirac_full(op, prec, out, in, nrhs, true, s); break;
     case LQ_DDAGD: {
-        op->tmp[0].ensure(2 * fb(prec, g) * nrhs);
-        dirac_full(op, prec, op->tmp[0].ptr, in, nrhs, false, s);
-        dirac_full(op, prec, out, op->tmp[0].ptr, nrhs, true, s);
+        dirac_full(op, prec, t0, in, nrhs, false, s);
+        dirac_full(op, prec, out, t0, nrhs, true, s);
         break;
     }
     case LQ_SCHUR:
     case LQ_SCHUR_DAG: {
-        op->tmp[0].ensure(fb(prec, g) * nrhs);
-        schur(op, prec, o, i, parity_view(op->tmp[0].ptr, prec, g, nrhs), kind == LQ_SCHUR_DAG, s);
+        schur(op, prec, o, i, parity_view(t0, prec, g, nrhs), kind == LQ_SCHUR_DAG, s);
         break;
     }
     case LQ_SCHUR_NORMAL: {
-        op->tmp[0].ensure(fb(prec, g) * nrhs);
-        op->tmp[1].ensure(fb(prec, g) * nrhs);
-        const FieldView t = parity_view(op->tmp[0].ptr, prec, g, nrhs);
-        const FieldView m = parity_view(op->tmp[1].ptr, prec, g, nrhs);
+        const FieldView t = parity_view(t0, prec, g, nrhs);
+        const FieldView m = parity_view(t1, prec, g, nrhs);
         schur(op, prec, m, i, t, false, s);
         schur(op, prec, o, m, t, true, s);
         break;
@@ -199,8 +219,7 @@ void apply_packed(lq_op *op, lq_kind kind, int prec, char *out, const char *in, 
     case LQ_CLOVER_INV_O: clover_apply(op, prec, 1, true, o, i, s); break;
     case LQ_SCHUR_LEFT: {
         ensure_even_inverse(op, s);
-        op->tmp[0].ensure(fb(prec, g) * nrhs);
-        schur_left(op, prec, o, i, parity_view(op->tmp[0].ptr, prec, g, nrhs), s);
+        schur_left(op, prec, o, i, parity_view(t0, prec, g, nrhs), s);
         break;
     }
     default: throw Failure{LQ_ERR_ARG, "unknown operator kind"};
