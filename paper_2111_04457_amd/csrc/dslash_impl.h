@@ -24,13 +24,13 @@ template <int P, int NL, int NR> struct HalfRaw {
     bool wrap;
 };
 
-// a b - c d with fused multiply-adds (8 operations instead of 14)
-template <typename R>
-__device__ __forceinline__ cx<R> cdet2(cx<R> a, cx<R> b, cx<R> c, cx<R> d)
+// a b - c d for binary16 operands, as 8 multiply-adds (each reads its
+// binary16 operands directly; 14 operations with separate products)
+__device__ __forceinline__ cx<float> cdet2(cx<float> a, cx<float> b, cx<float> c, cx<float> d)
 {
-    const R tr = fmar(-c.im, d.im, c.re * d.re);
-    const R tim = fmar(c.im, d.re, c.re * d.im);
-    return cx<R>{fmar(-a.im, b.im, fmar(a.re, b.re, -tr)), fmar(a.im, b.re, fmar(a.re, b.im, -tim))};
+    const float tr = fmar(-c.im, d.im, mul16(c.re, d.re));
+    const float tim = fmar(c.im, d.re, mul16(c.re, d.im));
+    return cx<float>{fmar(-a.im, b.im, fmar(a.re, b.re, -tr)), fmar(a.im, b.re, fmar(a.re, b.im, -tim))};
 }
 
 // The link of half K of site cb (parity p_out): U_mu(x) forward, U_mu(x - mu) backward.
@@ -95,49 +95,55 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
     cx<R> u[9];
 #pragma unroll
     for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)lnk[(2 * i) * LS], (R)lnk[(2 * i + 1) * LS]};
-    if constexpr (NL == 12) {
-        if constexpr (PT<P>::scaled) {
-            // binary16 (issue-bound): the third row with fused multiply-adds
+    const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], FWD ? (R)a.g.bc_im[MU] : -(R)a.g.bc_im[MU]};
+    if constexpr (PT<P>::scaled) {
+        // binary16 storage (the kernels are bound by instruction issue as much
+        // as by memory): every arithmetic operation on a stored value is a
+        // multiply-add, so the conversions fold into mixed-precision
+        // multiply-adds; the spinor's scale is applied in the projection (6
+        // components, not 12), and the boundary phase only where it is not 1.
+        if constexpr (NL == 12) {
             u[6] = conj(cdet2(u[1], u[5], u[2], u[4]));
             u[7] = conj(cdet2(u[2], u[3], u[0], u[5]));
             u[8] = conj(cdet2(u[0], u[4], u[1], u[3]));
-        } else {
+        }
+        const bool phase = a.g.bc_re[MU] != 1.0 || a.g.bc_im[MU] != 0.0;  // the same for every thread
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            Spinor<R> ps;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) ps.c[i] = cx<R>{(R)h.sp[r][2 * i], (R)h.sp[r][2 * i + 1]};
+            cx<R> hh[6], o[6];
+            project16<MU, SG>(ps, h.scale[r], hh);
+            if (phase && h.wrap) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) hh[i] = ph * hh[i];
+            }
+            su3_mul16<!FWD>(u, hh, o);
+            reconstruct<MU, SG>(acc[r], o);
+        }
+    } else {
+        if constexpr (NL == 12) {
             u[6] = conj(u[1] * u[5] - u[2] * u[4]);
             u[7] = conj(u[2] * u[3] - u[0] * u[5]);
             u[8] = conj(u[0] * u[4] - u[1] * u[3]);
         }
-    }
-    // The boundary phase (on links that wrap) and the binary16 scale act on
-    // the projected half spinor (6 components, not 12): off the boundary a
-    // real multiply by the scale, or nothing.  The kernels are bound by
-    // instruction issue in binary16, where this removes a sixth of them.
-    const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], FWD ? (R)a.g.bc_im[MU] : -(R)a.g.bc_im[MU]};
+        // FP32 / FP64 are bound by memory: a branch-free multiply by the
+        // boundary phase keeps the loads of the pipeline free to move (a
+        // branch here measured slower)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        Spinor<R> ps;
+        for (int r = 0; r < NR; ++r) {
+            Spinor<R> ps;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) ps.c[i] = cx<R>{(R)h.sp[r][2 * i], (R)h.sp[r][2 * i + 1]};
-        cx<R> hh[6], o[6];
-        project<MU, SG>(ps, hh);
-        if constexpr (PT<P>::scaled) {
-            const R sc = h.scale[r];
-            if (h.wrap) {
-                const cx<R> f = cx<R>{ph.re * sc, ph.im * sc};
-#pragma unroll
-                for (int i = 0; i < 6; ++i) hh[i] = f * hh[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < 6; ++i) hh[i] = sc * hh[i];
-            }
-        } else {
-            // FP32 / FP64 are bound by memory: a branch-free multiply keeps the
-            // loads of the pipeline free to move (a branch here measured slower)
+            for (int i = 0; i < 12; ++i) ps.c[i] = cx<R>{(R)h.sp[r][2 * i], (R)h.sp[r][2 * i + 1]};
+            cx<R> hh[6], o[6];
+            project<MU, SG>(ps, hh);
             const cx<R> f = h.wrap ? ph : cx<R>{1, 0};
 #pragma unroll
             for (int i = 0; i < 6; ++i) hh[i] = f * hh[i];
+            su3_mul<!FWD>(u, hh, o);
+            reconstruct<MU, SG>(acc[r], o);
         }
-        su3_mul<!FWD>(u, hh, o);
-        reconstruct<MU, SG>(acc[r], o);
     }
 }
 
@@ -213,13 +219,14 @@ __device__ __forceinline__ void epilogue(const HopArgs &a, int cb, int rhs0, int
 {
     using R = typename PT<P>::R;
     const R coef = (R)a.coef;
+    const bool unit = a.coef == 1.0;  // the same for every thread: no multiply by 1
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r < nr) {
             const int rhs = rhs0 + r;
             Spinor<R> res;
 #pragma unroll
-            for (int i = 0; i < 12; ++i) res.c[i] = coef * acc[r][i];
+            for (int i = 0; i < 12; ++i) res.c[i] = unit ? acc[r][i] : coef * acc[r][i];
             if constexpr (CLOV == 3) clover_mul_raw(craw, res);
             if constexpr (XPAY) {
                 Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);

@@ -81,6 +81,23 @@ template <typename R> __device__ __forceinline__ cx<R> ti(cx<R> a) { return {-a.
 template <typename R> __device__ __forceinline__ cx<R> tmi(cx<R> a) { return {a.im, -a.re}; }
 template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 
+// Products whose operands come from binary16 storage.  a * b is written as
+// fma(a, b, +0): the same value (up to the sign of an exact zero), but the
+// compiler then folds the binary16 -> FP32 conversion of each operand into
+// one mixed-precision multiply-add (v_fma_mix_f32) instead of converting
+// first, which takes a conversion off every binary16 value used.
+__device__ __forceinline__ float mul16(float a, float b) { return __builtin_fmaf(a, b, 0.0f); }
+// a * b (complex) in the same form
+__device__ __forceinline__ cx<float> cmul16(cx<float> a, cx<float> b)
+{
+    return {fmar(a.re, b.re, fmar(-a.im, b.im, 0.0f)), fmar(a.re, b.im, fmar(a.im, b.re, 0.0f))};
+}
+// conj(a) * b in the same form
+__device__ __forceinline__ cx<float> cmulc16(cx<float> a, cx<float> b)
+{
+    return {fmar(a.re, b.re, fmar(a.im, b.im, 0.0f)), fmar(a.re, b.im, fmar(-a.im, b.re, 0.0f))};
+}
+
 // --------------------------------------------------------------- planes --
 
 constexpr int SB = 64;  // sites per block
@@ -183,7 +200,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> load_spinor(const char *__r
     if constexpr (PT<P>::scaled) {
         const float sc = *reinterpret_cast<const float *>(base + 48 * (size_t)padded_sites(n) + (uint32_t)s * 4u);
 #pragma unroll
-        for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i] * sc, (R)raw[2 * i + 1] * sc};
+        for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{mul16((R)raw[2 * i], sc), mul16((R)raw[2 * i + 1], sc)};
     } else {
 #pragma unroll
         for (int i = 0; i < 12; ++i) o.c[i] = cx<R>{(R)raw[2 * i], (R)raw[2 * i + 1]};
@@ -249,7 +266,7 @@ __device__ __forceinline__ Spinor<typename PT<P>::R> as_stored(const Spinor<type
         Spinor<R> o;
 #pragma unroll
         for (int i = 0; i < 12; ++i)
-            o.c[i] = cx<R>{(R)to_f16(v.c[i].re * inv) * sc, (R)to_f16(v.c[i].im * inv) * sc};
+            o.c[i] = cx<R>{mul16((R)to_f16(v.c[i].re * inv), sc), mul16((R)to_f16(v.c[i].im * inv), sc)};
         return o;
     }
 }

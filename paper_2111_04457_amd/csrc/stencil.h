@@ -29,6 +29,29 @@ __device__ __forceinline__ void project(const Spinor<R> &p, cx<R> h[6])
     }
 }
 
+// The same projection of a spinor held as binary16 values (converted, no
+// arithmetic yet) times its FP32 scale sc: h = sc psi_up + s sc B psi_dn,
+// two mixed-precision multiply-adds per real component.
+template <int MU, int SG>
+__device__ __forceinline__ void project16(const Spinor<float> &p, float sc, cx<float> h[6])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<float> b0, b1;
+        const cx<float> d2 = p.c[6 + a], d3 = p.c[9 + a];
+        if constexpr (MU == 0) { b0 = tmi(d3); b1 = tmi(d2); }
+        else if constexpr (MU == 1) { b0 = mk(-d3.re, -d3.im); b1 = d2; }
+        else if constexpr (MU == 2) { b0 = tmi(d2); b1 = ti(d3); }
+        else { b0 = d2; b1 = d3; }
+        if constexpr (SG < 0) {
+            b0 = mk(-b0.re, -b0.im);
+            b1 = mk(-b1.re, -b1.im);
+        }
+        h[a] = mk(fmar(b0.re, sc, mul16(p.c[a].re, sc)), fmar(b0.im, sc, mul16(p.c[a].im, sc)));
+        h[3 + a] = mk(fmar(b1.re, sc, mul16(p.c[3 + a].re, sc)), fmar(b1.im, sc, mul16(p.c[3 + a].im, sc)));
+    }
+}
+
 // acc += (u, s B^dag u) with u the colour-multiplied half spinor.
 template <int MU, int SG, typename R>
 __device__ __forceinline__ void reconstruct(cx<R> acc[12], const cx<R> u[6])
@@ -95,6 +118,30 @@ __device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[6], cx<R
         }
 }
 
+// su3_mul with binary16 link entries (converted, no arithmetic yet): every
+// product is a multiply-add, so each entry is read by mixed-precision
+// multiply-adds without a conversion of its own.
+template <bool DAGU>
+__device__ __forceinline__ void su3_mul16(const cx<float> u[9], const cx<float> h[6], cx<float> o[6])
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<float> acc;
+            if constexpr (!DAGU) {
+                acc = cmul16(u[a * 3 + 0], h[s * 3 + 0]);
+                acc = cmac(acc, u[a * 3 + 1], h[s * 3 + 1]);
+                acc = cmac(acc, u[a * 3 + 2], h[s * 3 + 2]);
+            } else {
+                acc = cmulc16(u[0 * 3 + a], h[s * 3 + 0]);
+                acc = cmacc(acc, u[1 * 3 + a], h[s * 3 + 1]);
+                acc = cmacc(acc, u[2 * 3 + a], h[s * 3 + 2]);
+            }
+            o[s * 3 + a] = acc;
+        }
+}
+
 // y_i += l x_j and y_j += conj(l) x_i for one strictly-lower entry l of a
 // Hermitian block.  Fused in single precision, separate products in double
 // (the forms the register allocator handles best for each type; both are
@@ -112,15 +159,12 @@ __device__ __forceinline__ void clov_acc(cx<R> &yi, cx<R> &yj, const cx<R> l, co
 }
 
 // y = C x with C two packed 6x6 Hermitian blocks: per block 6 real diagonal
-// entries then the 15 strictly-lower entries (row-major) as complex pairs.
-template <int P>
-__device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh, int cb,
-                                           Spinor<typename PT<P>::R> &v)
+// entries then the 15 strictly-lower entries (row-major) as complex pairs,
+// the 72 reals already loaded (one load of the clover block can serve
+// several right-hand sides).
+template <typename S, typename R>
+__device__ __forceinline__ void clover_mul_raw(const S *__restrict__ raw, Spinor<R> &v)
 {
-    using S = typename PT<P>::S;
-    using R = typename PT<P>::R;
-    S raw[72];
-    load_planes<S, 72>(clov, cb, vh, raw);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const S *c = raw + 36 * b;
@@ -128,7 +172,10 @@ __device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh
 #pragma unroll
         for (int i = 0; i < 6; ++i) x[i] = v.c[6 * b + i];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) y[i] = (R)c[i] * x[i];
+        for (int i = 0; i < 6; ++i) {
+            if constexpr (sizeof(S) == 2) y[i] = mk(mul16((R)c[i], x[i].re), mul16((R)c[i], x[i].im));
+            else y[i] = (R)c[i] * x[i];
+        }
         int k = 6;
 #pragma unroll
         for (int i = 1; i < 6; ++i)
@@ -143,31 +190,14 @@ __device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh
     }
 }
 
-// The same product with the 72 packed reals already loaded (one load of the
-// clover block serves several right-hand sides).
-template <typename S, typename R>
-__device__ __forceinline__ void clover_mul_raw(const S *__restrict__ raw, Spinor<R> &v)
+// The same product loading the block of site cb.
+template <int P>
+__device__ __forceinline__ void clover_mul(const char *__restrict__ clov, int vh, int cb,
+                                           Spinor<typename PT<P>::R> &v)
 {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const S *c = raw + 36 * b;
-        cx<R> x[6], y[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) x[i] = v.c[6 * b + i];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) y[i] = (R)c[i] * x[i];
-        int k = 6;
-#pragma unroll
-        for (int i = 1; i < 6; ++i)
-#pragma unroll
-            for (int j = 0; j < i; ++j) {
-                const cx<R> l = cx<R>{(R)c[k], (R)c[k + 1]};
-                k += 2;
-                clov_acc(y[i], y[j], l, x[i], x[j]);
-            }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) v.c[6 * b + i] = y[i];
-    }
+    typename PT<P>::S raw[72];
+    load_planes<typename PT<P>::S, 72>(clov, cb, vh, raw);
+    clover_mul_raw(raw, v);
 }
 
 }  // namespace lq
