@@ -31,6 +31,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# the GPU solutions of the 16^3 x 32 ladder, compared with the oracle's in
+# the cpu_baseline leg
+C1_SOLUTIONS = {}
+
 
 def _kernel_source_hash():
     h = hashlib.sha256()
@@ -138,22 +142,21 @@ def _kernels(lq, torch, op, b_d, V, recon, reps, left):
         kern["dslash_%s_us" % prec] = best[1]
         kern["dslash_%s_block" % prec] = best[0]
         kern["dslash_%s_GBs" % prec] = b1 * (V // 2) / (best[1] * 1e-6) / 1e9
+        # the count without spinor reuse (8 links + 8 neighbour spinors + 1
+        # output = 360 reals per site, plus the binary16 spinors' 9 scales)
+        rs = {"f64": 8, "f32": 4, "f16": 2}[prec]
+        naive = 360 * rs + (9 * 4 if prec == "f16" else 0)
+        kern["dslash_%s_naive_GBs" % prec] = naive * (V // 2) / (best[1] * 1e-6) / 1e9
         kern["dslash_%s_TFLOPs" % prec] = f1 * (V // 2) / (best[1] * 1e-6) / 1e12
         fin.close()
         fout.close()
-    # device copy probe (1 GiB read + 1 GiB write per copy)
-    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    c = torch.empty_like(a)
-    c.copy_(a)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        c.copy_(a)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    kern["copy_probe_GBs"] = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, c
+    # the library's bandwidth probes over 1 GiB: a copy (bytes read + written)
+    # and a read-only stream
+    kern["copy_probe_GBs"] = lq.bandwidth_probe(1 << 30, "copy", reps=10)
+    kern["read_probe_GBs"] = lq.bandwidth_probe(1 << 30, "read", reps=10)
+    if roof is not None:
+        roof["frac_of_copy_probe"] = roof["achieved"] / kern["copy_probe_GBs"]
+        roof["frac_of_read_probe"] = roof["achieved"] / kern["read_probe_GBs"]
     return kern, roof
 
 
@@ -172,27 +175,33 @@ def _extras(lq, torch):
     from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_parity_spinor, gaussian_spinor,
                                 point_sources, workload_gauge, workload_source)
     out = {}
-    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=10, left_precond=True)
+    # the batched workloads with their stated FP32 inner solve, and with
+    # binary16 storage beside it
+    prms = {"f32": lq.SolverParams(tol=1e-10, inner="f32", inner_tol=1e-5, check_every=10, left_precond=True),
+            "f16": lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=10, left_precond=True)}
     w = WORKLOADS["clover_24x24x24x48"]
     d = w["dims"]
     op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
     op.set_gauge(torch.from_numpy(workload_gauge("clover_24x24x24x48")).cuda())
-    op.tune(12)
+    op.tune(12, left=True)
     src = torch.from_numpy(point_sources(d)).cuda()
-    op.solve(src, "D", prm)
-    (_, st), ms12 = _timed(torch, lambda: op.solve(src, "D", prm))
-    op.solve(src[0], "D", prm)
-    ms1 = 0.0
-    for k in range(12):
-        _, m = _timed(torch, lambda: op.solve(src[k], "D", prm))
-        ms1 += m
-    out["propagator_24x24x24x48_12rhs_ms"] = ms12
-    out["propagator_24x24x24x48_12_single_ms"] = ms1
-    out["propagator_12rhs_speedup"] = ms1 / ms12
-    out["propagator_max_diff"] = max(s.diff for s in st)
-    out["propagator_iters"] = [s.nconv for s in st]
+    for inner, prm in prms.items():
+        tag = "" if inner == "f16" else "_f32"
+        op.solve(src, "D", prm)
+        (_, st), ms12 = _timed(torch, lambda: op.solve(src, "D", prm))
+        op.solve(src[0], "D", prm)
+        ms1 = 0.0
+        for k in range(12):
+            _, m = _timed(torch, lambda: op.solve(src[k], "D", prm))
+            ms1 += m
+        out["propagator_24x24x24x48_12rhs%s_ms" % tag] = ms12
+        out["propagator_24x24x24x48_12_single%s_ms" % tag] = ms1
+        out["propagator_12rhs%s_speedup" % tag] = ms1 / ms12
+        out["propagator%s_max_diff" % tag] = max(s.diff for s in st)
+        out["propagator%s_iters" % tag] = [s.nconv for s in st]
+        print("bench: propagator inner %s %.1f ms (12 RHS) vs %.1f ms (12 single)" % (inner, ms12, ms1),
+              file=sys.stderr, flush=True)
     op.close()
-    print("bench: propagator %.1f ms (12 RHS) vs %.1f ms (12 single)" % (ms12, ms1), file=sys.stderr, flush=True)
 
     ops, bs = [], []
     for i, dd in enumerate(RAGGED_DIMS):
@@ -201,21 +210,24 @@ def _extras(lq, torch):
         ops.append(o)
         bs.append(torch.from_numpy(gaussian_spinor(dd, 2003 + 10 * i, 4)).cuda())
     batch = lq.Batch(ops, [4] * len(ops))
-    batch.solve(bs, prm)
-    (_, stb), msb = _timed(torch, lambda: batch.solve(bs, prm))
-    mss = 0.0
-    for o, b in zip(ops, bs):
-        o.solve(b, "D", prm)
-        _, m = _timed(torch, lambda: o.solve(b, "D", prm))
-        mss += m
-    out["ragged_batch_ms"] = msb
-    out["ragged_separate_ms"] = mss
-    out["ragged_batch_speedup"] = mss / msb
-    out["ragged_max_diff"] = max(s.diff for s in stb)
+    for inner, prm in prms.items():
+        tag = "" if inner == "f16" else "_f32"
+        batch.solve(bs, prm)
+        (_, stb), msb = _timed(torch, lambda: batch.solve(bs, prm))
+        mss = 0.0
+        for o, b in zip(ops, bs):
+            o.solve(b, "D", prm)
+            _, m = _timed(torch, lambda: o.solve(b, "D", prm))
+            mss += m
+        out["ragged_batch%s_ms" % tag] = msb
+        out["ragged_separate%s_ms" % tag] = mss
+        out["ragged_batch%s_speedup" % tag] = mss / msb
+        out["ragged%s_max_diff" % tag] = max(s.diff for s in stb)
+        print("bench: ragged batch inner %s %.1f ms vs %.1f ms separate" % (inner, msb, mss), file=sys.stderr,
+              flush=True)
     batch.close()
     for o in ops:
         o.close()
-    print("bench: ragged batch %.1f ms vs %.1f ms separate" % (msb, mss), file=sys.stderr, flush=True)
 
     w = WORKLOADS["clover_16x16x16x32"]
     d = w["dims"]
@@ -237,6 +249,7 @@ def _extras(lq, torch):
         else:
             out["clover_16x16x16x32_%s_err_vs_fp64" % name] = float(torch.linalg.vector_norm(xs - x64) /
                                                                     torch.linalg.vector_norm(x64))
+        C1_SOLUTIONS[name] = xs.cpu().numpy()
     op.close()
     print("bench: 16x16x16x32 ladder %s" % json.dumps({k: v for k, v in out.items() if k.startswith("clover_16")}),
           file=sys.stderr, flush=True)
@@ -412,7 +425,7 @@ def main(argv=None):
     tune = None
     if not args.no_tune:
         t_tune = time.time()
-        tune = op.tune(1)
+        tune = op.tune(1, left=args.left_precond)
         print("bench: tuned in %.1f s: %s" % (time.time() - t_tune, json.dumps(tune)), file=sys.stderr, flush=True)
 
     if args.kernels_only:
@@ -520,6 +533,25 @@ def main(argv=None):
             cpu["solve_16x16x16x32_fp64_s"] = time.perf_counter() - ta
             cpu["solve_16x16x16x32_fp64_iters"] = it1
             cpu["solve_16x16x16x32_fp64_diff"] = oracle.true_residual(ref, x1, b1)
+            # one D apply of the oracle on the same lattice
+            ta = time.perf_counter()
+            ref.D(b1)
+            cpu["dirac_16x16x16x32_s"] = time.perf_counter() - ta
+            # the GPU solutions of the ladder against the oracle's solution
+            # (solved on to 1e-13: its own error is then far below theirs)
+            x1t, _ = oracle.solve_eo(ref, b1, tol=1e-13)
+            cpu["c1_err_vs_oracle_solution"] = {
+                name: float(np.linalg.norm(xg.reshape(-1) - x1t.reshape(-1)) / np.linalg.norm(x1t.reshape(-1)))
+                for name, xg in C1_SOLUTIONS.items()}
+            # the FP64 solve on 32^3 x 64 by the oracle, extrapolated (it would
+            # take minutes): one BiCGStab iteration applies M twice, i.e. at
+            # least two full-lattice hopping terms, times the GPU FP64 solve's
+            # iterations (clover site products and vector operations not counted)
+            if "fp64_iters" in tts:
+                cpu["solve_%s_fp64_extrapolated_s" % args.workload] = 2 * tc * tts["fp64_iters"]
+                cpu["solve_%s_fp64_extrapolation" % args.workload] = (
+                    "2 full-lattice oracle hops per BiCGStab iteration x %d iterations (GPU FP64 count); "
+                    "a lower bound" % tts["fp64_iters"])
         print("bench: cpu baseline %s" % json.dumps(cpu), file=sys.stderr, flush=True)
 
     line = {

@@ -39,12 +39,20 @@
  * Memory and streams
  * ------------------
  *  Every spinor / gauge pointer is a DEVICE pointer owned by the caller and
- *  borrowed for the duration of the call.  The library owns the device
- *  copies it makes (packed links and clover in every precision, solver
- *  work vectors), allocated in lq_op_create / lq_field_create / on first
- *  solve, and freed by the matching destroy.  `stream` is a hipStream_t
- *  (NULL = the default stream); every call is ordered on it.  Calls that
- *  return host results (solves, forces, norms) synchronize the stream.
+ *  borrowed for the duration of the call, except in the *_host variants
+ *  (lq_op_set_gauge_host, lq_op_apply_host, lq_solve_host), which take host
+ *  pointers and stage them through device buffers of the operator.
+ *  The operator's device memory (packed links and clover in every
+ *  precision, the packed fields and work vectors of applies and solves) is
+ *  either one workspace the caller allocates and binds (lq_op_bind; its
+ *  size from lq_op_workspace_bytes), so that set_gauge, set_params, apply
+ *  and solve allocate nothing, or, unbound, allocated by the library on
+ *  first use (lq_op_set_gauge, the first apply or solve of a size) and
+ *  freed by lq_op_destroy.  The force, molecular-dynamics, eigensolver,
+ *  deflation and tuner calls and lq_field_create allocate their own extra
+ *  buffers in either case.  `stream` is a hipStream_t (NULL = the default
+ *  stream); every call is ordered on it.  Calls that return host results
+ *  (solves, forces, norms, host variants) synchronize the stream.
  *  An lq_op is not thread-safe: calls on one lq_op must not overlap.
  *
  * Errors
@@ -161,10 +169,44 @@ const char *lq_version(void);
 const char *lq_last_error(void);
 
 /* Create an operator for the parameters (validated on the host: even dims
- * >= 2, finite kappa and csw, |bc| = 1, link_recon in {12, 18}); allocates
- * the device copies.  LQ_ERR_NODEVICE if no gfx950 device is visible. */
+ * >= 2, finite kappa and csw, |bc| = 1, link_recon in {12, 18}).  No device
+ * memory is allocated here (only a stream and two events are created).
+ * LQ_ERR_NODEVICE if no gfx950 device is visible. */
 lq_status lq_op_create(const lq_op_params *p, lq_op **out);
 void lq_op_destroy(lq_op *op);
+
+/* Device memory (the interface object of Sec. 3.3 that holds the fields in
+ * the device layout; params_fopr / set_config / invert of Fig. 1 then run
+ * on it).
+ * lq_workspace_bytes: bytes of the workspace of an operator with parameters
+ * p for calls of up to nrhs right-hand sides: the packed links (FP64 with
+ * 18 reals; FP32, FP16 and, with link_recon 12, FP64 with link_recon
+ * reals), the clover blocks A and A^-1 in three precisions (csw != 0 only),
+ * the packed fields of an apply and of a solve, the staging of host fields,
+ * the reduction partials, the solver scalars and the solver's vectors, each
+ * region starting on a 256-byte boundary.  Host arithmetic only: no device
+ * is needed.  LQ_ERR_ARG for invalid dims, link_recon or nrhs < 1.
+ * lq_op_workspace_bytes: the same for an existing operator (its current
+ * csw decides whether clover blocks are stored). */
+lq_status lq_workspace_bytes(const lq_op_params *p, int nrhs, size_t *bytes);
+lq_status lq_op_workspace_bytes(const lq_op *op, int nrhs, size_t *bytes);
+
+/* Bind dev_mem (a device allocation of `bytes` bytes on the operator's
+ * device, owned by the caller, e.g. a torch uint8 tensor, 256-byte aligned)
+ * as the operator's device memory; it must stay allocated until the
+ * operator is destroyed or bound again.  The layout is that of
+ * lq_op_workspace_bytes for the largest nrhs whose size fits in `bytes`
+ * (lq_op_get_option "bound_nrhs"); calls with more right-hand sides return
+ * LQ_ERR_ARG.  Binding drops the gauge field (call lq_op_set_gauge again)
+ * and frees what the library had allocated; dev_mem = NULL unbinds (the
+ * library allocates on demand again).  Waits for the device to be idle.
+ * After binding, lq_op_set_gauge, lq_op_set_params, lq_op_apply,
+ * lq_op_apply_field and lq_solve (and their host variants) allocate no
+ * device memory ("owned_kib" stays 0); setting csw != 0 on an operator bound
+ * with csw = 0 returns LQ_ERR_NOMEM (no room for the clover blocks).
+ * LQ_ERR_ARG if bytes is below lq_op_workspace_bytes(op, 1) or dev_mem is
+ * misaligned. */
+lq_status lq_op_bind(lq_op *op, void *dev_mem, size_t bytes);
 
 /* Set the gauge field (set_config of Fig. 1).  U: device complex128 in the
  * gauge layout.  Packs FP64, FP32 and FP16 copies (even/odd split, SoA),
@@ -172,6 +214,9 @@ void lq_op_destroy(lq_op *op);
  * LQ_ERR_SINGULAR if a clover block of an odd site is not invertible
  * (A_oo is the block the even-odd solve inverts; A_ee is only applied). */
 lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream);
+/* The same with U in host memory (copied to the operator's device memory
+ * on the stream first; synchronizes it). */
+lq_status lq_op_set_gauge_host(lq_op *op, const void *U, void *stream);
 
 /* Change kappa, csw and the boundary phases; rebuilds the clover term from
  * the stored links.  bc may be NULL to keep the phases. */
@@ -183,6 +228,11 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
  * only at the boundary; prec selects the internal precision. */
 lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
                       void *stream);
+/* The same with in and out in host memory (staged through device buffers of
+ * the operator; the same kernels, so the same bits; synchronizes the
+ * stream). */
+lq_status lq_op_apply_host(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs,
+                           void *stream);
 
 /* lq_op_apply without any device allocation, for callers that cannot
  * allocate: code being captured into a HIP graph, tight serving loops,
@@ -223,14 +273,24 @@ lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_fie
 lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
 
 /* Other execution options (none changes a result bit):
- *   "xcd_remap" 0|1|2  order of the hopping kernel's workgroups: 0 plain,
- *                    1 XCD-aware (each XCD takes a contiguous range of site
- *                    blocks; default), 2 XCD-aware with the blocks of
+ *   "xcd_remap" 0|1|2  order of the hopping kernel's workgroups: 0 plain
+ *                    (default), 1 XCD-aware (each XCD takes a contiguous
+ *                    range of site blocks), 2 XCD-aware with the blocks of
  *                    neighbouring time slices visited one after another
  *                    (used when a time slice of one parity is a whole number
  *                    of workgroups, else as 1); all precisions;
  *                    "xcd_remap_f64" / "_f32" / "_f16" per precision;
  *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
+ *   "tune_form" 0|1  the operator form lq_tune times: 0 M (default), 1 A_ee^-1 M
+ *                    (clover operators; as 0 without clover);
+ *   "break_at"  k>=0 the next lq_solve's first inner BiCGStab solve takes rho = 0 at
+ *                    its iteration k (a forced breakdown, to exercise the restart
+ *                    path: the system freezes, the FP64 outer loop restarts the
+ *                    inner solve from the current iterate and counts a restart);
+ *                    reset to 0 by that solve; 0 (default) never;
+ *   "log_level" 0|1|2  progress lines of solves on stderr: 1 one per solve (outer
+ *                    steps, iterations, restarts, residual), 2 also one per outer
+ *                    step; the environment variable LQ_LOG_LEVEL sets a floor;
  *   "rhs_per_thread" 1|2|4  how the hopping kernel shares links between
  *                    right-hand sides applied together: 1 (default) one per
  *                    thread, the right-hand sides of one site block in
@@ -242,9 +302,12 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *                    FP32 storage with at least 4 right-hand sides, else 1);
  *                    per precision "rhs_per_thread_f64" / "_f32" / "_f16".
  * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16", and
- * "work_kib": the KiB of device work buffers the operator has allocated on
- * demand so far (temporaries, reduction partials, solver, force, eigensolver
- * and molecular-dynamics workspaces; not the packed links and clover).
+ * "work_kib": the KiB of device work buffers the operator holds (temporaries,
+ * reduction partials, solver, force, eigensolver and molecular-dynamics
+ * workspaces; not the packed links and clover), "owned_kib": the KiB of
+ * device memory the library allocated itself for the operator (0 for the
+ * regions of a bound workspace), "bound_nrhs": the right-hand sides the
+ * bound workspace is laid out for (0: not bound).
  * LQ_ERR_ARG for an unknown name or value. */
 lq_status lq_op_set_option(lq_op *op, const char *name, int value);
 lq_status lq_op_get_option(const lq_op *op, const char *name, int *value);
@@ -256,6 +319,10 @@ lq_status lq_op_get_option(const lq_op *op, const char *name, int *value);
 lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, double *bytes_per_site,
                         double *flops_per_site);
 
+/* LQ_DDAGD solves D^dag y = b to tol / 2, then D x = y to tol |b| / (2 |D| |y|)
+ * (|D| bounded by 1 + 16 kappa + 12 |c_sw| kappa), so that the normal residual
+ * |b - D^dag D x| / |b| reported in diff meets tol; it starts from zero
+ * (use_x0 = 1 is LQ_ERR_ARG). */
 /* Solve op x = b for mode LQ_D, LQ_DDAG or LQ_DDAGD (invert of Fig. 1) for
  * nrhs right-hand sides at once (multi-RHS kernels reuse every loaded link
  * across the right-hand sides).  b, x: device complex128 full fields
@@ -265,6 +332,10 @@ lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, dou
  * LQ_ERR_NONFINITE if b or an intermediate residual is not finite. */
 lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
                    int use_x0, lq_solve_stats *stats, void *stream);
+/* The same with b and x in host memory (copied through device buffers of the
+ * operator; the solve itself is that of lq_solve, so x is the same bits). */
+lq_status lq_solve_host(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
+                        int use_x0, lq_solve_stats *stats, void *stream);
 
 /* Batched solve over several lattices (a ragged batch: operators of
  * different volumes and gauge fields, nrhs[i] right-hand sides each).
@@ -284,18 +355,32 @@ lq_status lq_batch_solve(lq_batch *batch, const lq_solver_params *sp, void *cons
                          lq_solve_stats *stats, void *stream);
 void lq_batch_destroy(lq_batch *batch);
 
-/* Autotuner: for each storage precision, times the Schur operator (the two
- * fused hopping kernels of every solver iteration, nrhs right-hand sides)
+/* Autotuner: for each storage precision, times the operator work of one
+ * BiCGStab iteration (two applies of the Schur operator M, or with the
+ * option "tune_form" = 1 of the A_ee^-1-preconditioned form the inner solves
+ * use with left_precond; the second kernel of each apply with the dot
+ * products the solver fuses into it; nrhs right-hand sides) with HIP events
  * over workgroup sizes {64, 128, 256}, the three workgroup orders and, for
- * nrhs > 1, one or two right-hand sides per thread, with HIP events,
- * requires every candidate's output to be bitwise equal to the
- * first's, and keeps the fastest on the operator.  Results are cached in
- * the JSON file cache_path (or $LQ_TUNE_CACHE; NULL and unset: no cache),
- * keyed by kernel, precision, lattice, link format, nrhs and architecture;
- * cached entries are applied without timing.  report (may be NULL) receives
- * a JSON summary, truncated to report_len bytes.  Uses (and overwrites) the
- * operator's scratch fields; synchronizes the stream. */
+ * nrhs >= 4 in FP16 / FP32, four right-hand sides per workgroup sharing
+ * links in LDS; requires every candidate's output to be bitwise equal to
+ * the first's, and keeps the fastest on the operator unless the shape the
+ * operator had is within 2 % of it.  Results are cached in the JSON file
+ * cache_path (or $LQ_TUNE_CACHE; NULL and unset: no cache), keyed by
+ * operator form, precision, lattice, link format, nrhs and architecture;
+ * cached entries are applied without timing.  report (may be NULL)
+ * receives a JSON summary, truncated to report_len bytes.  Uses (and
+ * overwrites) the operator's scratch fields; synchronizes the stream. */
 lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *report, size_t report_len, void *stream);
+
+/* Device bandwidth probe, the reference point of the bandwidth figures
+ * (not part of the method): mode 0 copies `bytes` from src to dst, mode 1
+ * reads src (dst unused; one small partial sum per workgroup is written to a
+ * buffer of the call), 16 bytes per thread per step over a grid of 16
+ * workgroups per compute unit, non-temporal loads and stores; one warm-up
+ * launch, then reps launches between HIP events on the stream: *us receives
+ * the average launch duration.  bytes: a multiple of 16; src, dst: device
+ * buffers, 16-byte aligned.  Synchronizes the stream. */
+lq_status lq_bandwidth_probe(int mode, void *dst, const void *src, size_t bytes, int reps, double *us, void *stream);
 
 /* Pseudofermion action and force (molecular-dynamics force of the gauge-field
  * generation the paper's Sec. 2 describes, whose solves are the bottleneck):
@@ -365,7 +450,9 @@ void lq_eig_params_default(lq_eig_params *p);
  * vector or a degree with d arccosh((hi + lo) / (hi - lo)) > 600 (T_d would
  * overflow);
  * LQ_NOT_CONVERGED if fewer than nev pairs met tol after max_restarts (the
- * outputs hold the last estimates).  Synchronizes the stream. */
+ * outputs hold the last estimates); with the filter a pair counts as met
+ * only if its eigenvalue is at most lo (one above hi, amplified by T_d, is
+ * not among the wanted ones).  Synchronizes the stream. */
 lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *evals, double *resid, void *evecs,
                   lq_eig_stats *stats, void *stream);
 

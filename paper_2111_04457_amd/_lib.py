@@ -84,9 +84,14 @@ SIGNATURES = {
     "lq_op_create": (I, [ctypes.POINTER(OpParams), ctypes.POINTER(P)]),
     "lq_op_destroy": (None, [P]),
     "lq_op_set_gauge": (I, [P, P, P]),
+    "lq_op_set_gauge_host": (I, [P, P, P]),
+    "lq_workspace_bytes": (I, [ctypes.POINTER(OpParams), I, ctypes.POINTER(ctypes.c_size_t)]),
+    "lq_op_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_size_t)]),
+    "lq_op_bind": (I, [P, P, ctypes.c_size_t]),
     "lq_op_set_params": (I, [P, D, D, P, P]),
     "lq_op_apply": (I, [P, I, I, P, P, I, P]),
     "lq_op_apply_noalloc": (I, [P, I, I, P, P, I, P]),
+    "lq_op_apply_host": (I, [P, I, I, P, P, I, P]),
     "lq_field_create": (I, [P, I, I, ctypes.POINTER(P)]),
     "lq_field_destroy": (None, [P]),
     "lq_field_import": (I, [P, P, P]),
@@ -97,11 +102,13 @@ SIGNATURES = {
     "lq_op_get_option": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
     "lq_op_traffic": (I, [P, I, I, I, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "lq_solve": (I, [P, ctypes.POINTER(SolverParams), I, I, P, P, I, ctypes.POINTER(SolveStats), P]),
+    "lq_solve_host": (I, [P, ctypes.POINTER(SolverParams), I, I, P, P, I, ctypes.POINTER(SolveStats), P]),
     "lq_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(I), ctypes.POINTER(P)]),
     "lq_batch_solve": (I, [P, ctypes.POINTER(SolverParams), ctypes.POINTER(P), ctypes.POINTER(P),
                            ctypes.POINTER(SolveStats), P]),
     "lq_batch_destroy": (None, [P]),
     "lq_tune": (I, [P, I, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t, P]),
+    "lq_bandwidth_probe": (I, [I, P, P, ctypes.c_size_t, I, ctypes.POINTER(D), P]),
     "lq_pf_force": (I,[P, ctypes.POINTER(SolverParams), I, I, P, P, P, P, ctypes.POINTER(D),
                         ctypes.POINTER(SolveStats), P]),
     "lq_eig_params_default": (None, [ctypes.POINTER(EigParams)]),

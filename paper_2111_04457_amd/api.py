@@ -30,12 +30,37 @@ def _bc_array(bc):
     return arr
 
 
-def _dev(t: torch.Tensor, shape, name):
-    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.device.type != "cuda":
-        raise TypeError("%s must be a complex128 CUDA tensor" % name)
+def _dev(t: torch.Tensor, shape, name, host_ok: bool = False):
+    """t as a contiguous complex128 tensor of trailing shape `shape`, on the
+    GPU (or, with host_ok, in host memory: the *_host entry points)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or \
+            not (t.device.type == "cuda" or (host_ok and t.device.type == "cpu")):
+        raise TypeError("%s must be a complex128 %s tensor" % (name, "CUDA or CPU" if host_ok else "CUDA"))
     if tuple(t.shape[-len(shape):]) != tuple(shape):
         raise ValueError("%s has shape %s, expected [..., %s]" % (name, tuple(t.shape), shape))
     return t.contiguous()
+
+
+def _op_params(dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18) -> _lib.OpParams:
+    p = _lib.OpParams()
+    load().lq_op_params_default(ctypes.byref(p))
+    for i in range(4):
+        p.dims[i] = int(dims[i])
+    p.kappa = float(kappa)
+    p.csw = float(csw)
+    p.bc = _bc_array(bc)
+    p.clover_traceless = int(bool(traceless))
+    p.link_recon = int(link_recon)
+    return p
+
+
+def workspace_bytes(dims, csw=0.0, link_recon=18, nrhs: int = 1) -> int:
+    """Bytes of the device workspace an operator of this lattice needs for
+    calls of up to nrhs right-hand sides (lq_workspace_bytes; no GPU needed)."""
+    n = ctypes.c_size_t()
+    check(load().lq_workspace_bytes(ctypes.byref(_op_params(dims, 0.125, csw, None, True, link_recon)), int(nrhs),
+                                    ctypes.byref(n)))
+    return n.value
 
 
 @dataclass
@@ -84,18 +109,11 @@ class Operator:
 
     def __init__(self, dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18):
         lib = load()
-        p = _lib.OpParams()
-        lib.lq_op_params_default(ctypes.byref(p))
-        for i in range(4):
-            p.dims[i] = int(dims[i])
-        p.kappa = float(kappa)
-        p.csw = float(csw)
-        p.bc = _bc_array(bc)
-        p.clover_traceless = int(bool(traceless))
-        p.link_recon = int(link_recon)
+        p = _op_params(dims, kappa, csw, bc, traceless, link_recon)
         h = ctypes.c_void_p()
         check(lib.lq_op_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
+        self._ws = None  # the bound workspace (a torch uint8 tensor), if any
         self.dims = tuple(int(d) for d in dims)
         self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
         self.full_shape = tuple(self.dims[::-1]) + (4, 3)
@@ -105,6 +123,27 @@ class Operator:
         if getattr(self, "_h", None):
             load().lq_op_destroy(self._h)
             self._h = None
+        self._ws = None
+
+    def workspace_bytes(self, nrhs: int = 1) -> int:
+        n = ctypes.c_size_t()
+        check(load().lq_op_workspace_bytes(self._h, int(nrhs), ctypes.byref(n)))
+        return n.value
+
+    def bind(self, nrhs: int = 1) -> torch.Tensor:
+        """Allocate the operator's device memory as one torch tensor (uint8,
+        lq_op_workspace_bytes(nrhs) bytes) and bind it (lq_op_bind): from
+        then on the library allocates no device memory for set_gauge, apply
+        and solve.  Drops the gauge field (set it again).  Returns the tensor."""
+        ws = torch.empty(self.workspace_bytes(nrhs), dtype=torch.uint8, device="cuda")
+        check(load().lq_op_bind(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        self._ws = ws
+        return ws
+
+    def unbind(self):
+        """Give the device memory back to the library's own allocations."""
+        check(load().lq_op_bind(self._h, None, 0))
+        self._ws = None
 
     def __del__(self):
         try:
@@ -117,8 +156,10 @@ class Operator:
         return self._h
 
     def set_gauge(self, U: torch.Tensor):
-        U = _dev(U, self.dims[::-1] + (4, 3, 3), "U")
-        check(load().lq_op_set_gauge(self._h, ctypes.c_void_p(U.data_ptr()), _stream()))
+        """U on the GPU (lq_op_set_gauge) or in host memory (lq_op_set_gauge_host)."""
+        U = _dev(U, self.dims[::-1] + (4, 3, 3), "U", host_ok=True)
+        fn = load().lq_op_set_gauge if U.is_cuda else load().lq_op_set_gauge_host
+        check(fn(self._h, ctypes.c_void_p(U.data_ptr()), _stream()))
 
     def set_params(self, kappa, csw, bc=None):
         arr = None if bc is None else _bc_array(bc)
@@ -126,14 +167,17 @@ class Operator:
                                       None if arr is None else ctypes.byref(arr), _stream()))
 
     def apply(self, kind: str, psi: torch.Tensor, prec: str = "f64") -> torch.Tensor:
-        """out = K psi for K in D, Ddag, DdagD (full fields) or the parity kinds."""
+        """out = K psi for K in D, Ddag, DdagD (full fields) or the parity kinds;
+        psi on the GPU (lq_op_apply) or in host memory (lq_op_apply_host, the
+        result then in host memory too)."""
         full = kind in _lib.FULL_KINDS
         shape = self.full_shape if full else self.parity_shape
-        psi = _dev(psi, shape, "psi")
+        psi = _dev(psi, shape, "psi", host_ok=True)
         nrhs = psi.numel() // (12 * (self.V if full else self.V // 2))
         out = torch.empty_like(psi)
-        check(load().lq_op_apply(self._h, _lib.KINDS[kind], _lib.PREC[prec], ctypes.c_void_p(out.data_ptr()),
-                                 ctypes.c_void_p(psi.data_ptr()), nrhs, _stream()))
+        fn = load().lq_op_apply if psi.is_cuda else load().lq_op_apply_host
+        check(fn(self._h, _lib.KINDS[kind], _lib.PREC[prec], ctypes.c_void_p(out.data_ptr()),
+                 ctypes.c_void_p(psi.data_ptr()), nrhs, _stream()))
         return out
 
     def apply_noalloc(self, kind: str, psi: torch.Tensor, out: torch.Tensor, prec: str = "f64") -> torch.Tensor:
@@ -214,9 +258,12 @@ class Operator:
                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x0.data_ptr()), _stream()))
         return x0
 
-    def tune(self, nrhs: int = 1, cache: str | None = None) -> dict:
-        """Autotune the hopping kernels (lq_tune); returns the JSON report."""
+    def tune(self, nrhs: int = 1, cache: str | None = None, left: bool = False) -> dict:
+        """Autotune the hopping kernels (lq_tune) on the operator form the
+        solver will run (left: the A_ee^-1-preconditioned inner system of
+        left_precond); returns the JSON report."""
         import json
+        self.set_option("tune_form", int(bool(left)))
         buf = ctypes.create_string_buffer(4096)
         check(load().lq_tune(self._h, int(nrhs), cache.encode() if cache else None, buf, len(buf), _stream()))
         return json.loads(buf.value.decode())
@@ -224,22 +271,39 @@ class Operator:
     def solve(self, b: torch.Tensor, mode: str = "D", params: SolverParams | None = None,
               x0: torch.Tensor | None = None):
         """x = mode^-1 b for mode D, Ddag or DdagD (invert of Fig. 1).
-        b: [nrhs?, Lt, Lz, Ly, Lx, 4, 3] complex128.  Returns (x, [SolveStats])."""
+        b: [nrhs?, Lt, Lz, Ly, Lx, 4, 3] complex128 on the GPU (lq_solve) or in
+        host memory (lq_solve_host; x then in host memory too).  Returns
+        (x, [SolveStats])."""
         params = params or SolverParams()
-        b = _dev(b, self.full_shape, "b")
+        b = _dev(b, self.full_shape, "b", host_ok=True)
         nrhs = b.numel() // (12 * self.V)
         if x0 is not None:
-            x = _dev(x0, self.full_shape, "x0").clone()
+            x = _dev(x0, self.full_shape, "x0", host_ok=True).to(b.device).clone()
         else:
             x = torch.empty_like(b)  # not read without a guess; every entry is written
         stats = (_lib.SolveStats * nrhs)()
         cp = params.to_c()
-        st = load().lq_solve(self._h, ctypes.byref(cp), _lib.KINDS[mode], nrhs, ctypes.c_void_p(x.data_ptr()),
-                             ctypes.c_void_p(b.data_ptr()), int(x0 is not None), stats, _stream())
+        fn = load().lq_solve if b.is_cuda else load().lq_solve_host
+        st = fn(self._h, ctypes.byref(cp), _lib.KINDS[mode], nrhs, ctypes.c_void_p(x.data_ptr()),
+                ctypes.c_void_p(b.data_ptr()), int(x0 is not None), stats, _stream())
         check(st, allow_not_converged=True)
         out = [SolveStats(s.nconv, s.nouter, s.restarts, bool(s.converged), s.diff, s.t_solve_ms, s.hop_bytes, s.n_hop)
                for s in stats]
         return x, out
+
+
+def bandwidth_probe(nbytes: int = 1 << 30, mode: str = "copy", reps: int = 10) -> float:
+    """GB/s of the library's copy (bytes read + written) or read-only probe
+    kernel over nbytes of device memory (lq_bandwidth_probe)."""
+    nbytes = int(nbytes) // 16 * 16
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda") if mode == "copy" else None
+    us = ctypes.c_double()
+    check(load().lq_bandwidth_probe(0 if mode == "copy" else 1, ctypes.c_void_p(dst.data_ptr()) if dst is not None
+                                    else None, ctypes.c_void_p(src.data_ptr()), nbytes, int(reps), ctypes.byref(us),
+                                    _stream()))
+    moved = nbytes * (2 if mode == "copy" else 1)
+    return moved / (us.value * 1e-6) / 1e9
 
 
 class Field:

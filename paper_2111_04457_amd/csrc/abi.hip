@@ -143,21 +143,11 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
         lq_op *op = new lq_op();
         op->prm = *p;
         op->device = dev;
-        Geom &g = op->g;
-        for (int i = 0; i < 4; ++i) {
-            g.L[i] = p->dims[i];
-            g.bc_re[i] = p->bc[i][0];
-            g.bc_im[i] = p->bc[i][1];
-        }
-        g.lxh = p->dims[0] / 2;
-        g.vh = (int)(vol / 2);
+        op->g = make_geom(*p);
         op->has_clover = p->csw != 0.0;
         try {
-            op->links[F64].ensure(8 * link_bytes(F64, 18, g.vh));
-            op->links[F32].ensure(8 * link_bytes(F32, p->link_recon, g.vh));
-            op->links[F16].ensure(8 * link_bytes(F16, p->link_recon, g.vh));
-            if (p->link_recon == 12) op->links64r.ensure(8 * link_bytes(F64, 12, g.vh));
-            op->flag.ensure(sizeof(int));
+            // device memory comes later: a bound workspace, or allocations on
+            // first use (lq_op_set_gauge)
             LQ_HIP(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
             LQ_HIP(hipEventCreateWithFlags(&op->ev_in, hipEventDisableTiming));
             LQ_HIP(hipEventCreateWithFlags(&op->ev_out, hipEventDisableTiming));
@@ -188,10 +178,19 @@ static void build_clover(lq_op *op, hipStream_t s)
         op->clovinv[p].ensure(2 * clover_bytes(p, g.vh));
     }
     {
-        Buf fbuf;  // the field strengths, freed once the blocks are built
-        fbuf.ensure(clover_fbuf_bytes(g.vh));
+        // the field strengths: in the solver's region of a bound workspace,
+        // else a buffer freed once the blocks are built
+        Buf own;
+        char *fbuf;
+        if (op->bound_nrhs) {
+            op->solver_ws.ensure(clover_fbuf_bytes(g.vh));
+            fbuf = op->solver_ws.ptr;
+        } else {
+            own.ensure(clover_fbuf_bytes(g.vh));
+            fbuf = own.ptr;
+        }
         LQ_HIP(launch_clover_build(g, op->links[F64].ptr, op->prm.csw, op->prm.kappa, op->prm.clover_traceless,
-                                   fbuf.ptr, op->clov[F64].ptr, s));
+                                   fbuf, op->clov[F64].ptr, s));
         LQ_HIP(hipStreamSynchronize(s));
     }
     // only A_oo is inverted: the even-odd operators use A_ee and A_oo^-1
@@ -208,22 +207,48 @@ static void build_clover(lq_op *op, hipStream_t s)
     if (flag) throw Failure{LQ_ERR_SINGULAR, "a clover block A_oo = 1 + F on an odd site is singular"};
 }
 
+// Pack the links of the device complex128 gauge field U in every precision
+// and build the clover term.
+static void set_gauge_device(lq_op *op, const double *U, hipStream_t s)
+{
+    const Geom &g = op->g;
+    op->gauge_set = false;
+    op->clear_graphs();
+    op->links[F64].ensure(8 * link_bytes(F64, 18, g.vh));
+    op->links[F32].ensure(8 * link_bytes(F32, op->prm.link_recon, g.vh));
+    op->links[F16].ensure(8 * link_bytes(F16, op->prm.link_recon, g.vh));
+    if (op->prm.link_recon == 12) op->links64r.ensure(8 * link_bytes(F64, 12, g.vh));
+    op->flag.ensure(sizeof(int));
+    LQ_HIP(launch_pack_links_f64(g, U, op->links[F64].ptr, s));
+    LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F32, op->prm.link_recon, op->links[F32].ptr, s));
+    LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F16, op->prm.link_recon, op->links[F16].ptr, s));
+    if (op->prm.link_recon == 12) LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F64, 12, op->links64r.ptr, s));
+    build_clover(op, s);
+    op->gauge_set = true;
+}
+
 lq_status lq_op_set_gauge(lq_op *op, const void *U, void *stream)
 {
     if (!op || !U) return arg_error("lq_op_set_gauge: null argument");
     return guarded([&]() -> lq_status {
         select_device(op);
+        set_gauge_device(op, static_cast<const double *>(U), static_cast<hipStream_t>(stream));
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_set_gauge_host(lq_op *op, const void *U, void *stream)
+{
+    if (!op || !U) return arg_error("lq_op_set_gauge_host: null argument");
+    return guarded([&]() -> lq_status {
+        select_device(op);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const Geom &g = op->g;
-        op->gauge_set = false;
+        // staged in the solver's region (unused between solves)
+        const size_t bytes = (size_t)op->g.vh * 2 * 4 * 9 * 16;
+        op->solver_ws.ensure(bytes);
         op->clear_graphs();
-        LQ_HIP(launch_pack_links_f64(g, static_cast<const double *>(U), op->links[F64].ptr, s));
-        LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F32, op->prm.link_recon, op->links[F32].ptr, s));
-        LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F16, op->prm.link_recon, op->links[F16].ptr, s));
-        if (op->prm.link_recon == 12)
-            LQ_HIP(launch_convert_links(g, op->links[F64].ptr, F64, 12, op->links64r.ptr, s));
-        build_clover(op, s);
-        op->gauge_set = true;
+        LQ_HIP(hipMemcpyAsync(op->solver_ws.ptr, U, bytes, hipMemcpyHostToDevice, s));
+        set_gauge_device(op, reinterpret_cast<const double *>(op->solver_ws.ptr), s);
         return LQ_OK;
     });
 }
@@ -236,6 +261,11 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
         for (int i = 0; i < 4; ++i)
             if (!(std::fabs(std::hypot(bc[i][0], bc[i][1]) - 1.0) < 1e-12))
                 return arg_error("lq_op_set_params: boundary phases must have modulus 1");
+    if (op->bound_nrhs && csw != 0.0 && op->clov[F64].bytes < 2 * (size_t)clover_bytes(F64, op->g.vh)) {
+        set_error("lq_op_set_params: the bound workspace has no room for clover blocks (it was laid out with "
+                  "csw = 0): bind one of lq_op_workspace_bytes bytes after setting csw");
+        return LQ_ERR_NOMEM;
+    }
     return guarded([&]() -> lq_status {
         select_device(op);
         op->clear_graphs();
@@ -256,40 +286,82 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
     });
 }
 
-lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs, void *stream)
+// Bytes of the complex128 boundary-layout field of kind (full or parity) and nrhs.
+static size_t io_bytes(const lq_op *op, lq_kind kind, int nrhs)
 {
-    if (!op || !out || !in) return arg_error("lq_op_apply: null argument");
-    if (kind < LQ_D || kind > LQ_SCHUR_LEFT) return arg_error("lq_op_apply: unknown kind");
-    if (!valid_prec(prec)) return arg_error("lq_op_apply: unknown precision");
-    if (nrhs < 1) return arg_error("lq_op_apply: nrhs must be >= 1");
-    if (out == in) return arg_error("lq_op_apply: out and in must differ");
+    return (size_t)(kind_is_full(kind) ? 2 : 1) * op->g.vh * 12 * 16 * nrhs;
+}
+
+static lq_status check_apply_args(const char *fn, lq_op *op, lq_kind kind, lq_prec prec, const void *out,
+                                  const void *in, int nrhs)
+{
+    const std::string f(fn);
+    if (!op || !out || !in) return arg_error(f + ": null argument");
+    if (kind < LQ_D || kind > LQ_SCHUR_LEFT) return arg_error(f + ": unknown kind");
+    if (!valid_prec(prec)) return arg_error(f + ": unknown precision");
+    if (nrhs < 1) return arg_error(f + ": nrhs must be >= 1");
+    if (out == in) return arg_error(f + ": out and in must differ");
+    if (op->bound_nrhs && nrhs > op->bound_nrhs)
+        return arg_error(f + ": the bound workspace holds " + std::to_string(op->bound_nrhs) + " right-hand sides, " +
+                         std::to_string(nrhs) + " requested");
     if (!op->gauge_set) {
-        set_error("lq_op_apply: gauge field not set");
+        set_error(f + ": gauge field not set");
         return LQ_ERR_STATE;
     }
+    return LQ_OK;
+}
+
+// out = K in on device complex128 fields, through the packed buffers tmp[2], tmp[3].
+static void apply_device(lq_op *op, lq_kind kind, lq_prec prec, double *dst, const double *src, int nrhs,
+                         hipStream_t s)
+{
+    const Geom &g = op->g;
+    const bool full = kind_is_full(kind);
+    const long bytes = (full ? 2 : 1) * fb(prec, g) * nrhs;
+    op->tmp[2].ensure(bytes);
+    op->tmp[3].ensure(bytes);
+    if (full) {
+        for (int p = 0; p < 2; ++p)
+            LQ_HIP(launch_pack_spinor(g, p, 0, src, full_parity_view(op->tmp[2].ptr, prec, g, nrhs, p), s));
+    } else {
+        LQ_HIP(launch_pack_spinor(g, 0, 1, src, parity_view(op->tmp[2].ptr, prec, g, nrhs), s));
+    }
+    apply_packed(op, kind, prec, op->tmp[3].ptr, op->tmp[2].ptr, nrhs, s);
+    if (full) {
+        for (int p = 0; p < 2; ++p)
+            LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(op->tmp[3].ptr, prec, g, nrhs, p), dst, s));
+    } else {
+        LQ_HIP(launch_unpack_spinor(g, 0, 1, parity_view(op->tmp[3].ptr, prec, g, nrhs), dst, s));
+    }
+}
+
+lq_status lq_op_apply(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs, void *stream)
+{
+    const lq_status st = check_apply_args("lq_op_apply", op, kind, prec, out, in, nrhs);
+    if (st != LQ_OK) return st;
+    return guarded([&]() -> lq_status {
+        select_device(op);
+        apply_device(op, kind, prec, static_cast<double *>(out), static_cast<const double *>(in), nrhs,
+                     static_cast<hipStream_t>(stream));
+        return LQ_OK;
+    });
+}
+
+lq_status lq_op_apply_host(lq_op *op, lq_kind kind, lq_prec prec, void *out, const void *in, int nrhs, void *stream)
+{
+    const lq_status st = check_apply_args("lq_op_apply_host", op, kind, prec, out, in, nrhs);
+    if (st != LQ_OK) return st;
     return guarded([&]() -> lq_status {
         select_device(op);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const Geom &g = op->g;
-        const bool full = kind_is_full(kind);
-        const long bytes = (full ? 2 : 1) * fb(prec, g) * nrhs;
-        op->tmp[2].ensure(bytes);
-        op->tmp[3].ensure(bytes);
-        const double *src = static_cast<const double *>(in);
-        double *dst = static_cast<double *>(out);
-        if (full) {
-            for (int p = 0; p < 2; ++p)
-                LQ_HIP(launch_pack_spinor(g, p, 0, src, full_parity_view(op->tmp[2].ptr, prec, g, nrhs, p), s));
-        } else {
-            LQ_HIP(launch_pack_spinor(g, 0, 1, src, parity_view(op->tmp[2].ptr, prec, g, nrhs), s));
-        }
-        apply_packed(op, kind, prec, op->tmp[3].ptr, op->tmp[2].ptr, nrhs, s);
-        if (full) {
-            for (int p = 0; p < 2; ++p)
-                LQ_HIP(launch_unpack_spinor(g, p, 0, full_parity_view(op->tmp[3].ptr, prec, g, nrhs, p), dst, s));
-        } else {
-            LQ_HIP(launch_unpack_spinor(g, 0, 1, parity_view(op->tmp[3].ptr, prec, g, nrhs), dst, s));
-        }
+        const size_t n = io_bytes(op, kind, nrhs);
+        op->tmp[6].ensure(n);
+        op->tmp[7].ensure(n);
+        LQ_HIP(hipMemcpyAsync(op->tmp[6].ptr, in, n, hipMemcpyHostToDevice, s));
+        apply_device(op, kind, prec, reinterpret_cast<double *>(op->tmp[7].ptr),
+                     reinterpret_cast<const double *>(op->tmp[6].ptr), nrhs, s);
+        LQ_HIP(hipMemcpyAsync(out, op->tmp[7].ptr, n, hipMemcpyDeviceToHost, s));
+        LQ_HIP(hipStreamSynchronize(s));
         return LQ_OK;
     });
 }
@@ -439,6 +511,9 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
     else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F32] = value;
     else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F16] = value;
     else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
+    else if (n == "tune_form" && (value == 0 || value == 1)) op->tune_form = value;
+    else if (n == "break_at" && value >= 0) op->break_at = value;
+    else if (n == "log_level" && value >= 0 && value <= 2) op->log_level = value;
     else return arg_error("lq_op_set_option: unknown option or value: " + n);
     op->clear_graphs();
     return LQ_OK;
@@ -455,10 +530,15 @@ lq_status lq_op_get_option(const lq_op *op, const char *name, int *value)
     else if (n == "rhs_per_thread_f32") *value = op->rhs_per_thread[F32];
     else if (n == "rhs_per_thread" || n == "rhs_per_thread_f16") *value = op->rhs_per_thread[F16];
     else if (n == "graphs") *value = op->use_graphs;
+    else if (n == "tune_form") *value = op->tune_form;
+    else if (n == "break_at") *value = op->break_at;
+    else if (n == "log_level") *value = op->log_level;
     else if (n == "hop_block_f64") *value = op->hop_block[F64];
     else if (n == "hop_block_f32") *value = op->hop_block[F32];
     else if (n == "hop_block_f16") *value = op->hop_block[F16];
     else if (n == "work_kib") *value = (int)std::min<size_t>(op->work_bytes() >> 10, 0x7fffffff);
+    else if (n == "owned_kib") *value = (int)std::min<size_t>((op->owned_bytes() + 1023) >> 10, 0x7fffffff);
+    else if (n == "bound_nrhs") *value = op->bound_nrhs;
     else return arg_error("lq_op_get_option: unknown option: " + n);
     return LQ_OK;
 }

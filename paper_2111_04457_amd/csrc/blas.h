@@ -25,6 +25,8 @@ enum ScalarSlot {
     SC_ODONE,    // 1: outer residual already below target (inner solve skipped)
     SC_OTARGET2, // target of FIN_NORM for SC_ODONE
     SC_DOT_RE, SC_DOT_IM,
+    SC_FORCE_BREAK,  // > 0: BiCGStab takes rho_new = 0 at this iteration (a breakdown forced from
+                     // the host to exercise the restart path; 0 in every ordinary solve)
     NSC = 24
 };
 
@@ -40,7 +42,9 @@ enum FinishOp {
     FIN_DOT             // K=2: SC_DOT
 };
 
-// Per-slice reductions written to partial[(slice * nblocks + block) * K + k].
+// Per-slice reductions written to partial[(slice * nblocks + block) * K + k]
+// (ragged fields: partial[tile * K + k]).  Every vector kernel also takes
+// ragged fields (FieldView::tiles), all operands with the same slices.
 enum ReduceMode { RED_NORM = 1, RED_DOT = 2, RED_DOT_NORM = 3 };
 
 int blas_blocks(long n);
@@ -52,9 +56,11 @@ int blas_blocks(long n);
 hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s,
                          const double *mask = nullptr, int sps = 1);
 // finish: sums partials of nsys systems (sps slices each, nblocks per slice,
-// K values) and runs op on the scalars sc[sys * NSC + ...].
+// K values; or, with range, range[sys].y partials from index range[sys].x:
+// the partials of a ragged field's or a batched hop's systems) and runs op
+// on the scalars sc[sys * NSC + ...].
 hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,
-                         double eps, hipStream_t s);
+                         double eps, hipStream_t s, const int2 *range = nullptr);
 
 // Elementwise kernels (complex scalars read from sc of each slice's system,
 // system = slice / sps; systems with SC_DONE or SC_BREAK set are skipped

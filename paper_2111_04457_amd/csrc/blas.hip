@@ -18,6 +18,44 @@ template <typename R> __device__ __forceinline__ cx<R> scal(const double *sc, in
 
 __device__ __forceinline__ bool frozen(const double *sc) { return sc[SC_DONE] != 0.0 || sc[SC_BREAK] != 0.0; }
 
+// The site of this thread: slice, site index i, the slice's length n, and
+// the index of this workgroup's partial sum (one per workgroup, slice by
+// slice).  A uniform field's grid is (sites / BT, slices); a ragged one's
+// (tiles).
+struct Loc {
+    long i;
+    int slice;
+    long n;
+    long site_off;  // ragged: padded sites before the slice; uniform: -1
+    long part;
+};
+
+__device__ __forceinline__ Loc locate(const FieldView &x)
+{
+    Loc l;
+    if (x.tiles) {
+        const Tile t = x.tiles[blockIdx.x];
+        l.i = (long)t.blk * BT + threadIdx.x;
+        l.slice = t.slice;
+        l.n = t.n;
+        l.site_off = t.site_off;
+        l.part = blockIdx.x;
+    } else {
+        l.i = (long)blockIdx.x * BT + threadIdx.x;
+        l.slice = blockIdx.y;
+        l.n = x.n;
+        l.site_off = -1;
+        l.part = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    }
+    return l;
+}
+
+// Base of this thread's slice in field v (of v's own precision).
+__device__ __forceinline__ char *at(const FieldView &v, const Loc &l)
+{
+    return l.site_off >= 0 ? v.base + l.site_off * (spinor_field_bytes(v.prec, SB) / SB) : v.base + l.slice * v.rs;
+}
+
 // ------------------------------------------------------------ reductions --
 
 template <int P, int MODE>
@@ -25,17 +63,18 @@ __global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, do
                                                    int sps)
 {
     using R = typename PT<P>::R;
-    const long i = (long)blockIdx.x * BT + threadIdx.x;
-    const int slice = blockIdx.y;
+    const Loc L = locate(x);
+    const long i = L.i;
+    const int slice = L.slice;
     double a = 0, b = 0, c = 0;
     const bool live = !mask || !frozen(mask + (slice / sps) * NSC);
-    if (i < x.n && live) {
-        const Spinor<R> xv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+    if (i < L.n && live) {
+        const Spinor<R> xv = load_spinor<P>(at(x, L), i, L.n);
         if constexpr (MODE == RED_NORM) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) a += (double)norm2(xv.c[k]);
         } else {
-            const Spinor<R> yv = load_spinor<P>(y.base + slice * y.rs, i, y.n);
+            const Spinor<R> yv = load_spinor<P>(at(y, L), i, L.n);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cx<R> t = cmulc(xv.c[k], yv.c[k]);
@@ -47,7 +86,7 @@ __global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, do
     }
     __shared__ double lds[BT / 64];
     constexpr int K = MODE == RED_NORM ? 1 : MODE == RED_DOT ? 2 : 3;
-    double *out = partial + ((long)slice * gridDim.x + blockIdx.x) * K;
+    double *out = partial + L.part * K;
     const double sa = block_sum<BT>(a, lds);
     if (threadIdx.x == 0) out[0] = sa;
     if constexpr (K >= 2) {
@@ -63,7 +102,7 @@ __global__ __launch_bounds__(BT) void reduce_kernel(FieldView x, FieldView y, do
 hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hipStream_t s, const double *mask,
                          int sps)
 {
-    const dim3 grid(blas_blocks(x.n), x.nrhs);
+    const dim3 grid = x.tiles ? dim3(x.ntiles) : dim3(blas_blocks(x.n), x.nrhs);
 #define LQ_RED(P)                                                                                            \
     if (mode == RED_NORM) reduce_kernel<P, RED_NORM><<<grid, BT, 0, s>>>(x, y, partial, mask, sps);         \
     else if (mode == RED_DOT) reduce_kernel<P, RED_DOT><<<grid, BT, 0, s>>>(x, y, partial, mask, sps);      \
@@ -82,11 +121,13 @@ hipError_t launch_reduce(FieldView x, FieldView y, int mode, double *partial, hi
 // partials in a fixed order, then update the system's scalars.
 constexpr int FT = 1024;
 __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int sps, int nblocks, int K, int op,
-                                                   double *scal, double eps)
+                                                   double *scal, double eps, const int2 *range)
 {
     const int sys = blockIdx.x;
-    const long cnt = (long)sps * nblocks;
-    const double *p = partial + (long)sys * cnt * K;
+    // a system's partials: sps * nblocks of them in order, or (ragged) the
+    // count range[sys].y starting at range[sys].x
+    const long cnt = range ? (long)range[sys].y : (long)sps * nblocks;
+    const double *p = partial + (range ? (long)range[sys].x : (long)sys * cnt) * K;
     double v[3] = {0, 0, 0};
     // each thread adds its partials j = tid, tid + FT, ... in that order;
     // the loads of 8 of them are issued together
@@ -186,7 +227,8 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
         break;
     }
     case FIN_BICG_RHO: {
-        const double pr = tot[0], pi = tot[1], rr = tot[2];
+        const bool forced = sc[SC_FORCE_BREAK] > 0 && sc[SC_ITER] + 1.0 == sc[SC_FORCE_BREAK];
+        const double pr = forced ? 0.0 : tot[0], pi = forced ? 0.0 : tot[1], rr = tot[2];
         if (fz) {
             sc[SC_BETA_RE] = sc[SC_BETA_IM] = 0.0;
             break;
@@ -224,18 +266,19 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
 }
 
 hipError_t launch_finish(const double *partial, int nsys, int sps, int nblocks, int K, int op, double *sc,
-                         double eps, hipStream_t s)
+                         double eps, hipStream_t s, const int2 *range)
 {
-    finish_kernel<<<nsys, FT, 0, s>>>(partial, sps, nblocks, K, op, sc, eps);
+    finish_kernel<<<nsys, FT, 0, s>>>(partial, sps, nblocks, K, op, sc, eps, range);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------- elementwise --
 
 #define LQ_SITE                                                 \
-    const long i = (long)blockIdx.x * BT + threadIdx.x;         \
-    const int slice = blockIdx.y;                               \
-    if (i >= x.n) return;
+    const Loc L = locate(x);                                    \
+    const long i = L.i;                                         \
+    const int slice = L.slice;                                  \
+    if (i >= L.n) return;
 
 template <int P> __global__ __launch_bounds__(BT) void zero_kernel(FieldView x)
 {
@@ -244,7 +287,7 @@ template <int P> __global__ __launch_bounds__(BT) void zero_kernel(FieldView x)
     Spinor<R> z;
 #pragma unroll
     for (int k = 0; k < 12; ++k) z.c[k] = cx<R>{0, 0};
-    store_spinor<P>(x.base + slice * x.rs, i, x.n, z);
+    store_spinor<P>(at(x, L), i, L.n, z);
 }
 
 template <int PY, int PX>
@@ -253,12 +296,12 @@ __global__ __launch_bounds__(BT) void copy_kernel(FieldView y, FieldView x, cons
     using RX = typename PT<PX>::R;
     using RY = typename PT<PY>::R;
     LQ_SITE
-    const Spinor<RX> v = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+    const Spinor<RX> v = load_spinor<PX>(at(x, L), i, L.n);
     const double f = scaled ? sc[(slice / sps) * NSC + SC_INVSCALE] : 1.0;
     Spinor<RY> o;
 #pragma unroll
     for (int k = 0; k < 12; ++k) o.c[k] = cx<RY>{(RY)(f * (double)v.c[k].re), (RY)(f * (double)v.c[k].im)};
-    store_spinor<PY>(y.base + slice * y.rs, i, y.n, o);
+    store_spinor<PY>(at(y, L), i, L.n, o);
 }
 
 template <int PE>
@@ -269,36 +312,36 @@ __global__ __launch_bounds__(BT) void accum_kernel(FieldView x, FieldView e, con
     const double *s = sc + (slice / sps) * NSC;
     if (s[SC_ODONE] != 0.0) return;
     const double f = scaled ? s[SC_SCALE] : 1.0;
-    Spinor<double> xv = load_spinor<F64>(x.base + slice * x.rs, i, x.n);
-    const Spinor<RE> ev = load_spinor<PE>(e.base + slice * e.rs, i, e.n);
+    Spinor<double> xv = load_spinor<F64>(at(x, L), i, L.n);
+    const Spinor<RE> ev = load_spinor<PE>(at(e, L), i, L.n);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         xv.c[k].re += f * (double)ev.c[k].re;
         xv.c[k].im += f * (double)ev.c[k].im;
     }
-    store_spinor<F64>(x.base + slice * x.rs, i, x.n, xv);
+    store_spinor<F64>(at(x, L), i, L.n, xv);
 }
 
 __global__ __launch_bounds__(BT) void xmy_norm_kernel(FieldView r, FieldView b, FieldView x /* y */,
                                                      double *partial)
 {
-    const long i = (long)blockIdx.x * BT + threadIdx.x;
-    const int slice = blockIdx.y;
+    const Loc L = locate(r);
+    const long i = L.i;
     double a = 0;
-    if (i < r.n) {
-        const Spinor<double> bv = load_spinor<F64>(b.base + slice * b.rs, i, b.n);
-        const Spinor<double> yv = load_spinor<F64>(x.base + slice * x.rs, i, x.n);
+    if (i < L.n) {
+        const Spinor<double> bv = load_spinor<F64>(at(b, L), i, L.n);
+        const Spinor<double> yv = load_spinor<F64>(at(x, L), i, L.n);
         Spinor<double> o;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             o.c[k] = bv.c[k] - yv.c[k];
             a += norm2(o.c[k]);
         }
-        store_spinor<F64>(r.base + slice * r.rs, i, r.n, o);
+        store_spinor<F64>(at(r, L), i, L.n, o);
     }
     __shared__ double lds[BT / 64];
     const double t = block_sum<BT>(a, lds);
-    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[L.part] = t;
 }
 
 // r -= sc[SC_SCALE] e (systems with SC_ODONE set keep r) and partial |r|^2
@@ -307,25 +350,26 @@ __global__ __launch_bounds__(BT) void sub_scaled_norm_kernel(FieldView r, FieldV
                                                             double *partial)
 {
     using RE = typename PT<PE>::R;
-    const long i = (long)blockIdx.x * BT + threadIdx.x;
-    const int slice = blockIdx.y;
+    const Loc L = locate(r);
+    const long i = L.i;
+    const int slice = L.slice;
     const double *s = sc + (slice / sps) * NSC;
     const double f = s[SC_ODONE] != 0.0 ? 0.0 : s[SC_SCALE];
     double a = 0;
-    if (i < r.n) {
-        Spinor<double> rv = load_spinor<F64>(r.base + slice * r.rs, i, r.n);
-        const Spinor<RE> ev = load_spinor<PE>(e.base + slice * e.rs, i, e.n);
+    if (i < L.n) {
+        Spinor<double> rv = load_spinor<F64>(at(r, L), i, L.n);
+        const Spinor<RE> ev = load_spinor<PE>(at(e, L), i, L.n);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             rv.c[k].re -= f * (double)ev.c[k].re;
             rv.c[k].im -= f * (double)ev.c[k].im;
             a += norm2(rv.c[k]);
         }
-        store_spinor<F64>(r.base + slice * r.rs, i, r.n, rv);
+        store_spinor<F64>(at(r, L), i, L.n, rv);
     }
     __shared__ double lds[BT / 64];
     const double t = block_sum<BT>(a, lds);
-    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[L.part] = t;
 }
 
 template <int P, int PX>
@@ -334,33 +378,34 @@ __global__ __launch_bounds__(BT) void cg_xr_kernel(FieldView x, FieldView r, Fie
 {
     using R = typename PT<P>::R;
     using RX = typename PT<PX>::R;
-    const long i = (long)blockIdx.x * BT + threadIdx.x;
-    const int slice = blockIdx.y;
+    const Loc L = locate(r);
+    const long i = L.i;
+    const int slice = L.slice;
     const double *s = sc + (slice / sps) * NSC;
     double a = 0;
-    if (i < r.n && !frozen(s)) {
-        Spinor<R> rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+    if (i < L.n && !frozen(s)) {
+        Spinor<R> rv = load_spinor<P>(at(r, L), i, L.n);
         {
             const R al = (R)s[SC_ALPHA_RE];
-            const Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
-            const Spinor<R> qv = load_spinor<P>(q.base + slice * q.rs, i, q.n);
-            Spinor<RX> xv = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+            const Spinor<R> pv = load_spinor<P>(at(p, L), i, L.n);
+            const Spinor<R> qv = load_spinor<P>(at(q, L), i, L.n);
+            Spinor<RX> xv = load_spinor<PX>(at(x, L), i, L.n);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 xv.c[k].re += (RX)(al * pv.c[k].re);
                 xv.c[k].im += (RX)(al * pv.c[k].im);
                 rv.c[k] = rv.c[k] - al * qv.c[k];
             }
-            store_spinor<PX>(x.base + slice * x.rs, i, x.n, xv);
-            store_spinor<P>(r.base + slice * r.rs, i, r.n, rv);
-            if constexpr (PT<P>::scaled) rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
+            store_spinor<PX>(at(x, L), i, L.n, xv);
+            store_spinor<P>(at(r, L), i, L.n, rv);
+            if constexpr (PT<P>::scaled) rv = load_spinor<P>(at(r, L), i, L.n);
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) a += (double)norm2(rv.c[k]);
     }
     __shared__ double lds[BT / 64];
     const double t = block_sum<BT>(a, lds);
-    if (threadIdx.x == 0) partial[(long)slice * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[L.part] = t;
 }
 
 template <int P>
@@ -371,11 +416,11 @@ __global__ __launch_bounds__(BT) void cg_p_kernel(FieldView p, FieldView x /* r 
     const double *s = sc + (slice / sps) * NSC;
     if (s[SC_BREAK] != 0.0) return;
     const R be = (R)s[SC_BETA_RE];
-    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
-    Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+    const Spinor<R> rv = load_spinor<P>(at(x, L), i, L.n);
+    Spinor<R> pv = load_spinor<P>(at(p, L), i, L.n);
 #pragma unroll
     for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + be * pv.c[k];
-    store_spinor<P>(p.base + slice * p.rs, i, p.n, pv);
+    store_spinor<P>(at(p, L), i, L.n, pv);
 }
 
 template <int P>
@@ -387,12 +432,12 @@ __global__ __launch_bounds__(BT) void bicg_s_kernel(FieldView sv, FieldView x /*
     const double *s = sc + (slice / sps) * NSC;
     if (frozen(s)) return;
     const cx<R> al = scal<R>(s, SC_ALPHA_RE);
-    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
-    const Spinor<R> vv = load_spinor<P>(v.base + slice * v.rs, i, v.n);
+    const Spinor<R> rv = load_spinor<P>(at(x, L), i, L.n);
+    const Spinor<R> vv = load_spinor<P>(at(v, L), i, L.n);
     Spinor<R> o;
 #pragma unroll
     for (int k = 0; k < 12; ++k) o.c[k] = rv.c[k] - al * vv.c[k];
-    store_spinor<P>(sv.base + slice * sv.rs, i, sv.n, o);
+    store_spinor<P>(at(sv, L), i, L.n, o);
 }
 
 template <int P, int PX>
@@ -401,19 +446,20 @@ __global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, F
 {
     using R = typename PT<P>::R;
     using RX = typename PT<PX>::R;
-    const long i = (long)blockIdx.x * BT + threadIdx.x;
-    const int slice = blockIdx.y;
+    const Loc L = locate(r);
+    const long i = L.i;
+    const int slice = L.slice;
     const double *s = sc + (slice / sps) * NSC;
     double a = 0, b = 0, c = 0;
-    if (i < r.n) {
+    if (i < L.n) {
         Spinor<R> rv;
         if (!frozen(s)) {
             const cx<R> al = scal<R>(s, SC_ALPHA_RE);
             const cx<R> om = scal<R>(s, SC_OMEGA_RE);
-            const Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
-            const Spinor<R> svv = load_spinor<P>(sv.base + slice * sv.rs, i, sv.n);
-            const Spinor<R> tv = load_spinor<P>(t.base + slice * t.rs, i, t.n);
-            Spinor<RX> xv = load_spinor<PX>(x.base + slice * x.rs, i, x.n);
+            const Spinor<R> pv = load_spinor<P>(at(p, L), i, L.n);
+            const Spinor<R> svv = load_spinor<P>(at(sv, L), i, L.n);
+            const Spinor<R> tv = load_spinor<P>(at(t, L), i, L.n);
+            Spinor<RX> xv = load_spinor<PX>(at(x, L), i, L.n);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cx<R> d = al * pv.c[k] + om * svv.c[k];
@@ -421,10 +467,10 @@ __global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, F
                 xv.c[k].im += (RX)d.im;
                 rv.c[k] = svv.c[k] - om * tv.c[k];
             }
-            store_spinor<PX>(x.base + slice * x.rs, i, x.n, xv);
-            store_spinor<P>(r.base + slice * r.rs, i, r.n, rv);
-            if constexpr (PT<P>::scaled) rv = load_spinor<P>(r.base + slice * r.rs, i, r.n);
-            const Spinor<R> hv = load_spinor<P>(rhat.base + slice * rhat.rs, i, rhat.n);
+            store_spinor<PX>(at(x, L), i, L.n, xv);
+            store_spinor<P>(at(r, L), i, L.n, rv);
+            if constexpr (PT<P>::scaled) rv = load_spinor<P>(at(r, L), i, L.n);
+            const Spinor<R> hv = load_spinor<P>(at(rhat, L), i, L.n);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cx<R> d = cmulc(hv.c[k], rv.c[k]);
@@ -435,7 +481,7 @@ __global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, F
         }
     }
     __shared__ double lds[BT / 64];
-    double *out = partial + ((long)slice * gridDim.x + blockIdx.x) * 3;
+    double *out = partial + L.part * 3;
     const double sa = block_sum<BT>(a, lds);
     const double sb = block_sum<BT>(b, lds);
     const double scc = block_sum<BT>(c, lds);
@@ -456,27 +502,27 @@ __global__ __launch_bounds__(BT) void bicg_p_kernel(FieldView p, FieldView x /* 
     if (frozen(s)) return;
     const cx<R> be = scal<R>(s, SC_BETA_RE);
     const cx<R> om = scal<R>(s, SC_OMEGA_RE);
-    const Spinor<R> rv = load_spinor<P>(x.base + slice * x.rs, i, x.n);
-    const Spinor<R> vv = load_spinor<P>(v.base + slice * v.rs, i, v.n);
-    Spinor<R> pv = load_spinor<P>(p.base + slice * p.rs, i, p.n);
+    const Spinor<R> rv = load_spinor<P>(at(x, L), i, L.n);
+    const Spinor<R> vv = load_spinor<P>(at(v, L), i, L.n);
+    Spinor<R> pv = load_spinor<P>(at(p, L), i, L.n);
 #pragma unroll
     for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + be * (pv.c[k] - om * vv.c[k]);
-    store_spinor<P>(p.base + slice * p.rs, i, p.n, pv);
+    store_spinor<P>(at(p, L), i, L.n, pv);
 }
 
 template <int P> __global__ __launch_bounds__(BT) void gamma5_kernel(FieldView x)
 {
     using R = typename PT<P>::R;
     LQ_SITE
-    Spinor<R> v = load_spinor<P>(x.base + slice * x.rs, i, x.n);
+    Spinor<R> v = load_spinor<P>(at(x, L), i, L.n);
 #pragma unroll
     for (int k = 6; k < 12; ++k) v.c[k] = cx<R>{-v.c[k].re, -v.c[k].im};
-    store_spinor<P>(x.base + slice * x.rs, i, x.n, v);
+    store_spinor<P>(at(x, L), i, L.n, v);
 }
 
 #undef LQ_SITE
 
-static dim3 grid_of(const FieldView &x) { return dim3(blas_blocks(x.n), x.nrhs); }
+static dim3 grid_of(const FieldView &x) { return x.tiles ? dim3(x.ntiles) : dim3(blas_blocks(x.n), x.nrhs); }
 
 #define LQ_BY_PREC(prec, KER, ...)                                                    \
     switch (prec) {                                                                   \

@@ -64,6 +64,22 @@ struct HopArgs {
 hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov, bool xpay, int red, int nr, int block,
                       hipStream_t s);
 
+// The hopping term of up to kMaxBatch lattices in one launch: lattice i's
+// arguments a[i] (its geometry, links, clover blocks and field slices, the
+// right-hand sides of its systems) and its workgroups tile_off[i] ..
+// tile_off[i + 1] - 1 (hop_blocks(vh_i, 64) * nrhs_i of them).  64 threads
+// per workgroup, one right-hand side per thread, the tiles in plain order.
+constexpr int kMaxBatch = 8;
+struct HopBatch {
+    HopArgs a[kMaxBatch];
+    int tile_off[kMaxBatch + 1];
+    int nlat;
+};
+// (passed by value as the kernel's argument, within the 4 KiB of kernel arguments)
+static_assert(sizeof(HopBatch) <= 4096, "HopBatch exceeds the kernel argument space");
+hipError_t launch_hop_batch(const HopBatch &b, int prec, int recon, bool dag, int clov, bool xpay, int red,
+                            hipStream_t s);
+
 // Number of workgroups launch_hop uses for a lattice of vh sites.
 inline int hop_blocks(int vh, int block) { return (vh + block - 1) / block; }
 

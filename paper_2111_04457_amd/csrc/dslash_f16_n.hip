@@ -10,4 +10,9 @@ hipError_t launch_hop_f16_n(const HopArgs &a, int recon, int clov, bool xpay, in
     return launch_pd<F16, false>(a, recon, clov, xpay, red, nr, block, s);
 }
 
+hipError_t launch_hop_batch_f16_n(const HopBatch &b, int recon, int clov, bool xpay, int red, hipStream_t s)
+{
+    return launch_pd_batch<F16, false>(b, recon, clov, xpay, red, s);
+}
+
 }  // namespace lq

@@ -278,9 +278,11 @@ __device__ __forceinline__ void write_partials(const HopArgs &a, long wave, int 
     }
 }
 
+// One workgroup of the hopping term: tile `id` of the launch (site block and
+// group of right-hand sides, in the visiting order below).
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR, int PF = Prefetch<P, NR>::value,
           int CACHE = CachePolicy<P, CLOV>::value>
-__device__ __forceinline__ void hop_body(const HopArgs &a)
+__device__ __forceinline__ void hop_body(const HopArgs &a, const int id)
 {
     using R = typename PT<P>::R;
     using S = typename PT<P>::S;
@@ -292,7 +294,6 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
     const int ngr = (a.nrhs + NR - 1) / NR;
     const int total = nbs * ngr;
     const int full = a.xcd_remap ? (total / 8) * 8 : 0;
-    const int id = blockIdx.x;
     const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
     const int k = t / ngr;
     const int rhs0 = (t - k * ngr) * NR;
@@ -338,7 +339,19 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int NT, int NR>
 __global__ __launch_bounds__(NT) void hop_kernel(HopArgs a)
 {
-    hop_body<P, NL, DAG, CLOV, XPAY, RED, NT, NR>(a);
+    hop_body<P, NL, DAG, CLOV, XPAY, RED, NT, NR>(a, blockIdx.x);
+}
+
+// The hopping term of several lattices in one launch (a ragged batch): the
+// workgroups tile_off[i] .. tile_off[i + 1] - 1 run lattice i's tiles with
+// its arguments (64 sites per workgroup, one right-hand side per thread).
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+__global__ __launch_bounds__(64) void hop_batch_kernel(HopBatch b)
+{
+    const int t = blockIdx.x;
+    int i = 0;
+    while (i + 1 < b.nlat && t >= b.tile_off[i + 1]) ++i;
+    hop_body<P, NL, DAG, CLOV, XPAY, RED, 64, 1>(b.a[i], t - b.tile_off[i]);
 }
 
 // ------------------------------------------- right-hand sides sharing LDS --
@@ -524,6 +537,45 @@ static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int
             if (clov == 3 && red == 3) return launch_nr<P, NL, DAG, 3, true, 3>(a, nr, block, s);
         }
     }
+    return hipErrorInvalidValue;
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+static hipError_t launch_batch1(const HopBatch &b, hipStream_t s)
+{
+    hop_batch_kernel<P, NL, DAG, CLOV, XPAY, RED><<<dim3(b.tile_off[b.nlat]), 64, 0, s>>>(b);
+    return hipGetLastError();
+}
+
+// The epilogue combinations of launch_epi for a batch.
+template <int P, int NL, bool DAG>
+static hipError_t launch_epi_batch(const HopBatch &b, int clov, bool xpay, int red, hipStream_t s)
+{
+    if (!xpay && red == 0) {
+        if (clov == 0) return launch_batch1<P, NL, DAG, 0, false, 0>(b, s);
+        if (clov == 2) return launch_batch1<P, NL, DAG, 2, false, 0>(b, s);
+    } else if (xpay) {
+        if (clov == 0 && red == 0) return launch_batch1<P, NL, DAG, 0, true, 0>(b, s);
+        if (clov == 0 && red == 2) return launch_batch1<P, NL, DAG, 0, true, 2>(b, s);
+        if (clov == 0 && red == 3) return launch_batch1<P, NL, DAG, 0, true, 3>(b, s);
+        if (clov == 1 && red == 0) return launch_batch1<P, NL, DAG, 1, true, 0>(b, s);
+        if (clov == 1 && red == 2) return launch_batch1<P, NL, DAG, 1, true, 2>(b, s);
+        if (clov == 1 && red == 3) return launch_batch1<P, NL, DAG, 1, true, 3>(b, s);
+        if (clov == 2 && red == 0) return launch_batch1<P, NL, DAG, 2, true, 0>(b, s);
+        if constexpr (!DAG) {
+            if (clov == 3 && red == 0) return launch_batch1<P, NL, DAG, 3, true, 0>(b, s);
+            if (clov == 3 && red == 2) return launch_batch1<P, NL, DAG, 3, true, 2>(b, s);
+            if (clov == 3 && red == 3) return launch_batch1<P, NL, DAG, 3, true, 3>(b, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, bool DAG>
+static hipError_t launch_pd_batch(const HopBatch &b, int recon, int clov, bool xpay, int red, hipStream_t s)
+{
+    if (recon == 18) return launch_epi_batch<P, 18, DAG>(b, clov, xpay, red, s);
+    if (recon == 12) return launch_epi_batch<P, 12, DAG>(b, clov, xpay, red, s);
     return hipErrorInvalidValue;
 }
 

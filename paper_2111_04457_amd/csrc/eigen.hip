@@ -592,7 +592,9 @@ extern "C" lq_status lq_eigs(lq_op *op, const lq_eig_params *prm, const void *v0
                 lam[i] = ar / xr;
                 lz.vec.axpy(w, lz.X(i), -lam[i], 0.0);
                 res[i] = lz.vec.norm(w) / std::sqrt(xr);
-                if (res[i] <= prm->tol * std::fabs(lam[i])) ++conv;
+                // with the filter, a pair above lo is not one of the wanted
+                // (lowest) ones: an eigenvalue above hi that T_d amplified
+                if (res[i] <= prm->tol * std::fabs(lam[i]) && (d == 0 || lam[i] <= lo)) ++conv;
             }
             if (conv == nev || cy.invariant || restarts >= prm->max_restarts || cy.meff < m) break;
             // thick restart: keep kk Ritz vectors of B and v_m

@@ -7,14 +7,29 @@
 
 namespace lq {
 
+// One workgroup's share of a ragged field (slices of different lengths, as
+// in a batch of lattices): sites blk * 256 .. of slice `slice`, which holds
+// n sites and starts site_off padded sites after the field's base.
+struct Tile {
+    int slice;
+    int blk;
+    int n;
+    int site_off;
+};
+
 // A packed spinor field in HBM: nrhs slices of one parity field each,
-// `rs` bytes apart, plane stride n sites.
+// `rs` bytes apart, plane stride n sites.  A ragged field (tiles != null)
+// holds nrhs slices of their own lengths, back to back; its vector kernels
+// run one workgroup per entry of the device array tiles[ntiles] (slice by
+// slice, in order).
 struct FieldView {
     char *base;
     int prec;
     long n;
     long rs;
     int nrhs;
+    const Tile *tiles = nullptr;
+    int ntiles = 0;
 };
 
 // Spinor import/export.  mode 0: src/dst is a full lexicographic field

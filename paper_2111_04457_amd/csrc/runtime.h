@@ -31,17 +31,23 @@ struct Failure {
             throw ::lq::Failure{LQ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};    \
     } while (0)
 
-// Owned device allocation.
+// A device buffer: allocated by the library (owned), or a region of a
+// workspace the caller bound to the operator (borrowed; never reallocated).
 struct Buf {
     char *ptr = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     Buf() = default;
     Buf(const Buf &) = delete;
     Buf &operator=(const Buf &) = delete;
     ~Buf() { release(); }
     void release();
-    // make sure at least n bytes are allocated (contents are not kept)
+    // make sure at least n bytes are available (contents are not kept); a
+    // borrowed region that is too small is an error, not a reallocation
     void ensure(size_t n);
+    // use [p, p + n) of a caller's allocation
+    void borrow(char *p, size_t n);
+    size_t owned() const { return borrowed ? 0 : bytes; }
 };
 
 }  // namespace lq
@@ -56,7 +62,10 @@ struct lq_op {
     int hop_block[3] = {64, 64, 64};     // workgroup size of the hop kernel per precision
     // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
     // 2 XCD-aware and time slices interleaved
-    int xcd_remap[3] = {1, 1, 1};
+    int xcd_remap[3] = {0, 0, 0};
+    int tune_form = 0;                   // operator form lq_tune times: 0 M, 1 A_ee^-1 M
+    int break_at = 0;                    // > 0: the next solve's first inner BiCGStab breaks down here
+    int log_level = 0;                   // progress lines of solves on stderr (also $LQ_LOG_LEVEL)
     int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
     int inner_hint = 0;                  // iterations the last inner solve needed (first chunk length)
     lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
@@ -64,7 +73,10 @@ struct lq_op {
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])
     lq::Buf clovinv[3];                  // A^-1 per precision ([parity])
     lq::Buf flag;                        // device int: singular clover block
-    lq::Buf tmp[6];                      // scratch fields for composite applies
+    // scratch fields: 0, 1 temporaries of composite applies; 2, 3 packed
+    // input / output of an apply; 4, 5 packed b and x of a solve; 6, 7
+    // staging of host inputs and outputs
+    lq::Buf tmp[8];
     lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
     lq::Buf defl_ws[3];                  // deflated guess: packed fields, even fields, partial sums
     lq::Buf md_G;                        // molecular dynamics: the force on every link
@@ -75,6 +87,8 @@ struct lq_op {
     lq::Buf solver_sc;                   // solver scalars (device)
     double *host_sc = nullptr;           // pinned host mirror of the solver scalars
     size_t host_sc_n = 0;
+    int bound_nrhs = 0;                  // > 0: device memory is the caller's bound workspace, laid
+                                         // out for this many right-hand sides
     int use_graphs = 1;                  // capture inner-iteration chunks in hipGraphs
     const double *hop_mask = nullptr;    // per-system freeze flags for hop kernels (set by the solvers)
     hipStream_t stream = nullptr;        // internal stream of solves (capturable)
@@ -116,6 +130,18 @@ struct lq_op {
         for (const auto &b : md_X) n += b.bytes;
         return n;
     }
+    // device bytes the library allocated itself for this operator (not
+    // counting regions of a bound workspace)
+    size_t owned_bytes() const
+    {
+        size_t n = links64r.owned() + flag.owned() + force_ws.owned() + md_G.owned() + md_partial.owned() +
+                   partial.owned() + solver_ws.owned() + solver_sc.owned();
+        for (int p = 0; p < 3; ++p) n += links[p].owned() + clov[p].owned() + clovinv[p].owned();
+        for (const auto &b : tmp) n += b.owned();
+        for (const auto &b : defl_ws) n += b.owned();
+        for (const auto &b : md_X) n += b.owned();
+        return n;
+    }
     // link format of the hop kernels (the clover build and the force use the
     // 18-real FP64 links)
     int nl(int) const { return prm.link_recon; }
@@ -151,6 +177,14 @@ inline FieldView full_parity_view(char *base, int prec, const Geom &g, int nrhs,
     return FieldView{base + p * fb(prec, g), prec, (long)g.vh, 2 * fb(prec, g), nrhs};
 }
 
+// Arguments of the hopping kernel for out = epilogue(coef * H_{p_out,1-p_out} in)
+// on op's links and clover blocks (default launch shape, no mask, no
+// reduction partials).
+HopArgs hop_args(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, int clov_mode, bool inv,
+                 const FieldView *y, double coef, const FieldView *w);
+// Freeze mask of the hopping kernel: the solver scalars sc of its right-hand sides.
+void set_hop_mask(HopArgs &a, const double *sc);
+
 // Hopping term on packed fields: out = epilogue(coef * H_{p_out,1-p_out} in).
 // clov_mode: 0 none, 1 clover on y, 2 clover on the result; inv selects A^-1.
 // red: 0 none, 2 per-rhs <w, out>, 3 <w, out> and |out|^2, as per-wavefront
@@ -172,6 +206,31 @@ void apply_temp_bytes(lq_kind kind, int prec, const Geom &g, int nrhs, size_t &t
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s);
 
 bool kind_is_full(lq_kind k);
+
+// Progress output level of solves: the larger of $LQ_LOG_LEVEL (read once)
+// and the operator's "log_level" option.
+int log_level(const lq_op *op);
+
+// Geometry of the lattice of p (dims, parity split, boundary phases).
+Geom make_geom(const lq_op_params &p);
+
+// The regions of an operator's device memory for calls of up to nrhs
+// right-hand sides: packed links and clover blocks (per gauge field) and the
+// work buffers of applies and solves, each starting on a 256-byte boundary.
+struct WorkspaceLayout {
+    enum Region {
+        LINKS64, LINKS32, LINKS16, LINKS64R, CLOV64, CLOV32, CLOV16, CLOVINV64, CLOVINV32, CLOVINV16, FLAG,
+        TMP0, TMP1, TMP2, TMP3, TMP4, TMP5, TMP6, TMP7, PARTIAL, SOLVER_SC, SOLVER_WS, NREGION
+    };
+    size_t off[NREGION] = {};
+    size_t size[NREGION] = {};
+    size_t total = 0;
+};
+WorkspaceLayout workspace_layout(const lq_op_params &p, int nrhs);
+
+// Bytes of the solver workspace of nsys systems (solve space even-odd or full
+// lattice, inner storage precision inner).
+size_t solver_ws_bytes(const Geom &g, int nsys, bool eo, int inner);
 
 // Schur operator M (or M^dag) on packed even fields; t: odd scratch field.
 // red / w: reduction fused into the second kernel (as for hop).

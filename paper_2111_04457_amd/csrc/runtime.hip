@@ -2,6 +2,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "blas.h"
 
@@ -17,14 +18,27 @@ const char *get_error() { return g_last_error.c_str(); }
 
 void Buf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !borrowed) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+    borrowed = false;
+}
+
+void Buf::borrow(char *p, size_t n)
+{
+    release();
+    ptr = p;
+    bytes = n;
+    borrowed = true;
 }
 
 void Buf::ensure(size_t n)
 {
-    if (n <= bytes && ptr) return;
+    if (n <= bytes && (ptr || borrowed)) return;
+    if (borrowed)
+        throw Failure{LQ_ERR_NOMEM, "the bound workspace is too small for this call (a region of " +
+                                        std::to_string(bytes) + " bytes, " + std::to_string(n) +
+                                        " needed): bind one of lq_op_workspace_bytes bytes for its nrhs"};
     release();
     if (n == 0) n = 256;
     void *p = nullptr;
@@ -39,8 +53,17 @@ void Buf::ensure(size_t n)
 
 bool kind_is_full(lq_kind k) { return k == LQ_D || k == LQ_DDAG || k == LQ_DDAGD; }
 
-void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, bool dag, int clov_mode,
-         bool inv, const FieldView *y, double coef, int red, const FieldView *w, hipStream_t s)
+int log_level(const lq_op *op)
+{
+    static const int env = [] {
+        const char *v = std::getenv("LQ_LOG_LEVEL");
+        return v ? std::atoi(v) : 0;
+    }();
+    return std::max(env, op ? op->log_level : 0);
+}
+
+HopArgs hop_args(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, int clov_mode, bool inv,
+                 const FieldView *y, double coef, const FieldView *w)
 {
     const Geom &g = op->g;
     HopArgs a{};
@@ -64,9 +87,19 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         a.w_rs = w->rs;
     }
     a.links = op->hop_links(prec);
-    if (clov_mode && !op->has_clover) clov_mode = 0;
-    if (clov_mode) a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
+    if (clov_mode && op->has_clover)
+        a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
     a.coef = coef;
+    return a;
+}
+
+void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, bool dag, int clov_mode,
+         bool inv, const FieldView *y, double coef, int red, const FieldView *w, hipStream_t s)
+{
+    if (out.tiles || in.tiles) throw Failure{LQ_ERR_STATE, "hop: a ragged field needs the batched hopping kernel"};
+    const Geom &g = op->g;
+    HopArgs a = hop_args(op, prec, out, in, p_out, clov_mode, inv, y, coef, w);
+    if (clov_mode && !op->has_clover) clov_mode = 0;
     a.xcd_remap = op->xcd_remap[prec] != 0 ? 1 : 0;
     if (op->hop_mask) {
         a.mask = op->hop_mask;
@@ -96,6 +129,14 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;
     }
     LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, nr, block, s));
+}
+
+void set_hop_mask(HopArgs &a, const double *sc)
+{
+    a.mask = sc;
+    a.mask_stride = MASK_STRIDE;
+    a.mask_off0 = MASK_DONE;
+    a.mask_off1 = MASK_BREAK;
 }
 
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s)

@@ -8,12 +8,57 @@
 #include "blas.h"
 #include "runtime.h"
 
+// A ragged batch: several lattices (operators of their own volumes and gauge
+// fields, nrhs[i] systems each) solved together, every stage of an inner
+// iteration one launch over all of them.  Its vectors are ragged fields:
+// the even-site slices of every system, lattice by lattice, back to back.
+struct lq_batch {
+    std::vector<lq_op *> ops;
+    std::vector<int> nrhs;
+    // layout of the systems (filled by the solve for the current operators)
+    std::vector<int> sys0;        // first system of lattice i
+    std::vector<long> site0;      // padded sites before lattice i's first slice
+    std::vector<long> hop_part0;  // partials of the fused hop reductions before lattice i
+    long sites = 0;               // padded sites of all slices
+    int nsys = 0;
+    int ntiles = 0;               // vector-kernel workgroups over all slices
+    lq::Buf tiles;                // lq::Tile[ntiles]
+    lq::Buf blas_range;           // int2[nsys]: each system's vector-kernel partials
+    lq::Buf hop_range;            // int2[nsys]: each system's fused-hop partials
+    lq::Buf ws, sc, partial;      // solver vectors, scalars, partial sums
+    double *host_sc = nullptr;    // pinned mirror of the scalars
+    size_t host_sc_n = 0;
+    int inner_hint = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<lq_op::GraphEntry> graphs;
+    std::vector<long> generations;  // of the operators when the graphs were captured
+    void clear_graphs()
+    {
+        for (auto &e : graphs) {
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            if (e.graph) (void)hipGraphDestroy(e.graph);
+        }
+        graphs.clear();
+    }
+    ~lq_batch()
+    {
+        clear_graphs();
+        if (host_sc) (void)hipHostFree(host_sc);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
 namespace lq {
 
 // Solver context: nsys systems on the solve space (even sites for the
-// even-odd Schur system, or the full lattice), workspace and scalars.
+// even-odd Schur system, or the full lattice), workspace and scalars; of one
+// operator (op) or of a ragged batch of operators (bt, even-odd only).
 struct SolveCtx {
     lq_op *op = nullptr;
+    lq_batch *bt = nullptr;
     hipStream_t s = nullptr;
     int nsys = 1;
     bool eo = true;   // even-odd Schur system (else full lattice)
@@ -30,6 +75,8 @@ struct SolveCtx {
     // applies are counted afterwards from the systems' iteration counters
     bool masked = false;
     bool left = false;   // inner applies use the A_ee^-1-preconditioned Schur operator
+    int force_break = 0; // > 0: the first inner BiCGStab solve breaks down at this iteration
+    int log = 0;         // progress lines on stderr: 0 none, 1 per solve, 2 per outer step
     // FP64 vectors of the solve space
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
@@ -38,6 +85,17 @@ struct SolveCtx {
 
     FieldView space(char *base, int p) const;
     size_t space_bytes(int p) const;
+    // groups of systems whose outer-loop decisions are taken together: the
+    // whole solve, or each lattice of a batch (so that each lattice's solve
+    // is exactly its solve on its own)
+    int ngroups() const { return bt ? (int)bt->ops.size() : 1; }
+    lq_op *group_op(int g) const { return bt ? bt->ops[g] : op; }
+    int group_sys0(int g) const { return bt ? bt->sys0[g] : 0; }
+    int group_nsys(int g) const { return bt ? bt->nrhs[g] : nsys; }
+    // group g's part of a solve-space vector (an ordinary field of its lattice)
+    FieldView group_view(const FieldView &v, int g) const;
+    // out = M in on group g alone (its operator's kernels; no mask)
+    void apply_group(int g, const FieldView &out, const FieldView &in, bool dag);
     void count_hops(int prec, int n);
     // account 4 hopping applies (two operator applies) per inner iteration
     // the systems performed since the last call
@@ -91,20 +149,30 @@ struct ChunkPlan {
 
 template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body)
 {
-    if (!op->use_graphs) {
+    if (!(bt ? bt->ops[0]->use_graphs : op->use_graphs)) {
         for (int k = 0; k < chunk; ++k) body();
         return;
     }
     // the graph replays the chunk with the masking state it was captured with
     const long masked_key = masked ? 1 : 0;
-    const std::vector<long> key = {kind, chunk, nsys, eo ? 1 : 0, pin, px, (long)op->solver_ws.ptr,
-                                   (long)op->solver_ws.bytes, (long)partial, (long)sc,
-                                   (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
-                                   (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
-                                   (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1],
-                                   (long)op->rhs_per_thread[2], (long)(void *)s, masked_key, left ? 1L : 0L};
+    std::vector<long> key = {kind, chunk, nsys, eo ? 1 : 0, pin, px, (long)partial, (long)sc, (long)(void *)s,
+                             masked_key, left ? 1L : 0L};
+    if (bt) {
+        // every pointer and launch setting the batched kernels read
+        key.push_back((long)bt->ws.ptr);
+        key.push_back((long)bt->ws.bytes);
+        key.push_back((long)bt->tiles.ptr);
+        for (const lq_op *o : bt->ops) key.push_back(o->generation);
+    } else {
+        const long k2[] = {(long)op->solver_ws.ptr, (long)op->solver_ws.bytes,
+                           (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
+                           (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
+                           (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1], (long)op->rhs_per_thread[2]};
+        key.insert(key.end(), k2, k2 + sizeof(k2) / sizeof(k2[0]));
+    }
+    std::vector<lq_op::GraphEntry> &graphs = bt ? bt->graphs : op->graphs;
     lq_op::GraphEntry *e = nullptr;
-    for (auto &g : op->graphs)
+    for (auto &g : graphs)
         if (g.key == key) e = &g;
     if (!e) {
         lq_op::GraphEntry ne;
@@ -126,8 +194,8 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
         ne.hop_bytes = hop_bytes - b0;
         n_hop = n0;
         hop_bytes = b0;
-        op->graphs.push_back(ne);
-        e = &op->graphs.back();
+        graphs.push_back(ne);
+        e = &graphs.back();
     }
     LQ_HIP(hipGraphLaunch(e->exec, s));
     n_hop += e->n_hop;
@@ -137,6 +205,9 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
 // Allocate the workspace of a solve of nsys systems with inner precision
 // `inner` on the even-odd (eo) or full-lattice space.
 void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t s);
+// Point the solver's vectors of c (space, precisions set) into base; odd:
+// bytes of each odd temporary.
+void carve_vectors(SolveCtx &c, char *base, size_t odd);
 
 struct OuterStats {
     std::vector<int> iters, outer, restarts;
@@ -163,6 +234,11 @@ bool valid_solver_params(const lq_solver_params *sp, std::string &why);
 
 // |v|^2 per system of a field with sps slices per system.
 std::vector<double> norms2(SolveCtx &c, const FieldView &v, int sps);
+
+// The batched Schur operator over every lattice of c.bt (two launches of the
+// batched hopping kernel), with the fused reductions of hop() (red, w).
+void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &in, const FieldView &odd, bool dag,
+                 bool left, int red, const FieldView *w);
 
 
 // The pseudofermion force of lq_pf_force with an initial guess X0 for the

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 namespace lq {
@@ -145,38 +146,95 @@ void ChunkPlan::learn(const SolveCtx &c)
     hint = most;
 }
 
+// bytes of one padded site of a packed spinor field
+static long site_bytes_of(int p) { return spinor_field_bytes(p, SB) / SB; }
+
 FieldView SolveCtx::space(char *base, int p) const
 {
+    if (bt) {
+        FieldView v{base, p, 0, 0, nsys};
+        v.tiles = reinterpret_cast<const Tile *>(bt->tiles.ptr);
+        v.ntiles = bt->ntiles;
+        return v;
+    }
     return FieldView{base, p, (long)op->g.vh, fb(p, op->g), nsys * sps};
 }
 
-size_t SolveCtx::space_bytes(int p) const { return (size_t)fb(p, op->g) * nsys * sps; }
+size_t SolveCtx::space_bytes(int p) const
+{
+    if (bt) return (size_t)site_bytes_of(p) * bt->sites;
+    return (size_t)fb(p, op->g) * nsys * sps;
+}
+
+FieldView SolveCtx::group_view(const FieldView &v, int g) const
+{
+    if (!bt) return v;
+    const lq_op *o = bt->ops[g];
+    return FieldView{v.base + site_bytes_of(v.prec) * bt->site0[g], v.prec, (long)o->g.vh, fb(v.prec, o->g),
+                     bt->nrhs[g]};
+}
 
 void SolveCtx::count_hops(int prec, int n)
 {
-    double b, f;
-    // per output site and system, the links shared by the nsys systems
-    lq_op_traffic(op, (lq_prec)prec, nsys, op->has_clover ? 1 : 0, &b, &f);
+    // per output site and system, the links shared by each operator's systems
+    for (int g = 0; g < ngroups(); ++g) {
+        double b, f;
+        lq_op *o = group_op(g);
+        lq_op_traffic(o, (lq_prec)prec, group_nsys(g), o->has_clover ? 1 : 0, &b, &f);
+        hop_bytes += (double)n * b * o->g.vh * group_nsys(g);
+    }
     n_hop += n;
-    hop_bytes += (double)n * b * op->g.vh * nsys;
 }
 
 void SolveCtx::count_iterations(std::vector<double> &prev)
 {
-    double b, f;
-    lq_op_traffic(op, (lq_prec)pin, nsys, op->has_clover ? 1 : 0, &b, &f);
-    for (int i = 0; i < nsys; ++i) {
-        const double it = hsc[i * NSC + SC_ITER];
-        const double d = it - prev[i];
-        prev[i] = it;
-        n_hop += (long)(4 * d);
-        hop_bytes += 4.0 * d * b * op->g.vh;
+    for (int g = 0; g < ngroups(); ++g) {
+        double b, f;
+        lq_op *o = group_op(g);
+        lq_op_traffic(o, (lq_prec)pin, group_nsys(g), o->has_clover ? 1 : 0, &b, &f);
+        for (int i = group_sys0(g); i < group_sys0(g) + group_nsys(g); ++i) {
+            const double it = hsc[i * NSC + SC_ITER];
+            const double d = it - prev[i];
+            prev[i] = it;
+            n_hop += (long)(4 * d);
+            hop_bytes += 4.0 * d * b * o->g.vh;
+        }
     }
+}
+
+void SolveCtx::apply_group(int g, const FieldView &out, const FieldView &in, bool dag)
+{
+    if (!bt) {
+        const bool m = masked;
+        masked = false;
+        try {
+            apply(out, in, dag);
+        } catch (...) {
+            masked = m;
+            throw;
+        }
+        masked = m;
+        return;
+    }
+    lq_op *o = bt->ops[g];
+    const int p = in.prec;
+    const FieldView t = group_view(space(odd_tmp[p], p), g);
+    if (left) schur_left(o, p, out, in, t, s);
+    else schur(o, p, out, in, t, dag, s);
+    double b, f;
+    lq_op_traffic(o, (lq_prec)p, group_nsys(g), o->has_clover ? 1 : 0, &b, &f);
+    n_hop += 2;
+    hop_bytes += 2.0 * b * o->g.vh * group_nsys(g);
 }
 
 void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
 {
     const int p = in.prec;
+    if (bt) {
+        batch_schur(*this, p, out, in, space(odd_tmp[p], p), dag, eo && left, 0, nullptr);
+        if (!masked) count_hops(p, 2);
+        return;
+    }
     op->hop_mask = masked ? sc : nullptr;
     try {
         const FieldView t{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys};
@@ -206,6 +264,13 @@ void SolveCtx::apply_reduce_finish(const FieldView &out, const FieldView &in, co
     }
     const int p = in.prec;
     const int red = mode == RED_DOT ? 2 : 3;
+    if (bt) {
+        batch_schur(*this, p, out, in, space(odd_tmp[p], p), false, left, red, &w);
+        if (!masked) count_hops(p, 2);
+        LQ_HIP(launch_finish(partial, nsys, 1, 0, red, op_fin, sc, 1e-30, s,
+                             reinterpret_cast<const int2 *>(bt->hop_range.ptr)));
+        return;
+    }
     op->hop_mask = masked ? sc : nullptr;
     try {
         const FieldView t{odd_tmp[p], p, (long)op->g.vh, fb(p, op->g), nsys};
@@ -226,12 +291,13 @@ void SolveCtx::reduce_finish(const FieldView &x, const FieldView &y, int mode, i
 {
     LQ_HIP(launch_reduce(x, y, mode, partial, s, masked ? sc : nullptr, sps));
     const int K = mode == RED_NORM ? 1 : mode == RED_DOT ? 2 : 3;
-    LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(x.n), K, op_fin, sc, 1e-30, s));
+    finish(K, op_fin, x.n);
 }
 
 void SolveCtx::finish(int K, int op_fin, long n)
 {
-    LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(n), K, op_fin, sc, 1e-30, s));
+    LQ_HIP(launch_finish(partial, nsys, sps, blas_blocks(n), K, op_fin, sc, 1e-30, s,
+                         bt ? reinterpret_cast<const int2 *>(bt->blas_range.ptr) : nullptr));
 }
 
 void SolveCtx::pull()
@@ -242,22 +308,14 @@ void SolveCtx::pull()
 
 void SolveCtx::push() { LQ_HIP(hipMemcpyAsync(sc, hsc, sizeof(double) * NSC * nsys, hipMemcpyHostToDevice, s)); }
 
-void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t s)
+// The solver's vectors, carved from base in the order solver_ws_bytes counts
+// them: x, r, y, t, aux (FP64), three odd temporaries (FP64 size), x and
+// M x in the inner solution precision, nine inner vectors.
+void carve_vectors(SolveCtx &c, char *base, size_t odd)
 {
-    const Geom &g = op->g;
-    c.op = op;
-    c.s = s;
-    c.nsys = nsys;
-    c.eo = eo;
-    c.sps = eo ? 1 : 2;
-    c.pin = inner;
-    c.px = inner == F64 ? F64 : F32;
     const size_t f64b = c.space_bytes(F64), finb = c.space_bytes(c.pin), fxb = c.space_bytes(c.px);
-    const size_t odd = (size_t)fb(F64, g) * nsys;
-    const size_t need = 5 * (f64b + 256) + 9 * (finb + 256) + 2 * (fxb + 256) + 3 * (odd + 256);
-    op->solver_ws.ensure(need);
     Arena A;
-    A.base = op->solver_ws.ptr;
+    A.base = base;
     c.x64 = c.space(A.take(f64b), F64);
     c.r64 = c.space(A.take(f64b), F64);
     c.y64 = c.space(A.take(f64b), F64);
@@ -274,6 +332,20 @@ void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t 
     c.irhat = c.space(A.take(finb), c.pin);
     c.iw = c.space(A.take(finb), c.pin);
     c.irin = c.space(A.take(finb), c.pin);
+}
+
+void make_ctx(SolveCtx &c, lq_op *op, int nsys, bool eo, int inner, hipStream_t s)
+{
+    const Geom &g = op->g;
+    c.op = op;
+    c.s = s;
+    c.nsys = nsys;
+    c.eo = eo;
+    c.sps = eo ? 1 : 2;
+    c.pin = inner;
+    c.px = inner == F64 ? F64 : F32;
+    op->solver_ws.ensure(solver_ws_bytes(g, nsys, eo, inner));
+    carve_vectors(c, op->solver_ws.ptr, (size_t)fb(F64, g) * nsys);
 
     op->solver_sc.ensure(sizeof(double) * NSC * nsys);
     c.sc = reinterpret_cast<double *>(op->solver_sc.ptr);
@@ -310,38 +382,19 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     os.iters.assign(nsys, 0);
     os.outer.assign(nsys, 0);
     os.restarts.assign(nsys, 0);
+    os.r2.assign(nsys, 0.0);
     int total_inner = 0;
     ChunkPlan plan;
-    plan.hint = c.op->inner_hint;  // from the operator's previous solve
+    int &hint = c.bt ? c.bt->inner_hint : c.op->inner_hint;
+    plan.hint = hint;  // from the previous solve
     // the outer target of each system (FIN_NORM flags systems below it)
     c.pull();
     for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
     c.push();
-    // r = rhs - A x in FP64, |r|^2 (A x = 0 for a zero initial guess)
-    auto true_residual = [&](bool zero_x) {
-        if (zero_x) {
-            LQ_HIP(launch_zero(c.y64, c.s));
-        } else if (normal) {
-            c.apply(c.t64, c.x64, false);
-            c.apply(c.y64, c.t64, true);
-        } else {
-            c.apply(c.y64, c.x64, false);
-        }
-        LQ_HIP(launch_xmy_norm(c.r64, rhs, c.y64, c.partial, c.s));
-        c.finish(1, FIN_NORM, c.r64.n);
-    };
-    bool all = true;
-    auto read_norms = [&]() {
-        c.pull();
-        all = true;
-        os.r2.assign(nsys, 0.0);
-        for (int i = 0; i < nsys; ++i) {
-            const double n2 = c.hsc[i * NSC + SC_NORM2];
-            os.r2[i] = n2;
-            if (!std::isfinite(n2)) throw Failure{LQ_ERR_NONFINITE, "residual is not finite"};
-            if (c.hsc[i * NSC + SC_ODONE] == 0.0) all = false;
-        }
-    };
+    // The outer loop keeps its decisions per group of systems (the whole
+    // solve, or each lattice of a batch, which then runs exactly as it would
+    // alone); the inner solves run on every system at once.
+    //
     // After an FP64 residual r, the next one may be updated as r - |r| M e
     // with M applied to the inner solution e in e's precision: that apply
     // rounds at ~1e-7 of |r|, a small fraction of the updated residual when
@@ -349,47 +402,120 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     // least 1e-3, as with binary16 storage).  The next residual is FP64
     // again, so the rounding never accumulates, and every convergence
     // decision is taken on an FP64 residual.  It pays only where the FP64
-    // apply is bandwidth-bound (at least 2^19 sites per parity over all
-    // systems): on less work its extra launches and the FP64 check of a
-    // converged update cost more than the FP64 apply they replace.
-    const bool can_update = !normal && c.eo && c.px != F64 && (long)c.op->g.vh * nsys >= (1L << 19);
-    bool last_fp64 = true;
-    double last_rel = 0.0;  // smallest relative target of the last inner solve
-    for (int step = 0; step <= sp.max_outer; ++step) {
-        const bool update = can_update && step > 0 && last_fp64 && last_rel >= 1e-3;
+    // apply is bandwidth-bound (at least 2^19 sites per parity over the
+    // group's systems): on less work its extra launches and the FP64 check
+    // of a converged update cost more than the FP64 apply they replace.
+    struct Group {
+        bool can_update = false, last_fp64 = true, update = false, all = false, done = false;
+        double last_rel = 0.0;  // smallest relative target of the last inner solve
+    };
+    const int ng = c.ngroups();
+    std::vector<Group> gs(ng);
+    for (int g = 0; g < ng; ++g)
+        gs[g].can_update = !normal && c.eo && c.px != F64 && (long)c.group_op(g)->g.vh * c.group_nsys(g) >= (1L << 19);
+    // r = rhs - A x in FP64 (A x = 0 for a zero initial guess), or the
+    // update r -= |r| M e, and |r|^2, on group g's systems
+    auto residual = [&](int g, bool zero_x, bool update) {
+        double *scg = c.sc + (long)c.group_sys0(g) * NSC;
+        const FieldView r = c.group_view(c.r64, g);
         if (update) {
-            c.apply(c.ex, c.ix, false);
-            LQ_HIP(launch_sub_scaled_norm(c.r64, c.ex, c.sc, c.sps, c.partial, c.s));  // r -= |r| M e
-            c.finish(1, FIN_NORM, c.r64.n);
+            const FieldView ex = c.group_view(c.ex, g);
+            c.apply_group(g, ex, c.group_view(c.ix, g), false);
+            LQ_HIP(launch_sub_scaled_norm(r, ex, scg, c.sps, c.partial, c.s));  // r -= |r| M e
         } else {
-            true_residual(step == 0 && x_zero);
+            const FieldView y = c.group_view(c.y64, g), x = c.group_view(c.x64, g);
+            if (zero_x) {
+                LQ_HIP(launch_zero(y, c.s));
+            } else if (normal) {
+                const FieldView t = c.group_view(c.t64, g);
+                c.apply_group(g, t, x, false);
+                c.apply_group(g, y, t, true);
+            } else {
+                c.apply_group(g, y, x, false);
+            }
+            LQ_HIP(launch_xmy_norm(r, c.group_view(rhs, g), y, c.partial, c.s));
+        }
+        LQ_HIP(launch_finish(c.partial, c.group_nsys(g), c.sps, blas_blocks(r.n), 1, FIN_NORM, scg, 1e-30, c.s));
+    };
+    auto read_norms = [&]() {
+        c.pull();
+        for (int g = 0; g < ng; ++g) {
+            if (gs[g].done) continue;
+            gs[g].all = true;
+            for (int i = c.group_sys0(g); i < c.group_sys0(g) + c.group_nsys(g); ++i) {
+                const double n2 = c.hsc[i * NSC + SC_NORM2];
+                os.r2[i] = n2;
+                if (!std::isfinite(n2)) throw Failure{LQ_ERR_NONFINITE, "residual is not finite"};
+                if (c.hsc[i * NSC + SC_ODONE] == 0.0) gs[g].all = false;
+            }
+        }
+    };
+    // the largest |r| / |b| of group g's systems (progress output)
+    auto max_rel_residual = [&](int g) {
+        double m = 0;
+        for (int i = c.group_sys0(g); i < c.group_sys0(g) + c.group_nsys(g); ++i)
+            if (target2[i] > 0) m = std::max(m, std::sqrt(os.r2[i] / target2[i]) * sp.tol);
+        return m;
+    };
+    bool first_inner = true;
+    for (int step = 0; step <= sp.max_outer; ++step) {
+        for (int g = 0; g < ng; ++g) {
+            Group &G = gs[g];
+            if (G.done) continue;
+            G.update = G.can_update && step > 0 && G.last_fp64 && G.last_rel >= 1e-3;
+            residual(g, step == 0 && x_zero, G.update);
         }
         read_norms();
         const bool last_step = step == sp.max_outer || total_inner >= sp.max_iter;
-        if (update && (all || last_step)) {
-            true_residual(false);
-            read_norms();
+        // a converged (or final) updated residual is confirmed in FP64
+        bool again = false;
+        for (int g = 0; g < ng; ++g)
+            if (!gs[g].done && gs[g].update && (gs[g].all || last_step)) {
+                residual(g, false, false);
+                again = true;
+            }
+        if (again) read_norms();
+        bool finished = true;
+        for (int g = 0; g < ng; ++g) {
+            Group &G = gs[g];
+            if (G.done) continue;
+            G.last_fp64 = !G.update || G.all || last_step;
+            if (G.all || last_step) G.done = true;
+            else finished = false;
         }
-        last_fp64 = !update || all || last_step;
-        if (all || last_step) break;
+        if (finished) break;
         // relative target of this inner solve, per system
-        last_rel = 1.0;
-        for (int i = 0; i < nsys; ++i) {
-            double *h = c.hsc + i * NSC;
-            const double rn = std::sqrt(h[SC_NORM2]);
-            double rel = 0.5 * std::sqrt(target2[i]) / (rn > 0 ? rn : 1.0);
-            if (c.pin != F64) rel = std::max(rel, sp.inner_tol);
-            rel = std::min(rel, 0.5);
-            if (h[SC_ODONE] == 0.0) last_rel = std::min(last_rel, rel);
-            h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT_* makes it absolute
-            if (h[SC_ODONE] == 0.0) os.outer[i]++;
+        for (int g = 0; g < ng; ++g) {
+            Group &G = gs[g];
+            if (G.done) continue;
+            G.last_rel = 1.0;
+            for (int i = c.group_sys0(g); i < c.group_sys0(g) + c.group_nsys(g); ++i) {
+                double *h = c.hsc + i * NSC;
+                const double rn = std::sqrt(h[SC_NORM2]);
+                double rel = 0.5 * std::sqrt(target2[i]) / (rn > 0 ? rn : 1.0);
+                if (c.pin != F64) rel = std::max(rel, sp.inner_tol);
+                rel = std::min(rel, 0.5);
+                if (h[SC_ODONE] == 0.0) G.last_rel = std::min(G.last_rel, rel);
+                h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT_* makes it absolute
+                h[SC_FORCE_BREAK] = first_inner ? c.force_break : 0;
+                if (h[SC_ODONE] == 0.0) os.outer[i]++;
+            }
+            if (c.log >= 2)
+                std::fprintf(stderr, "lq: outer step %d, lattice %d: |r| / |b| max %.3e (%s), inner target %.1e\n",
+                             step, g, max_rel_residual(g), G.update ? "updated" : "FP64", G.last_rel);
         }
+        first_inner = false;
         c.push();
         LQ_HIP(launch_copy(c.irin, c.r64, c.sc, c.sps, true, c.s));
         // left preconditioning of the inner system: A_ee^-1 M e = A_ee^-1 r
         // (the outer loop keeps the true residual of M x = b)
-        const bool left = sp.left_precond && c.eo && !normal && sp.solver == LQ_BICGSTAB && c.op->has_clover;
-        if (left) clover_apply(c.op, c.pin, 0, true, c.irin, c.irin, c.s);
+        const bool left = sp.left_precond && c.eo && !normal && sp.solver == LQ_BICGSTAB && c.group_op(0)->has_clover;
+        if (left)
+            for (int g = 0; g < ng; ++g)
+                if (!gs[g].done) {
+                    const FieldView in = c.group_view(c.irin, g);
+                    clover_apply(c.group_op(g), c.pin, 0, true, in, in, c.s);
+                }
         c.left = left;
         // a stagnating inner solve hands back to the outer loop after
         // kInnerCap iterations (a restart from the current FP64 iterate)
@@ -412,7 +538,21 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         // x += |r| e
         LQ_HIP(launch_accum(c.x64, c.ix, c.sc, c.sps, true, c.s));
     }
-    if (plan.hint > 0) c.op->inner_hint = plan.hint;
+    if (plan.hint > 0) hint = plan.hint;
+    if (c.log >= 1)
+        for (int g = 0; g < ng; ++g) {
+            int it = 0, outer = 0, rst = 0;
+            for (int i = c.group_sys0(g); i < c.group_sys0(g) + c.group_nsys(g); ++i) {
+                it = std::max(it, os.iters[i]);
+                outer = std::max(outer, os.outer[i]);
+                rst += os.restarts[i];
+            }
+            const Geom &gg = c.group_op(g)->g;
+            std::fprintf(stderr,
+                         "lq: solve %dx%dx%dx%d, %d systems: %d outer steps, %d inner iterations (most), %d restarts, "
+                         "|r| / |b| max %.3e\n",
+                         gg.L[0], gg.L[1], gg.L[2], gg.L[3], c.group_nsys(g), outer, it, rst, max_rel_residual(g));
+        }
     return os;
 }
 
@@ -424,6 +564,9 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
     const Geom &g = op->g;
     SolveCtx c;
     make_ctx(c, op, nsys, sp.even_odd != 0, sp.inner, s);
+    c.force_break = op->break_at;
+    op->break_at = 0;  // once
+    c.log = log_level(op);
     const auto t0 = std::chrono::steady_clock::now();
 
     const FieldView bfull{const_cast<char *>(b64), F64, (long)g.vh, fb(F64, g), 2 * nsys};
@@ -519,6 +662,9 @@ bool valid_solver_params(const lq_solver_params *sp, std::string &why)
 
 using namespace lq;
 
+static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
+                              int use_x0, lq_solve_stats *stats, void *stream);
+
 extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
                               int use_x0, lq_solve_stats *stats, void *stream)
 {
@@ -526,6 +672,52 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
         set_error("lq_solve: null argument");
         return LQ_ERR_ARG;
     }
+    return solve_device(op, sp, mode, nrhs, x, b, use_x0, stats, stream);
+}
+
+extern "C" lq_status lq_solve_host(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x,
+                                   const void *b, int use_x0, lq_solve_stats *stats, void *stream)
+{
+    if (!op || !sp || !x || !b) {
+        set_error("lq_solve_host: null argument");
+        return LQ_ERR_ARG;
+    }
+    if (nrhs < 1) {
+        set_error("lq_solve_host: nrhs < 1");
+        return LQ_ERR_ARG;
+    }
+    if (op->bound_nrhs && nrhs > op->bound_nrhs) {
+        set_error("lq_solve_host: the bound workspace holds " + std::to_string(op->bound_nrhs) +
+                  " right-hand sides, " + std::to_string(nrhs) + " requested");
+        return LQ_ERR_ARG;
+    }
+    if (!op->gauge_set) {
+        set_error("lq_solve_host: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    try {
+        LQ_HIP(hipSetDevice(op->device));
+        hipStream_t us = static_cast<hipStream_t>(stream);
+        // b and x staged in device buffers on the caller's stream
+        const size_t n = (size_t)op->g.vh * 2 * 12 * 16 * nrhs;
+        op->tmp[6].ensure(n);
+        op->tmp[7].ensure(n);
+        LQ_HIP(hipMemcpyAsync(op->tmp[6].ptr, b, n, hipMemcpyHostToDevice, us));
+        if (use_x0) LQ_HIP(hipMemcpyAsync(op->tmp[7].ptr, x, n, hipMemcpyHostToDevice, us));
+        const lq_status st = solve_device(op, sp, mode, nrhs, op->tmp[7].ptr, op->tmp[6].ptr, use_x0, stats, stream);
+        if (st < 0) return st;
+        LQ_HIP(hipMemcpyAsync(x, op->tmp[7].ptr, n, hipMemcpyDeviceToHost, us));
+        LQ_HIP(hipStreamSynchronize(us));
+        return st;
+    } catch (const Failure &f) {
+        set_error(f.msg);
+        return f.code;
+    }
+}
+
+static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
+                              int use_x0, lq_solve_stats *stats, void *stream)
+{
     if (mode != LQ_D && mode != LQ_DDAG && mode != LQ_DDAGD) {
         set_error("lq_solve: mode must be LQ_D, LQ_DDAG or LQ_DDAGD");
         return LQ_ERR_ARG;
@@ -533,6 +725,15 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
     std::string why;
     if (nrhs < 1 || !valid_solver_params(sp, why)) {
         set_error("lq_solve: invalid solver parameters: " + (nrhs < 1 ? std::string("nrhs < 1") : why));
+        return LQ_ERR_ARG;
+    }
+    if (op->bound_nrhs && nrhs > op->bound_nrhs) {
+        set_error("lq_solve: the bound workspace holds " + std::to_string(op->bound_nrhs) + " right-hand sides, " +
+                  std::to_string(nrhs) + " requested");
+        return LQ_ERR_ARG;
+    }
+    if (mode == LQ_DDAGD && use_x0) {
+        set_error("lq_solve: LQ_DDAGD solves from zero (two solves in sequence); use_x0 must be 0");
         return LQ_ERR_ARG;
     }
     if (!op->gauge_set) {
@@ -572,24 +773,23 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
             st = solve_packed(op, *sp, nrhs, xp, bp, use_x0, stats, s);
             LQ_HIP(launch_gamma5(xfull, s));
         } else {
-            // D^dag D x = b: y = (D^dag)^-1 b = gamma_5 D^-1 gamma_5 b, then x = D^-1 y
+            // D^dag D x = b: y = (D^dag)^-1 b = gamma_5 D^-1 gamma_5 b, then x = D^-1 y.
+            // With r1 = b - D^dag y and r2 = y - D x, b - D^dag D x = r1 + D^dag r2,
+            // so |b - D^dag D x| <= |r1| + |D| |r2|: the first solve runs to tol / 2
+            // and the second to tol |b| / (2 |D| |y|), with the bound
+            // |D| <= 1 + 16 kappa + 12 |c_sw| kappa: each of the eight hopping
+            // terms is kappa (1 -+ gamma_mu) (norm 2) times a unitary link; each of
+            // the six terms of F is c_sw kappa gamma_mu gamma_nu (norm 1) times
+            // Fhat, whose norm is at most 2 ((Q - Q^dag) / 8 with Q four unitary
+            // plaquettes, and at most as much again for the removed trace).
             std::vector<lq_solve_stats> st1(nrhs);
             LQ_HIP(launch_gamma5(bfull, s));
-            st = solve_packed(op, *sp, nrhs, xp, bp, false, st1.data(), s);
+            lq_solver_params sp1 = *sp;
+            sp1.tol = sp->tol * 0.5;
+            st = solve_packed(op, sp1, nrhs, xp, bp, false, st1.data(), s);
             if (st < 0) return st;
             LQ_HIP(launch_gamma5(xfull, s));  // y
             LQ_HIP(launch_gamma5(bfull, s));  // b restored
-            LQ_HIP(hipMemcpyAsync(bp, xp, full, hipMemcpyDeviceToDevice, s));  // b slot := y
-            lq_solver_params sp2 = *sp;
-            sp2.tol = sp->tol * 0.5;
-            st = solve_packed(op, sp2, nrhs, xp, bp, false, stats, s);
-            if (st < 0) return st;
-            // diff of the normal system |b - D^dag D x| / |b|, b re-packed
-            for (int p = 0; p < 2; ++p) LQ_HIP(launch_pack_spinor(g, p, 0, bsrc, full_parity_view(bp, F64, g, nrhs, p), s));
-            op->tmp[0].ensure(full);
-            op->tmp[1].ensure(full);
-            dirac_full(op, F64, op->tmp[0].ptr, xp, nrhs, false, s);
-            dirac_full(op, F64, op->tmp[1].ptr, op->tmp[0].ptr, nrhs, true, s);
             SolveCtx c;
             c.op = op;
             c.s = s;
@@ -598,6 +798,21 @@ extern "C" lq_status lq_solve(lq_op *op, const lq_solver_params *sp, lq_kind mod
             c.hsc = op->host_sc;
             c.partial = reinterpret_cast<double *>(op->partial.ptr);
             const std::vector<double> bn2 = norms2(c, bfull, 2);
+            const std::vector<double> yn2 = norms2(c, xfull, 2);
+            const double dnorm = 1.0 + std::fabs(op->prm.kappa) * (16.0 + 12.0 * std::fabs(op->prm.csw));
+            lq_solver_params sp2 = *sp;
+            sp2.tol = 0.5 * sp->tol;
+            for (int i = 0; i < nrhs; ++i)
+                if (yn2[i] > 0) sp2.tol = std::min(sp2.tol, 0.5 * sp->tol * std::sqrt(bn2[i] / yn2[i]) / dnorm);
+            LQ_HIP(hipMemcpyAsync(bp, xp, full, hipMemcpyDeviceToDevice, s));  // b slot := y
+            st = solve_packed(op, sp2, nrhs, xp, bp, false, stats, s);
+            if (st < 0) return st;
+            // diff of the normal system |b - D^dag D x| / |b|, b re-packed
+            for (int p = 0; p < 2; ++p) LQ_HIP(launch_pack_spinor(g, p, 0, bsrc, full_parity_view(bp, F64, g, nrhs, p), s));
+            op->tmp[0].ensure(full);
+            op->tmp[1].ensure(full);
+            dirac_full(op, F64, op->tmp[0].ptr, xp, nrhs, false, s);
+            dirac_full(op, F64, op->tmp[1].ptr, op->tmp[0].ptr, nrhs, true, s);
             const FieldView fy{op->tmp[1].ptr, F64, (long)g.vh, fb(F64, g), 2 * nrhs};
             const FieldView fr{op->tmp[0].ptr, F64, (long)g.vh, fb(F64, g), 2 * nrhs};
             LQ_HIP(launch_xmy_norm(fr, bfull, fy, c.partial, s));

@@ -1,14 +1,21 @@
 // tune.hip -- autotuner of the hopping kernels.
 //
-// For each storage precision the Schur operator M (two fused hopping
-// kernels, the work of every solver iteration) is timed with HIP events for
-// every workgroup size {64, 128, 256} and both workgroup orders (plain,
-// XCD-aware); the output of every candidate must be bitwise equal to the
-// first candidate's (each site's sum is formed in the same order whatever
-// the launch shape).  The fastest candidate is kept on the operator.  Results
-// are cached in a JSON file keyed by kernel, precision, lattice, link format,
-// right-hand sides and architecture; a cached entry is applied without
-// timing.
+// For each storage precision the work of one BiCGStab iteration on the
+// operator is timed with HIP events: two applies of the Schur operator
+// (M = A_ee - kappa^2 H_eo A_oo^-1 H_oe, or with the "tune_form" option 1 the
+// A_ee^-1-preconditioned 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe the inner
+// solves use with left_precond), each two fused hopping kernels, the second
+// with the dot products the solver fuses into it (<w, out>, then <w, out>
+// and |out|^2).  Candidates: workgroup sizes {64, 128, 256} x the three
+// workgroup orders (plain, XCD-aware, XCD-aware with time slices
+// interleaved), and with several right-hand sides four per workgroup with
+// links and clover blocks staged in LDS (binary16 / FP32).  The output of
+// every candidate must be bitwise equal to the first candidate's (each
+// site's sum is formed in the same order whatever the launch shape).  The
+// fastest candidate is kept on the operator, unless the shape the operator
+// had before is within 2 % of it.  Results are cached in a JSON file keyed
+// by operator form, precision, lattice, link format, right-hand sides and
+// architecture; a cached entry is applied without timing.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -26,12 +33,13 @@ namespace lq {
 
 namespace {
 
-std::string tune_key(const lq_op *op, int prec, int nrhs)
+std::string tune_key(const lq_op *op, int prec, int nrhs, bool left)
 {
     static const char *pn[3] = {"f64", "f32", "f16"};
     char buf[256];
-    std::snprintf(buf, sizeof buf, "schur_%s_%dx%dx%dx%d_nl%d_%s_nrhs%d_gfx950", pn[prec], op->g.L[0], op->g.L[1],
-                  op->g.L[2], op->g.L[3], op->nl(prec), op->has_clover ? "clover" : "wilson", nrhs);
+    std::snprintf(buf, sizeof buf, "%s_red_%s_%dx%dx%dx%d_nl%d_%s_nrhs%d_gfx950", left ? "schur_left" : "schur",
+                  pn[prec], op->g.L[0], op->g.L[1], op->g.L[2], op->g.L[3], op->nl(prec),
+                  op->has_clover ? "clover" : "wilson", nrhs);
     return buf;
 }
 
@@ -140,8 +148,10 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
         hipEvent_t e0, e1;
         LQ_HIP(hipEventCreate(&e0));
         LQ_HIP(hipEventCreate(&e1));
+        const bool left = op->tune_form == 1 && op->has_clover;
+        if (left) ensure_even_inverse(op, s);
         for (int prec = F64; prec <= F16; ++prec) {
-            const std::string key = tune_key(op, prec, nrhs);
+            const std::string key = tune_key(op, prec, nrhs, left);
             Entry best;
             best.key = key;
             bool found = false;
@@ -155,8 +165,18 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 op->tmp[2].ensure(b);
                 op->tmp[3].ensure(b);
                 // input: a deterministic smooth test field, the same for every rhs
+                op->tmp[0].ensure(b);
                 const FieldView in = parity_view(op->tmp[2].ptr, prec, g, nrhs);
                 const FieldView out = parity_view(op->tmp[3].ptr, prec, g, nrhs);
+                const FieldView odd = parity_view(op->tmp[0].ptr, prec, g, nrhs);
+                // one BiCGStab iteration's operator work: two applies, the
+                // dot products <w, out> and then <w, out>, |out|^2 fused
+                const auto iteration = [&]() {
+                    for (int red = 2; red <= 3; ++red) {
+                        if (left) schur_left(op, prec, out, in, odd, s, red, &in);
+                        else schur(op, prec, out, in, odd, false, s, red, &in);
+                    }
+                };
                 std::vector<double> host(24 * (size_t)g.vh);
                 for (size_t i = 0; i < host.size(); ++i) host[i] = std::sin(0.37 * (double)(i % 1021) + 0.11 * (double)(i / 1021));
                 op->tmp[5].ensure(host.size() * sizeof(double));
@@ -169,8 +189,11 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
                 const int save_nr = op->rhs_per_thread[prec];
-                std::vector<int> nrs = nrhs > 1 ? std::vector<int>{1, 2} : std::vector<int>{save_nr};
+                // (two right-hand sides per thread are not swept: they cannot
+                // carry the fused reductions and need twice the registers)
+                std::vector<int> nrs = {1};
                 if (nrhs >= 4 && prec != F64) nrs.push_back(4);
+                const int def_nr = nrhs > 1 && (save_nr == 1 || save_nr == 4) ? save_nr : 1;
                 for (int nrt : nrs)
                 for (int block : {256, 128, 64}) {
                     for (int remap : {2, 1, 0}) {
@@ -179,12 +202,12 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         op->hop_block[prec] = block;
                         op->xcd_remap[prec] = remap;
                         op->rhs_per_thread[prec] = nrt;
-                        for (int w = 0; w < 2; ++w) apply_packed(op, LQ_SCHUR, prec, out.base, in.base, nrhs, s);
+                        for (int w = 0; w < 2; ++w) iteration();
                         const int reps = g.vh >= (1 << 18) ? 10 : 40;
                         std::vector<float> t(reps);
                         for (int k = 0; k < reps; ++k) {
                             LQ_HIP(hipEventRecord(e0, s));
-                            apply_packed(op, LQ_SCHUR, prec, out.base, in.base, nrhs, s);
+                            iteration();
                             LQ_HIP(hipEventRecord(e1, s));
                             LQ_HIP(hipEventSynchronize(e1));
                             LQ_HIP(hipEventElapsedTime(&t[k], e0, e1));
@@ -208,16 +231,16 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                             best.xcd = remap;
                             best.nr = nrt;
                         }
-                        if (nrt == nrs[0] && block == 64 && remap == 0) default_us = us;
+                        if (nrt == def_nr && block == save_block && remap == save_remap) default_us = us;
                     }
                 }
-                // the default shape (64 threads, plain order) unless another is
-                // faster by more than 2 %: closer times are within run-to-run noise
+                // the shape the operator had unless another is faster by more
+                // than 2 %: closer times are within run-to-run noise
                 if (default_us <= 1.02 * best_us) {
                     best_us = default_us;
-                    best.block = 64;
-                    best.xcd = 0;
-                    best.nr = nrs[0];
+                    best.block = save_block;
+                    best.xcd = save_remap;
+                    best.nr = def_nr;
                 }
                 best.us = best_us;
                 cache.push_back(best);
@@ -225,7 +248,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             }
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
-            if (nrhs > 1 && (best.nr == 1 || best.nr == 2 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
+            if (nrhs > 1 && (best.nr == 1 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
                 << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";

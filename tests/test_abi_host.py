@@ -164,3 +164,67 @@ def test_eigensolver_entry_points_on_host(lib):
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     assert lib.lq_eigs(None, ctypes.byref(p), dummy, ev, None, None, None, None) == -1
     assert lib.lq_deflated_guess(None, 1, ev, dummy, dummy, dummy, None) == -1
+
+
+def _ws_bytes(lib, nrhs, **kw):
+    n = ctypes.c_size_t()
+    st = lib.lq_workspace_bytes(ctypes.byref(_params(**kw)), nrhs, ctypes.byref(n))
+    return st, n.value
+
+
+def _expected_workspace(dims, csw, nl, nrhs):
+    """The workspace written out region by region from the storage formats:
+    packed fields of padded 64-site blocks, 16-byte planes per site."""
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    pad = (vh + 63) // 64 * 64
+    r256 = lambda n: (n + 255) // 256 * 256  # noqa: E731
+    f64 = 192 * pad                       # one FP64 parity spinor field
+    f32, f16 = 96 * pad, 52 * pad
+    links = [8 * 18 * 8 * pad, 8 * nl * 4 * pad, 8 * nl * 2 * pad, 8 * 12 * 8 * pad if nl == 12 else 0]
+    clov = [2 * 72 * b * pad if csw else 0 for b in (8, 4, 2)] * 2
+    full = 2 * f64 * nrhs
+    tmps = [full, full, max(full, 8 * f64), max(full, 8 * f64), full, full, full, full]
+    nblk = max((vh + 63) // 64, (vh + 255) // 256)
+    partial = 8 * 3 * nblk * nrhs * 2
+    sc = 8 * 24 * nrhs
+
+    def solver(eo, fin, fx):
+        sps = 1 if eo else 2
+        return (5 * (f64 * nrhs * sps + 256) + 9 * (fin * nrhs * sps + 256) + 2 * (fx * nrhs * sps + 256)
+                + 3 * (f64 * nrhs + 256))
+    ws = max(solver(eo, fin, fx) for eo in (0, 1) for fin, fx in ((f64, f64), (f32, f32), (f16, f32)))
+    ws = max(ws, vh * 2 * 4 * 9 * 16, 2 * 6 * 18 * 8 * pad)
+    return sum(r256(x) for x in links + clov + [256] + tmps + [partial, sc, ws])
+
+
+@pytest.mark.parametrize("dims,csw,nl,nrhs", [
+    ((4, 4, 4, 4), 0.0, 18, 1), ((8, 8, 4, 8), 1.0, 12, 3), ((16, 16, 16, 32), 1.7, 12, 12),
+    ((6, 2, 4, 2), 1.0, 18, 5)])
+def test_workspace_bytes_region_by_region(lib, dims, csw, nl, nrhs):
+    st, n = _ws_bytes(lib, nrhs, dims=dims, csw=csw, link_recon=nl)
+    assert st == 0
+    assert n == _expected_workspace(dims, csw, nl, nrhs)
+    assert n % 256 == 0
+    # more right-hand sides never need less; the Python helper agrees
+    st2, n2 = _ws_bytes(lib, nrhs + 1, dims=dims, csw=csw, link_recon=nl)
+    assert st2 == 0 and n2 > n
+    from paper_2111_04457_amd.api import workspace_bytes
+    assert workspace_bytes(dims, csw, nl, nrhs) == n
+
+
+def test_workspace_and_bind_reject_bad_arguments(lib):
+    n = ctypes.c_size_t(7)
+    assert lib.lq_workspace_bytes(None, 1, ctypes.byref(n)) == -1
+    assert lib.lq_workspace_bytes(ctypes.byref(_params()), 1, None) == -1
+    for kw, frag in ((dict(dims=(4, 4, 3, 4)), b"even"), (dict(link_recon=10), b"link_recon")):
+        assert _ws_bytes(lib, 1, **kw)[0] == -1
+        assert frag in lib.lq_last_error()
+    assert _ws_bytes(lib, 0)[0] == -1 and b"nrhs" in lib.lq_last_error()
+    assert lib.lq_op_workspace_bytes(None, 1, ctypes.byref(n)) == -1
+    assert lib.lq_op_bind(None, None, 0) == -1
+    assert lib.lq_op_set_gauge_host(None, None, None) == -1
+    assert lib.lq_op_apply_host(None, 0, 0, None, None, 1, None) == -1
+    from paper_2111_04457_amd import _lib
+    sp = _lib.SolverParams()
+    lib.lq_solver_params_default(ctypes.byref(sp))
+    assert lib.lq_solve_host(None, ctypes.byref(sp), 0, 1, None, None, 0, None, None) == -1

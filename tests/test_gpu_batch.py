@@ -4,9 +4,11 @@
   Wilson-clover lattice solved as one 12-RHS solve (each loaded link used
   for several right-hand sides) match the oracle's true residual.
 - A ragged batch of lattices of different volumes, 4 Gaussian sources each,
-  solved with lq_batch_solve (every chunk of inner iterations of all
-  lattices in one hipGraph launch) equals the per-lattice solves bit for
-  bit, and every system reaches its true FP64 residual (oracle's D).
+  solved with lq_batch_solve (each stage of an inner iteration one launch
+  over all lattices' systems, every chunk of inner iterations captured in
+  one hipGraph) equals the per-lattice solves bit for bit, and every system
+  reaches its true FP64 residual (oracle's D).  Batches of more lattices
+  than one launch takes (8) run in groups of 8 with the same result.
 """
 import numpy as np
 import pytest
@@ -82,3 +84,63 @@ def test_batch_rejects_duplicate_operator(lq):
     with pytest.raises(lq.LQError):
         lq.Batch([op, op], [1, 1])
     op.close()
+
+
+def test_ragged_batch_of_nine_lattices_left_preconditioned(lq):
+    """Nine lattices (two launches of the batched hopping kernel per stage),
+    1 to 3 right-hand sides each, FP16 inner BiCGStab on the
+    A_ee^-1-preconditioned system: bit for bit the separate solves."""
+    dims_list = [(4, 4, 4, 4), (4, 4, 2, 6), (6, 4, 4, 4), (2, 4, 4, 8), (4, 6, 4, 6), (8, 4, 4, 4),
+                 (4, 4, 4, 8), (6, 6, 4, 4), (4, 8, 4, 4)]
+    nr = [1 + (i % 3) for i in range(len(dims_list))]
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=3, left_precond=True)
+    ops, bs, Us = [], [], []
+    for i, d in enumerate(dims_list):
+        U = gauge_exp(d, EPS, 1901 + i)
+        op = lq.Operator(d, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
+        op.set_gauge(to_dev(U))
+        ops.append(op)
+        Us.append(U)
+        bs.append(gaussian_spinor(d, 2901 + i, nr[i]))
+    batch = lq.Batch(ops, nr)
+    xs, st = batch.solve([to_dev(b) for b in bs], prm)
+    k = 0
+    for i, (op, d) in enumerate(zip(ops, dims_list)):
+        x1, s1 = op.solve(to_dev(bs[i]), "D", prm)
+        assert np.array_equal(to_host(xs[i]), to_host(x1)), d
+        assert [s.nconv for s in s1] == [s.nconv for s in st[k:k + nr[i]]]
+        ref = oracle.Operator(d, Us[i], KAPPA, CSW, ANTIPERIODIC_T)
+        xb = to_host(xs[i]).reshape((nr[i],) + bs[i].shape[-6:])
+        bb = bs[i].reshape(xb.shape)
+        for r in range(nr[i]):
+            assert oracle.true_residual(ref, xb[r], bb[r]) <= 1.01e-10, (d, r)
+        k += nr[i]
+    announce("nine-lattice batch iters %s" % [s.nconv for s in st])
+    batch.close()
+    for op in ops:
+        op.close()
+
+
+def test_batch_rejects_mixed_operators(lq):
+    """A batch needs one link format and one kind of operator (all clover or
+    all Wilson), and solves the even-odd system."""
+    d = (4, 4, 4, 4)
+    a = lq.Operator(d, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
+    b = lq.Operator(d, KAPPA, CSW, ANTIPERIODIC_T, link_recon=18)
+    with pytest.raises(lq.LQError, match="link format"):
+        lq.Batch([a, b], [1, 1])
+    c = lq.Operator(d, KAPPA, 0.0, ANTIPERIODIC_T, link_recon=12)
+    U = gauge_exp(d, EPS, 1950)
+    for o in (a, c):
+        o.set_gauge(to_dev(U))
+    batch = lq.Batch([a, c], [1, 1])
+    src = [to_dev(gaussian_spinor(d, 2950)), to_dev(gaussian_spinor(d, 2951))]
+    with pytest.raises(lq.LQError, match="clover"):
+        batch.solve(src, lq.SolverParams(tol=1e-10))
+    batch.close()
+    batch = lq.Batch([a], [1])
+    with pytest.raises(lq.LQError, match="even-odd"):
+        batch.solve(src[:1], lq.SolverParams(tol=1e-10, solver="cgne", even_odd=False))
+    batch.close()
+    for o in (a, b, c):
+        o.close()

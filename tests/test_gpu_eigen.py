@@ -251,6 +251,9 @@ def test_eigs_16x16x16x32_workload_against_oracle(lq):
     ev, res, X, st = op.eigs(8, 64, v0=to_dev(gaussian_parity_spinor(dims, 2008)), tol=1e-8, vectors=True)
     announce("  %s: %s, lowest %.6e, largest resid %.1e" % (name, st, ev[0], max(res)))
     assert st["nconv"] == 8
+    # the pairs are from the wanted end: every eigenvalue below the filter's
+    # lower edge (which lies above the 9th eigenvalue)
+    assert max(ev) <= st["cheb_lo"] < st["cheb_hi"]
     Xh = to_host(X).reshape(8, -1)
     assert np.abs(Xh.conj() @ Xh.T - np.eye(8)).max() < 1e-10
     ref = oracle.Operator(dims, U, w["kappa"], w["csw"], ANTIPERIODIC_T)

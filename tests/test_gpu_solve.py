@@ -181,3 +181,32 @@ def test_left_preconditioned_inner_solves(lq, clover_case, inner, recon):
             assert rel_err(x[i], xr[i]) < 50 * tol
     announce("  iterations: plain %s, A_ee^-1-preconditioned %s" % (iters[False], iters[True]))
     op.close()
+
+
+def test_forced_breakdown_restarts_and_converges(lq, clover_case, capfd):
+    """A BiCGStab breakdown forced from the host (rho = 0 at the first inner
+    solve's 3rd iteration): the system freezes, the FP64 outer loop counts a
+    restart and starts a new inner solve from its iterate, and the solve
+    still reaches the oracle's true residual and the oracle's solution.  The
+    option is one-shot, and log level 2 prints the outer steps."""
+    U, b, ref, xr = clover_case
+    op = lq.Operator(CLOVER["dims"], CLOVER["kappa"], CLOVER["csw"], ANTIPERIODIC_T)
+    op.set_gauge(to_dev(U))
+    prm = lq.SolverParams(tol=1e-10, inner="f32", inner_tol=1e-5)
+    _, st0 = op.solve(to_dev(b[0]), "D", prm)
+    assert st0[0].restarts == 0
+    op.set_option("break_at", 3)
+    op.set_option("log_level", 2)
+    x, st = op.solve(to_dev(b[0]), "D", prm)
+    err = capfd.readouterr().err
+    assert "lq: outer step 0" in err and "restarts" in err
+    assert op.get_option("break_at") == 0
+    assert st[0].restarts >= 1 and st[0].converged
+    res = oracle.true_residual(ref, to_host(x), b[0])
+    announce("  forced breakdown: %d restarts, %d iters (%d without), oracle residual %.2e"
+             % (st[0].restarts, st[0].nconv, st0[0].nconv, res))
+    assert res <= 1.01e-10 and rel_err(to_host(x), xr[0]) < 50 * 1e-10
+    op.set_option("log_level", 0)
+    _, st2 = op.solve(to_dev(b[0]), "D", prm)
+    assert st2[0].restarts == 0
+    op.close()

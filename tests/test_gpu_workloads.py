@@ -102,7 +102,7 @@ def test_full_size_mixed_solves_true_residual(lq, big):
     dims, U, b, w = big
     op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
     op.set_gauge(to_dev(U))
-    op.tune(1)
+    op.tune(1, left=True)
     F = oracle.clover(dims, U, w["csw"], w["kappa"])
     xs = {}
     for name, inner, itol, left in C2_SOLVES:
@@ -163,7 +163,7 @@ def test_propagator_24x24x24x48_twelve_rhs(lq, inner, itol):
     src = point_sources(dims)
     op = lq.Operator(dims, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=12)
     op.set_gauge(to_dev(U))
-    op.tune(12)
+    op.tune(12, left=True)
     announce("12-RHS propagator 24x24x24x48 inner %s" % inner)
     x, st = op.solve(to_dev(src), "D", lq.SolverParams(tol=1e-10, inner=inner, inner_tol=itol, check_every=10,
                                                        left_precond=True))
