@@ -511,6 +511,8 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
     else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F32] = value;
     else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F16] = value;
     else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
+    else if (n == "halo" && (value == 0 || value == 1)) op->halo[0] = op->halo[1] = op->halo[2] = value;
+    else if (n == "halo_f16" && (value == 0 || value == 1)) op->halo[F16] = value;
     else if (n == "tune_form" && (value == 0 || value == 1)) op->tune_form = value;
     else if (n == "break_at" && value >= 0) op->break_at = value;
     else if (n == "log_level" && value >= 0 && value <= 2) op->log_level = value;
@@ -530,6 +532,7 @@ lq_status lq_op_get_option(const lq_op *op, const char *name, int *value)
     else if (n == "rhs_per_thread_f32") *value = op->rhs_per_thread[F32];
     else if (n == "rhs_per_thread" || n == "rhs_per_thread_f16") *value = op->rhs_per_thread[F16];
     else if (n == "graphs") *value = op->use_graphs;
+    else if (n == "halo" || n == "halo_f16") *value = op->halo[F16];
     else if (n == "tune_form") *value = op->tune_form;
     else if (n == "break_at") *value = op->break_at;
     else if (n == "log_level") *value = op->log_level;

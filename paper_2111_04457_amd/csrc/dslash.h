@@ -80,6 +80,30 @@ static_assert(sizeof(HopBatch) <= 4096, "HopBatch exceeds the kernel argument sp
 hipError_t launch_hop_batch(const HopBatch &b, int prec, int recon, bool dag, int clov, bool xpay, int red,
                             hipStream_t s);
 
+// A tile of the hopping kernel with the neighbour spinors staged in LDS:
+// 256 threads, ty * tz * tt whole x-rows (lxh sites each) of the output
+// parity, lxh * ty a multiple of 64; ny * nz * nt tiles cover the lattice;
+// nrows rows staged (the tile's own and its six faces).
+struct HaloTile {
+    int ty, tz, tt;
+    int ny, nz, nt;
+    int nrows;
+    int sx, sy, sz;  // log2 of lxh, ty, tz (all powers of two: their product divides 256)
+};
+// The tile for geometry g, if one fits (lxh * ty * tz * tt == 256, lxh * ty a
+// multiple of 64, each extent dividing the lattice; the fewest staged rows).
+bool halo_tile(const Geom &g, HaloTile &t);
+// LDS bytes of the staged spinors of a tile in precision prec.
+inline size_t halo_lds_bytes(int prec, const HaloTile &t, int lxh)
+{
+    const size_t n = (size_t)t.nrows * lxh;
+    return n * (prec == F64 ? 192 : prec == F32 ? 96 : 52);
+}
+// The hopping term with staged neighbours (one right-hand side; arguments
+// and results as launch_hop).
+hipError_t launch_hop_halo(const HopArgs &a, const HaloTile &t, int prec, int recon, bool dag, int clov, bool xpay,
+                           int red, hipStream_t s);
+
 // Number of workgroups launch_hop uses for a lattice of vh sites.
 inline int hop_blocks(int vh, int block) { return (vh + block - 1) / block; }
 

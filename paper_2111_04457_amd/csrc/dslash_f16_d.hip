@@ -15,4 +15,10 @@ hipError_t launch_hop_batch_f16_d(const HopBatch &b, int recon, int clov, bool x
     return launch_pd_batch<F16, true>(b, recon, clov, xpay, red, s);
 }
 
+hipError_t launch_hop_halo_f16_d(const HopArgs &a, const HaloTile &t, int recon, int clov, bool xpay, int red,
+                              hipStream_t s)
+{
+    return launch_pd_halo<F16, true>(a, t, recon, clov, xpay, red, s);
+}
+
 }  // namespace lq

@@ -354,6 +354,228 @@ __global__ __launch_bounds__(64) void hop_batch_kernel(HopBatch b)
     hop_body<P, NL, DAG, CLOV, XPAY, RED, 64, 1>(b.a[i], t - b.tile_off[i]);
 }
 
+// ------------------------------------------------ neighbours staged in LDS --
+//
+// One workgroup of 256 threads per tile of whole x-rows of the output parity
+// (lxh sites each): ty x tz x tt rows, lxh * ty a multiple of 64, so that a
+// wavefront covers 64 consecutive sites (its partial sums are those of
+// hop_body).  Every input spinor the tile needs -- its own rows (the x
+// neighbours) and the six faces of rows around it (the y, z, t neighbours)
+// -- is read from memory once into LDS; the eight neighbour terms of each
+// site then read their spinors from LDS.  The operations are those of
+// hop_body in the same order, so the results are the same bits.
+
+// LDS slot of the staged row at offset (dy, dz, dt) from the tile's origin,
+// at most one of them outside the tile: the tile's rows, then the y, z and
+// t faces (the -1 face before the +T face).
+__device__ __forceinline__ int halo_slot(const HaloTile &h, int dy, int dz, int dt)
+{
+    const int I = h.ty * h.tz * h.tt;
+    if (dy < 0 || dy >= h.ty) return I + (dy < 0 ? 0 : h.tz * h.tt) + dz + h.tz * dt;
+    if (dz < 0 || dz >= h.tz) return I + 2 * h.tz * h.tt + (dz < 0 ? 0 : h.ty * h.tt) + dy + h.ty * dt;
+    if (dt < 0 || dt >= h.tt)
+        return I + 2 * h.tz * h.tt + 2 * h.ty * h.tt + (dt < 0 ? 0 : h.ty * h.tz) + dy + h.ty * dz;
+    return dy + h.ty * (dz + h.tz * dt);
+}
+
+// The offsets of slot s (the inverse of halo_slot); tile extents are powers
+// of two (shifts and masks).
+__device__ __forceinline__ void halo_offsets(const HaloTile &h, int s, int &dy, int &dz, int &dt)
+{
+    const int syz = h.sy + h.sz;
+    const int I = 1 << (syz + __builtin_ctz(h.tt));
+    if (s < I) {
+        dy = s & (h.ty - 1);
+        dz = (s >> h.sy) & (h.tz - 1);
+        dt = s >> syz;
+        return;
+    }
+    s -= I;
+    const int fy = h.tz * h.tt, fz = h.ty * h.tt, ft = h.ty * h.tz;
+    if (s < 2 * fy) {
+        dy = s < fy ? -1 : h.ty;
+        s &= fy - 1;
+        dz = s & (h.tz - 1);
+        dt = s >> h.sz;
+        return;
+    }
+    s -= 2 * fy;
+    if (s < 2 * fz) {
+        dz = s < fz ? -1 : h.tz;
+        s &= fz - 1;
+        dy = s & (h.ty - 1);
+        dt = s >> h.sy;
+        return;
+    }
+    s -= 2 * fz;
+    dt = s < ft ? -1 : h.tt;
+    s &= ft - 1;
+    dy = s & (h.ty - 1);
+    dz = s >> h.sy;
+}
+
+__device__ __forceinline__ int wrap_coord(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// Half K of a site whose neighbour spinor is in LDS at (slot, jn): the link
+// from memory (loaded before the staging), the term computed as in hop_body.
+template <int P, int NL, bool DAG, int K>
+__device__ __forceinline__ void halo_half(const HopArgs &a, const HaloTile &h, const char *smem, int nsites,
+                                          int slot, int jn, const typename PT<P>::S *link, bool wrap,
+                                          cx<typename PT<P>::R> (&acc)[1][12])
+{
+    using S = typename PT<P>::S;
+    constexpr int K16 = Planes<S, 24>::K16;
+    HalfRaw<P, NL, 1> hr;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) hr.link[i] = link[i];
+    const int e = slot * a.g.lxh + jn;
+    const u32x4 *lsp = reinterpret_cast<const u32x4 *>(smem);
+#pragma unroll
+    for (int k = 0; k < K16; ++k) {
+        const u32x4 q = lsp[(size_t)k * nsites + e];
+        __builtin_memcpy(hr.sp[0] + k * (16 / sizeof(S)), &q, 16);
+    }
+    if constexpr (PT<P>::scaled)
+        hr.scale[0] = reinterpret_cast<const float *>(smem + (size_t)K16 * 16 * nsites)[e];
+    hr.wrap = wrap;
+    consume<P, NL, DAG, 1, K>(a, hr, acc);
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+__global__ __launch_bounds__(256) void hop_halo_kernel(HopArgs a, HaloTile h)
+{
+    using S = typename PT<P>::S;
+    using R = typename PT<P>::R;
+    constexpr int CACHE = CachePolicy<P, CLOV>::value;
+    constexpr bool NTL = (CACHE & 1) != 0;
+    constexpr int K16 = Planes<S, 24>::K16;
+    static_assert(Planes<S, 24>::TAIL == 0, "spinor records are whole 16-byte planes");
+    extern __shared__ __align__(16) char smem[];
+    const int lxh = a.g.lxh;
+    const int nsites = h.nrows * lxh;
+    // a frozen system (the single right-hand side of a solver) exits at once
+    if (a.mask && (a.mask[a.mask_off0] != 0.0 || a.mask[a.mask_off1] != 0.0)) return;
+    int tile = blockIdx.x;
+    const int y0 = (tile % h.ny) * h.ty;
+    tile /= h.ny;
+    const int z0 = (tile % h.nz) * h.tz;
+    const int t0 = (tile / h.nz) * h.tt;
+    // this thread's output site: x-row position j, row (ry, rz, rt) of the tile
+    const int j = threadIdx.x & (lxh - 1);
+    const int r = threadIdx.x >> h.sx;
+    const int ry = r & (h.ty - 1);
+    const int rz = (r >> h.sy) & (h.tz - 1);
+    const int rt = r >> (h.sy + h.sz);
+    int c[4];
+    c[1] = y0 + ry;
+    c[2] = z0 + rz;
+    c[3] = t0 + rt;
+    const int px = (c[1] + c[2] + c[3] + a.p_out) & 1;
+    c[0] = 2 * j + px;
+    const int cb = j + lxh * (c[1] + a.g.L[1] * (c[2] + a.g.L[2] * c[3]));
+    // the eight links first (from memory, in flight while the spinors are staged)
+    S link[8][NL];
+    bool wrap[8];
+    {
+        int nb;
+        nb = half_neighbour<0>(a, c, wrap[0]);
+        load_half_link<P, NL, 0, NTL>(a, cb, nb, link[0]);
+        nb = half_neighbour<1>(a, c, wrap[1]);
+        load_half_link<P, NL, 1, NTL>(a, cb, nb, link[1]);
+        nb = half_neighbour<2>(a, c, wrap[2]);
+        load_half_link<P, NL, 2, NTL>(a, cb, nb, link[2]);
+        nb = half_neighbour<3>(a, c, wrap[3]);
+        load_half_link<P, NL, 3, NTL>(a, cb, nb, link[3]);
+        nb = half_neighbour<4>(a, c, wrap[4]);
+        load_half_link<P, NL, 4, NTL>(a, cb, nb, link[4]);
+        nb = half_neighbour<5>(a, c, wrap[5]);
+        load_half_link<P, NL, 5, NTL>(a, cb, nb, link[5]);
+        nb = half_neighbour<6>(a, c, wrap[6]);
+        load_half_link<P, NL, 6, NTL>(a, cb, nb, link[6]);
+        nb = half_neighbour<7>(a, c, wrap[7]);
+        load_half_link<P, NL, 7, NTL>(a, cb, nb, link[7]);
+    }
+    // stage the input spinors of the tile's rows and faces
+    {
+        u32x4 *lsp = reinterpret_cast<u32x4 *>(smem);
+        float *lsc = reinterpret_cast<float *>(smem + (size_t)K16 * 16 * nsites);
+        for (int e = threadIdx.x; e < nsites; e += 256) {
+            const int row = e >> h.sx, jj = e & (lxh - 1);
+            int dy, dz, dt;
+            halo_offsets(h, row, dy, dz, dt);
+            const int y = wrap_coord(y0 + dy, a.g.L[1]), z = wrap_coord(z0 + dz, a.g.L[2]),
+                      t = wrap_coord(t0 + dt, a.g.L[3]);
+            const long g = jj + (long)lxh * (y + a.g.L[1] * (z + (long)a.g.L[2] * t));
+            const char *blk = a.in + (size_t)(g >> 6) * (size_t)(Planes<S, 24>::BYTES * SB);
+            const uint32_t lane = (uint32_t)(g & 63);
+#pragma unroll
+            for (int k = 0; k < K16; ++k) lsp[(size_t)k * nsites + e] = ld<u32x4, false>(blk + k * 16 * SB + lane * 16u);
+            if constexpr (PT<P>::scaled)
+                lsc[e] = *reinterpret_cast<const float *>(a.in + 48 * (size_t)padded_sites(a.in_n) + (uint32_t)g * 4u);
+        }
+    }
+    __syncthreads();
+    cx<R> acc[1][12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[0][i] = cx<R>{0, 0};
+    const int own = halo_slot(h, ry, rz, rt);
+    // x: the same row, the neighbouring position (x + 1 -> (x + 1) / 2, x - 1 -> (x - 1) / 2)
+    halo_half<P, NL, DAG, 0>(a, h, smem, nsites, own, j + px == lxh ? 0 : j + px, link[0], wrap[0], acc);
+    halo_half<P, NL, DAG, 1>(a, h, smem, nsites, own, j - 1 + px < 0 ? lxh - 1 : j - 1 + px, link[1], wrap[1], acc);
+    halo_half<P, NL, DAG, 2>(a, h, smem, nsites, halo_slot(h, ry + 1, rz, rt), j, link[2], wrap[2], acc);
+    halo_half<P, NL, DAG, 3>(a, h, smem, nsites, halo_slot(h, ry - 1, rz, rt), j, link[3], wrap[3], acc);
+    halo_half<P, NL, DAG, 4>(a, h, smem, nsites, halo_slot(h, ry, rz + 1, rt), j, link[4], wrap[4], acc);
+    halo_half<P, NL, DAG, 5>(a, h, smem, nsites, halo_slot(h, ry, rz - 1, rt), j, link[5], wrap[5], acc);
+    halo_half<P, NL, DAG, 6>(a, h, smem, nsites, halo_slot(h, ry, rz, rt + 1), j, link[6], wrap[6], acc);
+    halo_half<P, NL, DAG, 7>(a, h, smem, nsites, halo_slot(h, ry, rz, rt - 1), j, link[7], wrap[7], acc);
+    S craw[CLOV ? 72 : 1];
+    if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
+    double red0[1] = {0.0}, red1[1] = {0.0}, red2[1] = {0.0};
+    epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, 0, 1, craw, acc, red0, red1, red2);
+    if constexpr (RED != 0) write_partials<RED, 1>(a, cb >> 6, 0, 1, red0, red1, red2);
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
+static hipError_t launch_halo1(const HopArgs &a, const HaloTile &h, hipStream_t s)
+{
+    const size_t lds = halo_lds_bytes(P, h, a.g.lxh);
+    hop_halo_kernel<P, NL, DAG, CLOV, XPAY, RED><<<dim3(h.ny * h.nz * h.nt), 256, lds, s>>>(a, h);
+    return hipGetLastError();
+}
+
+// The epilogue combinations of launch_epi for the staged kernel.
+template <int P, int NL, bool DAG>
+static hipError_t launch_epi_halo(const HopArgs &a, const HaloTile &h, int clov, bool xpay, int red, hipStream_t s)
+{
+    if (!xpay && red == 0) {
+        if (clov == 0) return launch_halo1<P, NL, DAG, 0, false, 0>(a, h, s);
+        if (clov == 2) return launch_halo1<P, NL, DAG, 2, false, 0>(a, h, s);
+    } else if (xpay) {
+        if (clov == 0 && red == 0) return launch_halo1<P, NL, DAG, 0, true, 0>(a, h, s);
+        if (clov == 0 && red == 2) return launch_halo1<P, NL, DAG, 0, true, 2>(a, h, s);
+        if (clov == 0 && red == 3) return launch_halo1<P, NL, DAG, 0, true, 3>(a, h, s);
+        if (clov == 1 && red == 0) return launch_halo1<P, NL, DAG, 1, true, 0>(a, h, s);
+        if (clov == 1 && red == 2) return launch_halo1<P, NL, DAG, 1, true, 2>(a, h, s);
+        if (clov == 1 && red == 3) return launch_halo1<P, NL, DAG, 1, true, 3>(a, h, s);
+        if (clov == 2 && red == 0) return launch_halo1<P, NL, DAG, 2, true, 0>(a, h, s);
+        if constexpr (!DAG) {
+            if (clov == 3 && red == 0) return launch_halo1<P, NL, DAG, 3, true, 0>(a, h, s);
+            if (clov == 3 && red == 2) return launch_halo1<P, NL, DAG, 3, true, 2>(a, h, s);
+            if (clov == 3 && red == 3) return launch_halo1<P, NL, DAG, 3, true, 3>(a, h, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, bool DAG>
+static hipError_t launch_pd_halo(const HopArgs &a, const HaloTile &h, int recon, int clov, bool xpay, int red,
+                                 hipStream_t s)
+{
+    if (recon == 18) return launch_epi_halo<P, 18, DAG>(a, h, clov, xpay, red, s);
+    if (recon == 12) return launch_epi_halo<P, 12, DAG>(a, h, clov, xpay, red, s);
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------- right-hand sides sharing LDS --
 //
 // Several right-hand sides per workgroup: 64 sites x R right-hand sides, one

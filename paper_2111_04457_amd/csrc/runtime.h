@@ -67,6 +67,7 @@ struct lq_op {
     int break_at = 0;                    // > 0: the next solve's first inner BiCGStab breaks down here
     int log_level = 0;                   // progress lines of solves on stderr (also $LQ_LOG_LEVEL)
     int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
+    int halo[3] = {0, 0, 0};             // 1: neighbour spinors staged in LDS (binary16, one rhs, if a tile fits)
     int inner_hint = 0;                  // iterations the last inner solve needed (first chunk length)
     lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
     lq::Buf links64r;                    // FP64 links with 12 reals (hop kernels) when link_recon == 12

@@ -100,13 +100,19 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     const Geom &g = op->g;
     HopArgs a = hop_args(op, prec, out, in, p_out, clov_mode, inv, y, coef, w);
     if (clov_mode && !op->has_clover) clov_mode = 0;
-    a.xcd_remap = op->xcd_remap[prec] != 0 ? 1 : 0;
-    if (op->hop_mask) {
-        a.mask = op->hop_mask;
-        a.mask_stride = MASK_STRIDE;
-        a.mask_off0 = MASK_DONE;
-        a.mask_off1 = MASK_BREAK;
+    if (op->hop_mask) set_hop_mask(a, op->hop_mask);
+    if (red) {
+        // one partial per 64-site wavefront and right-hand side, K <= 3
+        op->partial.ensure((size_t)((g.vh + 63) / 64) * in.nrhs * 3 * sizeof(double));
+        a.partial = reinterpret_cast<double *>(op->partial.ptr);
     }
+    // neighbour spinors staged in LDS (binary16, one right-hand side)
+    HaloTile tile;
+    if (op->halo[prec] && prec == F16 && in.nrhs == 1 && halo_tile(g, tile)) {
+        LQ_HIP(launch_hop_halo(a, tile, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, s));
+        return;
+    }
+    a.xcd_remap = op->xcd_remap[prec] != 0 ? 1 : 0;
     const int block = op->hop_block[prec];
     if (op->xcd_remap[prec] == 2) {
         const long slice = (long)g.L[0] * g.L[1] * g.L[2] / 2;  // sites of one parity per time slice
@@ -114,11 +120,6 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
             a.slice_tiles = (int)(slice / block);
             a.tgroup = std::max(1, g.L[3] / 8);  // one group of slices per XCD
         }
-    }
-    if (red) {
-        // one partial per 64-site wavefront and right-hand side, K <= 3
-        op->partial.ensure((size_t)((g.vh + 63) / 64) * in.nrhs * 3 * sizeof(double));
-        a.partial = reinterpret_cast<double *>(op->partial.ptr);
     }
     // right-hand sides per thread (2, no reductions), or 4 per workgroup
     // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)

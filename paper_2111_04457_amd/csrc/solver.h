@@ -167,7 +167,8 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
         const long k2[] = {(long)op->solver_ws.ptr, (long)op->solver_ws.bytes,
                            (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
                            (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
-                           (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1], (long)op->rhs_per_thread[2]};
+                           (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1], (long)op->rhs_per_thread[2],
+                           (long)op->halo[2]};
         key.insert(key.end(), k2, k2 + sizeof(k2) / sizeof(k2[0]));
     }
     std::vector<lq_op::GraphEntry> &graphs = bt ? bt->graphs : op->graphs;

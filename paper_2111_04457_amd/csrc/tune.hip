@@ -8,8 +8,10 @@
 // with the dot products the solver fuses into it (<w, out>, then <w, out>
 // and |out|^2).  Candidates: workgroup sizes {64, 128, 256} x the three
 // workgroup orders (plain, XCD-aware, XCD-aware with time slices
-// interleaved), and with several right-hand sides four per workgroup with
-// links and clover blocks staged in LDS (binary16 / FP32).  The output of
+// interleaved), with several right-hand sides four per workgroup with links
+// and clover blocks staged in LDS (binary16 / FP32), and with one
+// right-hand side in binary16 the kernel with the neighbour spinors of a
+// tile staged in LDS (when a tile fits the lattice).  The output of
 // every candidate must be bitwise equal to the first candidate's (each
 // site's sum is formed in the same order whatever the launch shape).  The
 // fastest candidate is kept on the operator, unless the shape the operator
@@ -45,9 +47,10 @@ std::string tune_key(const lq_op *op, int prec, int nrhs, bool left)
 
 struct Entry {
     std::string key;
-    int block = 256;
-    int xcd = 1;
-    int nr = 2;
+    int block = 64;
+    int xcd = 0;
+    int nr = 1;
+    int halo = 0;
     double us = 0;
 };
 
@@ -86,6 +89,7 @@ std::vector<Entry> read_cache(const std::string &path)
         e.block = (int)num("block", 256);
         e.xcd = (int)num("xcd_remap", 1);
         e.nr = (int)num("rhs_per_thread", 1);
+        e.halo = (int)num("halo", 0) != 0 ? 1 : 0;
         e.us = num("us", 0);
         if (e.block == 64 || e.block == 128 || e.block == 256) out.push_back(e);
         pos = cb + 1;
@@ -102,7 +106,7 @@ void write_cache(const std::string &path, const std::vector<Entry> &entries)
     for (size_t i = 0; i < entries.size(); ++i) {
         const Entry &e = entries[i];
         f << "  \"" << e.key << "\": {\"block\": " << e.block << ", \"xcd_remap\": " << e.xcd
-          << ", \"rhs_per_thread\": " << e.nr << ", \"us\": " << e.us
+          << ", \"rhs_per_thread\": " << e.nr << ", \"halo\": " << e.halo << ", \"us\": " << e.us
           << "}" << (i + 1 < entries.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -185,54 +189,67 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     LQ_HIP(launch_pack_spinor(g, 0, 1, reinterpret_cast<const double *>(op->tmp[5].ptr),
                                               FieldView{in.base + r * in.rs, prec, in.n, in.rs, 1}, s));
                 const int save_block = op->hop_block[prec], save_remap = op->xcd_remap[prec];
+                const int save_nr = op->rhs_per_thread[prec], save_halo = op->halo[prec];
                 double best_us = 1e30, default_us = 1e30;
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
-                const int save_nr = op->rhs_per_thread[prec];
-                // (two right-hand sides per thread are not swept: they cannot
-                // carry the fused reductions and need twice the registers)
-                std::vector<int> nrs = {1};
-                if (nrhs >= 4 && prec != F64) nrs.push_back(4);
                 const int def_nr = nrhs > 1 && (save_nr == 1 || save_nr == 4) ? save_nr : 1;
-                for (int nrt : nrs)
-                for (int block : {256, 128, 64}) {
-                    for (int remap : {2, 1, 0}) {
-                        // four right-hand sides per workgroup: 256 threads, plain or XCD order
-                        if (nrt == 4 && (block != 64 || remap == 2)) continue;
-                        op->hop_block[prec] = block;
-                        op->xcd_remap[prec] = remap;
-                        op->rhs_per_thread[prec] = nrt;
-                        for (int w = 0; w < 2; ++w) iteration();
-                        const int reps = g.vh >= (1 << 18) ? 10 : 40;
-                        std::vector<float> t(reps);
-                        for (int k = 0; k < reps; ++k) {
-                            LQ_HIP(hipEventRecord(e0, s));
-                            iteration();
-                            LQ_HIP(hipEventRecord(e1, s));
-                            LQ_HIP(hipEventSynchronize(e1));
-                            LQ_HIP(hipEventElapsedTime(&t[k], e0, e1));
-                        }
-                        std::sort(t.begin(), t.end());
-                        const double us = 1e3 * t[reps / 2];
-                        LQ_HIP(hipMemcpyAsync(cur_host.data(), out.base, b, hipMemcpyDeviceToHost, s));
-                        LQ_HIP(hipStreamSynchronize(s));
-                        if (first) {
-                            ref_host = cur_host;
-                            first = false;
-                        } else if (cur_host != ref_host) {
-                            op->hop_block[prec] = save_block;
-                            op->xcd_remap[prec] = save_remap;
-                            op->rhs_per_thread[prec] = save_nr;
-                            throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results"};
-                        }
-                        if (us < best_us) {
-                            best_us = us;
-                            best.block = block;
-                            best.xcd = remap;
-                            best.nr = nrt;
-                        }
-                        if (nrt == def_nr && block == save_block && remap == save_remap) default_us = us;
+                // candidates (right-hand sides per thread, workgroup size, order,
+                // LDS staging of the neighbours); two right-hand sides per thread
+                // are not swept: they cannot carry the fused reductions and need
+                // twice the registers
+                struct Cand {
+                    int nr, block, remap, halo;
+                };
+                std::vector<Cand> cands;
+                for (int block : {256, 128, 64})
+                    for (int remap : {2, 1, 0}) cands.push_back({1, block, remap, 0});
+                // four right-hand sides per workgroup (links in LDS): 256 threads, plain or XCD order
+                if (nrhs >= 4 && prec != F64)
+                    for (int remap : {1, 0}) cands.push_back({4, 64, remap, 0});
+                HaloTile tile;
+                if (prec == F16 && nrhs == 1 && halo_tile(g, tile)) cands.push_back({1, 64, 0, 1});
+                auto restore = [&]() {
+                    op->hop_block[prec] = save_block;
+                    op->xcd_remap[prec] = save_remap;
+                    op->rhs_per_thread[prec] = save_nr;
+                    op->halo[prec] = save_halo;
+                };
+                for (const Cand &cd : cands) {
+                    op->hop_block[prec] = cd.block;
+                    op->xcd_remap[prec] = cd.remap;
+                    op->rhs_per_thread[prec] = cd.nr;
+                    op->halo[prec] = cd.halo;
+                    for (int w = 0; w < 2; ++w) iteration();
+                    const int reps = g.vh >= (1 << 18) ? 10 : 40;
+                    std::vector<float> t(reps);
+                    for (int k = 0; k < reps; ++k) {
+                        LQ_HIP(hipEventRecord(e0, s));
+                        iteration();
+                        LQ_HIP(hipEventRecord(e1, s));
+                        LQ_HIP(hipEventSynchronize(e1));
+                        LQ_HIP(hipEventElapsedTime(&t[k], e0, e1));
                     }
+                    std::sort(t.begin(), t.end());
+                    const double us = 1e3 * t[reps / 2];
+                    LQ_HIP(hipMemcpyAsync(cur_host.data(), out.base, b, hipMemcpyDeviceToHost, s));
+                    LQ_HIP(hipStreamSynchronize(s));
+                    if (first) {
+                        ref_host = cur_host;
+                        first = false;
+                    } else if (cur_host != ref_host) {
+                        restore();
+                        throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results"};
+                    }
+                    if (us < best_us) {
+                        best_us = us;
+                        best.block = cd.block;
+                        best.xcd = cd.remap;
+                        best.nr = cd.nr;
+                        best.halo = cd.halo;
+                    }
+                    if (cd.nr == def_nr && cd.block == save_block && cd.remap == save_remap && cd.halo == save_halo)
+                        default_us = us;
                 }
                 // the shape the operator had unless another is faster by more
                 // than 2 %: closer times are within run-to-run noise
@@ -241,6 +258,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     best.block = save_block;
                     best.xcd = save_remap;
                     best.nr = def_nr;
+                    best.halo = save_halo;
                 }
                 best.us = best_us;
                 cache.push_back(best);
@@ -248,9 +266,10 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             }
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
+            op->halo[prec] = best.halo;
             if (nrhs > 1 && (best.nr == 1 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
-                << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec]
+                << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec] << ", \"halo\": " << op->halo[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";
         }
         LQ_HIP(hipEventDestroy(e0));
