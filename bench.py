@@ -47,7 +47,7 @@ def _kernel_source_hash():
 def _traffic_from_profile(kernel_tag: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_schur_f16_32x32x32x64.txt")
+    path = os.path.join(ROOT, "profiles", "schur_f16_32x32x32x64.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -350,6 +350,79 @@ def _eigs(lq, torch):
     return out
 
 
+def _profile(lq, torch, args):
+    """One workload alone (for rocprofv3 runs; see --profile)."""
+    from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_spinor, point_sources,
+                                workload_gauge, workload_source)
+    out = {}
+    if args.profile in ("schur_f16", "schur12_f16", "solve"):
+        name = args.workload if args.profile != "schur12_f16" else "clover_24x24x24x48"
+        w = WORKLOADS[name]
+        d = w["dims"]
+        op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=args.recon)
+        op.set_gauge(torch.from_numpy(workload_gauge(name)).cuda())
+        V = d[0] * d[1] * d[2] * d[3]
+        if args.profile == "solve":
+            b = torch.from_numpy(workload_source(name)).cuda()
+            inner_tol = args.inner_tol or {"f16": 5e-3, "f32": 1e-5, "f64": 1e-5}[args.inner]
+            prm = lq.SolverParams(solver=args.solver, tol=args.tol, inner=args.inner, inner_tol=inner_tol,
+                                  check_every=10, left_precond=args.left_precond)
+            for _ in range(args.warmup):
+                op.solve(b, "D", prm)
+            times = []
+            for _ in range(args.steps):
+                (_, st), ms = _timed(torch, lambda: op.solve(b, "D", prm))
+                times.append(ms)
+            out = {"workload": name, "solve_ms": times, "iters": st[0].nconv, "outer": st[0].nouter,
+                   "diff": st[0].diff}
+        else:
+            nrhs = 1 if args.profile == "schur_f16" else 12
+            fin, fout = lq.Field(op, "f16", nrhs), lq.Field(op, "f16", nrhs)
+            src = torch.from_numpy(workload_source(name, nrhs=nrhs if nrhs > 1 else None)).cuda()
+            fin.load(src.reshape(nrhs, -1, 4, 3)[:, : V // 2].contiguous().reshape((nrhs,) + op.parity_shape))
+            op.tune(nrhs, left=args.left_precond)
+            kind = "schur_left" if args.left_precond else "schur"
+            us = _graph_time_us(torch, lambda: lq.apply_field(op, kind, fout, fin), args.kernel_reps)
+            b2, _ = op.traffic("f16", nrhs, clover=True)
+            bps = 2 * b2 + 52.0  # per site and right-hand side: kernel 1 + kernel 2 (+ the axpy operand)
+            out = {"workload": name, "nrhs": nrhs, "kind": kind, "avg_apply_us": us,
+                   "bytes_per_apply": bps * nrhs * (V // 2),
+                   "GBs": bps * nrhs * (V // 2) / (us * 1e-6) / 1e9,
+                   "block": op.get_option("hop_block_f16"), "xcd_remap": op.get_option("xcd_remap_f16"),
+                   "rhs_per_thread": op.get_option("rhs_per_thread_f16")}
+            fin.close()
+            fout.close()
+            # a copy of known size in the same run (1 GiB read + 1 GiB written per
+            # launch, 3 launches): the reference for scaling hardware counters
+            out["copy_probe_GBs"] = lq.bandwidth_probe(1 << 30, "copy", reps=2)
+        op.close()
+    else:
+        prm = lq.SolverParams(tol=1e-10, inner=args.inner, inner_tol=args.inner_tol or
+                              {"f16": 5e-3, "f32": 1e-5, "f64": 1e-5}[args.inner], check_every=10,
+                              left_precond=args.left_precond)
+        ops, bs = [], []
+        for i, dd in enumerate(RAGGED_DIMS):
+            o = lq.Operator(dd, 0.135, 1.7, ANTIPERIODIC_T, link_recon=12)
+            o.set_gauge(torch.from_numpy(workload_gauge("clover_24x24x24x48", dims=dd)).cuda())
+            ops.append(o)
+            bs.append(torch.from_numpy(gaussian_spinor(dd, 2003 + 10 * i, 4)).cuda())
+        batch = lq.Batch(ops, [4] * len(ops))
+        batch.solve(bs, prm)
+        for o, b in zip(ops, bs):
+            o.solve(b, "D", prm)
+        for _ in range(args.steps):
+            (_, stb), msb = _timed(torch, lambda: batch.solve(bs, prm))
+            out.setdefault("batch_ms", []).append(msb)
+            for k, (o, b) in enumerate(zip(ops, bs)):
+                (_, st), m = _timed(torch, lambda: o.solve(b, "D", prm))
+                out.setdefault("separate_ms_%dx%dx%dx%d" % tuple(RAGGED_DIMS[k]), []).append(m)
+        out["batch_iters"] = [s.nconv for s in stb]
+        batch.close()
+        for o in ops:
+            o.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,6 +450,11 @@ def main(argv=None):
                     help="only the eigensolver measurement; prints its JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
+    ap.add_argument("--profile", choices=["schur_f16", "schur12_f16", "solve", "ragged"], default=None,
+                    help="run one workload alone for a profiler: schur_f16 the roofline kernel pair on the "
+                         "workload (kernel-reps graph-replayed applies), schur12_f16 the same operator with the "
+                         "12 point sources of 24^3x48, solve the timed mixed solve (warmup + steps solves), ragged "
+                         "the ragged batch solve and its lattices' separate solves; prints its timings as JSON")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -394,6 +472,10 @@ def main(argv=None):
     if not os.path.exists(hip_build.LIB):
         hip_build.build()
 
+    if args.profile:
+        torch.cuda.set_device(0)
+        print(json.dumps({"profile": _profile(lq, torch, args)}), flush=True)
+        return 0
     if args.force_only:
         torch.cuda.set_device(0)
         print(json.dumps({"forces": _forces(lq, torch)}), flush=True)

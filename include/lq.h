@@ -123,6 +123,12 @@ typedef struct {
     int link_recon;       /* 18 or 12: reals per link read by the hopping kernels (all
                              precisions; 12 stores rows 0 and 1 and rebuilds row 2 as
                              conj(row0 x row1), valid for SU(3) links only) */
+    double twist;         /* twisted-mass Wilson operator D = 1 - kappa H + i twist gamma_5
+                             (twist = 2 kappa mu for a twisted mass mu); 0 (default): none.
+                             Finite; not with the clover term (csw must be 0).  Twisted
+                             operators solve the modes LQ_D only (D^dag of a twisted
+                             operator is gamma_5 D(-twist) gamma_5), and have no force or
+                             molecular-dynamics calls */
 } lq_op_params;
 
 /* Solver parameters (params_solver of Fig. 1). */

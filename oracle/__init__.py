@@ -231,20 +231,34 @@ def from_parity(dims, half, p, out=None) -> np.ndarray:
     return out.reshape(tuple(int(v) for v in dims[::-1]) + (4, 3))
 
 
+def twist_term(V, twist) -> np.ndarray:
+    """i tau gamma_5 (x) 1_colour at every site, [V, 12, 12]: the twisted-mass
+    term of the Wilson operator D = 1 - kappa H + i tau gamma_5 (tau = 2 kappa mu
+    for a twisted mass mu in the normalisation of eq. (1))."""
+    g5 = np.kron(np.diag([1.0, 1.0, -1.0, -1.0]), np.eye(3)).astype(np.complex128)
+    return np.broadcast_to(1j * float(twist) * g5, (V, 12, 12)).copy()
+
+
 class Operator:
     """The fermion matrix D = A - kappa H with A = 1 + F on one gauge field,
-    and its even-odd blocks D = [[A_ee, -kappa H_eo], [-kappa H_oe, A_oo]]."""
+    and its even-odd blocks D = [[A_ee, -kappa H_eo], [-kappa H_oe, A_oo]].
+    With twist != 0, F also holds the twisted-mass term i twist gamma_5
+    (A is then not Hermitian)."""
 
-    def __init__(self, dims, U, kappa, csw=0.0, bc=None, traceless=True):
+    def __init__(self, dims, U, kappa, csw=0.0, bc=None, traceless=True, twist=0.0):
         self.dims = tuple(int(v) for v in dims)
         self.V = volume(dims)
         self.U = _c128(U)
         self.kappa = float(kappa)
         self.csw = float(csw)
+        self.twist = float(twist)
         self.bc = _bc(bc)
         self.shape = tuple(self.dims[::-1]) + (4, 3)
-        if self.csw != 0.0:
-            self.F = clover(self.dims, self.U, self.csw, self.kappa, traceless)
+        F = clover(self.dims, self.U, self.csw, self.kappa, traceless) if self.csw != 0.0 else None
+        if self.twist != 0.0:
+            F = twist_term(self.V, self.twist) if F is None else F + twist_term(self.V, self.twist)
+        if F is not None:
+            self.F = F
             A = self.F + np.eye(12)[None]
             self.A = A
             self.Ainv, nsing = site_invert(A)
@@ -275,10 +289,12 @@ class Operator:
         full = from_parity(self.dims, v_in, 1 - p_out)
         return to_parity(self.dims, hop(self.dims, self.U, self.bc, full, dagger), p_out)
 
-    def clover_apply(self, p, v, inverse=False):
+    def clover_apply(self, p, v, inverse=False, dagger=False):
         if self.A is None:
             return v.copy()
         M = (self.Ainv if inverse else self.A)[self.sites[p]]
+        if dagger:
+            M = np.ascontiguousarray(np.conj(np.swapaxes(M, 1, 2)))
         return site_apply(M, v).reshape(v.shape)
 
     def schur(self, xe):
@@ -287,9 +303,9 @@ class Operator:
         return self.clover_apply(0, xe) - self.kappa ** 2 * self.hop_to(0, t)
 
     def schur_dag(self, xe):
-        """M^dag = A_ee - kappa^2 (H_oe)^dag A_oo^-1 (H_eo)^dag  (A Hermitian)."""
-        t = self.clover_apply(1, self.hop_to(1, xe, dagger=True), inverse=True)
-        return self.clover_apply(0, xe) - self.kappa ** 2 * self.hop_to(0, t, dagger=True)
+        """M^dag = A_ee^dag - kappa^2 (H_oe)^dag (A_oo^-1)^dag (H_eo)^dag."""
+        t = self.clover_apply(1, self.hop_to(1, xe, dagger=True), inverse=True, dagger=True)
+        return self.clover_apply(0, xe, dagger=True) - self.kappa ** 2 * self.hop_to(0, t, dagger=True)
 
     def schur_normal(self, xe):
         return self.schur_dag(self.schur(xe))

@@ -90,10 +90,11 @@ def clover_site(U, dims, c, csw, kappa, traceless=True):
     return F
 
 
-def dense_dirac(dims, U, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True):
-    """The N x N matrix D of eq. (1); blocks are kron(spin 4x4, colour 3x3)."""
+def dense_dirac(dims, U, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True, twist=0.0):
+    """The N x N matrix D of eq. (1); blocks are kron(spin 4x4, colour 3x3).
+    twist != 0 adds the twisted-mass term i twist gamma_5 on every site."""
     dims = tuple(int(v) for v in dims)
-    g, _ = chiral_gammas()
+    g, g5 = chiral_gammas()
     V = int(np.prod(dims))
     N = 12 * V
     D = np.zeros((N, N), dtype=complex)
@@ -102,6 +103,8 @@ def dense_dirac(dims, U, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True):
         i = _lex(dims, c)
         bi = slice(12 * i, 12 * i + 12)
         D[bi, bi] += np.eye(12)
+        if twist != 0.0:
+            D[bi, bi] += 1j * twist * np.kron(g5, np.eye(3))
         if csw != 0.0:
             D[bi, bi] += clover_site(U, dims, c, csw, kappa, traceless)
         for mu in range(4):

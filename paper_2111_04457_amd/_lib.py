@@ -28,7 +28,8 @@ CGNE, BICGSTAB = 0, 1
 
 class OpParams(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("kappa", ctypes.c_double), ("csw", ctypes.c_double),
-                ("bc", (ctypes.c_double * 2) * 4), ("clover_traceless", ctypes.c_int), ("link_recon", ctypes.c_int)]
+                ("bc", (ctypes.c_double * 2) * 4), ("clover_traceless", ctypes.c_int), ("link_recon", ctypes.c_int),
+                ("twist", ctypes.c_double)]
 
 
 class SolverParams(ctypes.Structure):

@@ -41,7 +41,7 @@ def _dev(t: torch.Tensor, shape, name, host_ok: bool = False):
     return t.contiguous()
 
 
-def _op_params(dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18) -> _lib.OpParams:
+def _op_params(dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18, twist=0.0) -> _lib.OpParams:
     p = _lib.OpParams()
     load().lq_op_params_default(ctypes.byref(p))
     for i in range(4):
@@ -51,6 +51,7 @@ def _op_params(dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18) -> 
     p.bc = _bc_array(bc)
     p.clover_traceless = int(bool(traceless))
     p.link_recon = int(link_recon)
+    p.twist = float(twist)
     return p
 
 
@@ -107,9 +108,9 @@ class Operator:
     """The fermion matrix of eq. (1) on one gauge field (params_fopr +
     set_config of Fig. 1)."""
 
-    def __init__(self, dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18):
+    def __init__(self, dims, kappa, csw=0.0, bc=None, traceless=True, link_recon=18, twist=0.0):
         lib = load()
-        p = _op_params(dims, kappa, csw, bc, traceless, link_recon)
+        p = _op_params(dims, kappa, csw, bc, traceless, link_recon, twist)
         h = ctypes.c_void_p()
         check(lib.lq_op_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h

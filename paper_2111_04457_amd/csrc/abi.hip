@@ -125,6 +125,9 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
         if (!(std::fabs(m - 1.0) < 1e-12)) return arg_error("lq_op_create: boundary phases must have modulus 1");
     }
     if (p->link_recon != 18 && p->link_recon != 12) return arg_error("lq_op_create: link_recon must be 12 or 18");
+    if (!std::isfinite(p->twist)) return arg_error("lq_op_create: twist must be finite");
+    if (p->twist != 0.0 && p->csw != 0.0)
+        return arg_error("lq_op_create: the twisted-mass operator is provided without the clover term (csw = 0)");
     return guarded([&]() -> lq_status {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
@@ -145,6 +148,7 @@ lq_status lq_op_create(const lq_op_params *p, lq_op **out)
         op->device = dev;
         op->g = make_geom(*p);
         op->has_clover = p->csw != 0.0;
+        op->has_twist = p->twist != 0.0;
         try {
             // device memory comes later: a bound workspace, or allocations on
             // first use (lq_op_set_gauge)
@@ -261,6 +265,8 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
         for (int i = 0; i < 4; ++i)
             if (!(std::fabs(std::hypot(bc[i][0], bc[i][1]) - 1.0) < 1e-12))
                 return arg_error("lq_op_set_params: boundary phases must have modulus 1");
+    if (op->has_twist && csw != 0.0)
+        return arg_error("lq_op_set_params: the twisted-mass operator is provided without the clover term (csw = 0)");
     if (op->bound_nrhs && csw != 0.0 && op->clov[F64].bytes < 2 * (size_t)clover_bytes(F64, op->g.vh)) {
         set_error("lq_op_set_params: the bound workspace has no room for clover blocks (it was laid out with "
                   "csw = 0): bind one of lq_op_workspace_bytes bytes after setting csw");

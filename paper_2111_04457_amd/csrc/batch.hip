@@ -124,7 +124,7 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
     lq_batch *bt = c.bt;
     if (left && dag) throw Failure{LQ_ERR_STATE, "the preconditioned Schur operator has no dagger form here"};
     const int n = (int)bt->ops.size();
-    const bool clover = bt->ops[0]->has_clover;
+    const bool clover = bt->ops[0]->has_clover || bt->ops[0]->has_twist;  // a site-local factor
     const int K = red == 2 ? 2 : 3;
     for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
         HopBatch k1{}, k2{};
@@ -139,8 +139,8 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
             const double k = o->prm.kappa;
             // t_o = A_oo^-1 H_oe x_e, then y_e = A_ee x_e - kappa^2 H_eo t_o
             // (left: x_e - kappa^2 A_ee^-1 H_eo t_o), as the operator's schur()
-            HopArgs a1 = hop_args(o, prec, odd_g, in_g, 1, 2, true, nullptr, 1.0, nullptr);
-            HopArgs a2 = hop_args(o, prec, out_g, odd_g, 0, left ? 3 : 1, left, &in_g, -k * k, w ? &w_g : nullptr);
+            HopArgs a1 = hop_args(o, prec, odd_g, in_g, 1, 2, true, dag, nullptr, 1.0, nullptr);
+            HopArgs a2 = hop_args(o, prec, out_g, odd_g, 0, left ? 3 : 1, left, dag, &in_g, -k * k, w ? &w_g : nullptr);
             if (c.masked) {
                 set_hop_mask(a1, c.sc + (long)bt->sys0[g] * NSC);
                 set_hop_mask(a2, c.sc + (long)bt->sys0[g] * NSC);
@@ -329,8 +329,9 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
             set_error("lq_batch_solve: gauge field not set");
             return LQ_ERR_STATE;
         }
-        if (o->has_clover != bt->ops[0]->has_clover) {
-            set_error("lq_batch_solve: the operators of a batch must all be clover or all Wilson");
+        if (o->has_clover != bt->ops[0]->has_clover || o->has_twist != bt->ops[0]->has_twist) {
+            set_error("lq_batch_solve: the operators of a batch must be of one kind (all clover, all twisted-mass or "
+                      "all Wilson)");
             return LQ_ERR_ARG;
         }
         if (o->bound_nrhs && bt->nrhs[i] > o->bound_nrhs) {

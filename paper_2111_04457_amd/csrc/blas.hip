@@ -398,7 +398,7 @@ __global__ __launch_bounds__(BT) void cg_xr_kernel(FieldView x, FieldView r, Fie
             }
             store_spinor<PX>(at(x, L), i, L.n, xv);
             store_spinor<P>(at(r, L), i, L.n, rv);
-            if constexpr (PT<P>::scaled) rv = load_spinor<P>(at(r, L), i, L.n);
+            rv = as_stored<P>(rv);  // the values as stored (binary16: rounded and scaled), not re-read
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) a += (double)norm2(rv.c[k]);
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(BT) void bicg_xr_kernel(FieldView x, FieldView r, F
             }
             store_spinor<PX>(at(x, L), i, L.n, xv);
             store_spinor<P>(at(r, L), i, L.n, rv);
-            if constexpr (PT<P>::scaled) rv = load_spinor<P>(at(r, L), i, L.n);
+            rv = as_stored<P>(rv);  // the values as stored (binary16: rounded and scaled), not re-read
             const Spinor<R> hv = load_spinor<P>(at(rhat, L), i, L.n);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {

@@ -19,7 +19,8 @@ namespace lq {
 //   CLOV == 3: res = C res (before the axpy)
 //   XPAY:      res = (CLOV == 1 ? C y : y) + res
 //   CLOV == 2: res = C res
-// where C is the packed clover block field of the output parity (A or A^-1).
+// where C is the packed clover block field of the output parity (A or A^-1),
+// or (clov null) the twisted-mass diagonal A = 1 + i tau gamma_5 or its inverse.
 struct HopArgs {
     Geom g;
     int p_out;           // output parity
@@ -34,7 +35,8 @@ struct HopArgs {
     long y_n;
     long y_rs;
     const char *links;   // packed links [parity][mu] (vh sites each)
-    const char *clov;    // packed clover blocks of the output parity (vh sites)
+    const char *clov;    // packed clover blocks of the output parity (vh sites), or null: then
+    double tw_re, tw_im; // the twisted-mass factor on spins 0, 1 (its conjugate on spins 2, 3)
     double coef;
     double *partial;     // per-wavefront partial sums (reduction epilogue) or null
     const char *w;       // second operand of a fused dot product, or null

@@ -210,6 +210,25 @@ template <int P, int CLOV> struct CachePolicy {
     static constexpr int value = (P == F16 && CLOV == 0) ? 2 : 3;
 };
 
+// The site-local factor C of the epilogue: a clover block (A or A^-1, two
+// 6x6 Hermitian blocks, already loaded into craw), or, for the twisted-mass
+// Wilson operator (no clover block), the scalar tw on spins 0, 1 and its
+// conjugate on spins 2, 3 (A = 1 + i tau gamma_5 or its inverse, conjugated
+// for the dagger).
+template <typename S, typename R>
+__device__ __forceinline__ void diag_mul(const HopArgs &a, const S *__restrict__ craw, Spinor<R> &v)
+{
+    if (a.clov) {
+        clover_mul_raw(craw, v);
+    } else {
+        const cx<R> c = cx<R>{(R)a.tw_re, (R)a.tw_im};
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v.c[i] = c * v.c[i];
+#pragma unroll
+        for (int i = 6; i < 12; ++i) v.c[i] = conj(c) * v.c[i];
+    }
+}
+
 // The epilogue of one site: res = coef * acc, then the axpy / clover terms,
 // the store, and the fused dot products of the values as stored.
 template <int P, int CLOV, bool XPAY, int RED, int NR, int CACHE>
@@ -227,14 +246,14 @@ __device__ __forceinline__ void epilogue(const HopArgs &a, int cb, int rhs0, int
             Spinor<R> res;
 #pragma unroll
             for (int i = 0; i < 12; ++i) res.c[i] = unit ? acc[r][i] : coef * acc[r][i];
-            if constexpr (CLOV == 3) clover_mul_raw(craw, res);
+            if constexpr (CLOV == 3) diag_mul(a, craw, res);
             if constexpr (XPAY) {
                 Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
-                if constexpr (CLOV == 1) clover_mul_raw(craw, yv);
+                if constexpr (CLOV == 1) diag_mul(a, craw, yv);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
             }
-            if constexpr (CLOV == 2) clover_mul_raw(craw, res);
+            if constexpr (CLOV == 2) diag_mul(a, craw, res);
             store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
             if constexpr (RED != 0) {
                 // <w, out> (and |out|^2) of the values as stored
@@ -327,7 +346,9 @@ __device__ __forceinline__ void hop_body(const HopArgs &a, const int id)
         prologue<P, NL, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot);
         pipeline<P, NL, DAG, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot, acc);
         S craw[CLOV ? 72 : 1];
-        if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
+        if constexpr (CLOV != 0) {
+            if (a.clov) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
+        }
         epilogue<P, CLOV, XPAY, RED, NR, CACHE>(a, cb, rhs0, nr, craw, acc, red0, red1, red2);
     }
     if constexpr (RED != 0) {
@@ -529,7 +550,9 @@ __global__ __launch_bounds__(256) void hop_halo_kernel(HopArgs a, HaloTile h)
     halo_half<P, NL, DAG, 6>(a, h, smem, nsites, halo_slot(h, ry, rz, rt + 1), j, link[6], wrap[6], acc);
     halo_half<P, NL, DAG, 7>(a, h, smem, nsites, halo_slot(h, ry, rz, rt - 1), j, link[7], wrap[7], acc);
     S craw[CLOV ? 72 : 1];
-    if constexpr (CLOV != 0) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
+    if constexpr (CLOV != 0) {
+            if (a.clov) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
+        }
     double red0[1] = {0.0}, red1[1] = {0.0}, red2[1] = {0.0};
     epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, 0, 1, craw, acc, red0, red1, red2);
     if constexpr (RED != 0) write_partials<RED, 1>(a, cb >> 6, 0, 1, red0, red1, red2);
@@ -668,7 +691,7 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
     if (site_ok) {
         stage_links<P, NL, 0, R, (CACHE & 1) != 0>(a, w, lane, cb, c, lk);
         if constexpr (CLOV != 0) {
-            if (w == R - 1) {
+            if (w == R - 1 && a.clov) {
                 S raw[72];
                 load_planes<S, 72>(a.clov, cb, a.g.vh, raw);
 #pragma unroll
@@ -685,8 +708,10 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
         pipeline_sp<P, NL, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
         S craw[CLOV ? 72 : 1];
         if constexpr (CLOV != 0) {
+            if (a.clov) {
 #pragma unroll
-            for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
+                for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
+            }
         }
         epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, rhs, 1, craw, acc, red0, red1, red2);
     }

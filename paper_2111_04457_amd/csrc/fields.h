@@ -61,6 +61,9 @@ hipError_t launch_convert_clover(const Geom &g, const char *clov64, int prec, ch
                                  int np = 2);
 // Site-local y = C x on one parity with packed clover C of that parity.
 hipError_t launch_clover_apply(const Geom &g, const char *clov, FieldView out, FieldView in, hipStream_t s);
+// Site-local y = (c on spins 0, 1, conj(c) on spins 2, 3) x: the twisted-mass
+// diagonal 1 + i tau gamma_5 or its inverse.
+hipError_t launch_twist_apply(const Geom &g, double c_re, double c_im, FieldView out, FieldView in, hipStream_t s);
 
 __host__ __device__ inline long link_bytes(int prec, int nl, long vh)
 {

@@ -434,6 +434,34 @@ __global__ __launch_bounds__(256) void clover_apply_kernel(Geom g, const char *c
     store_spinor<P>(out.base + rhs * out.rs, cb, out.n, v);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void twist_apply_kernel(Geom g, double c_re, double c_im, FieldView out, FieldView in)
+{
+    using R = typename PT<P>::R;
+    const int cb = blockIdx.x * 256 + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (cb >= g.vh) return;
+    Spinor<R> v = load_spinor<P>(in.base + rhs * in.rs, cb, in.n);
+    const cx<R> c = cx<R>{(R)c_re, (R)c_im};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v.c[i] = c * v.c[i];
+#pragma unroll
+    for (int i = 6; i < 12; ++i) v.c[i] = conj(c) * v.c[i];
+    store_spinor<P>(out.base + rhs * out.rs, cb, out.n, v);
+}
+
+hipError_t launch_twist_apply(const Geom &g, double c_re, double c_im, FieldView out, FieldView in, hipStream_t s)
+{
+    const dim3 grid((g.vh + 255) / 256, in.nrhs);
+    switch (in.prec) {
+    case F64: twist_apply_kernel<F64><<<grid, 256, 0, s>>>(g, c_re, c_im, out, in); break;
+    case F32: twist_apply_kernel<F32><<<grid, 256, 0, s>>>(g, c_re, c_im, out, in); break;
+    case F16: twist_apply_kernel<F16><<<grid, 256, 0, s>>>(g, c_re, c_im, out, in); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_clover_build(const Geom &g, const char *links64, double csw, double kappa, int traceless,
                                char *fbuf, char *clov64, hipStream_t s)
 {

@@ -400,6 +400,10 @@ lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_
         set_error("lq_pf_force: invalid solver parameters: " + why);
         return LQ_ERR_ARG;
     }
+    if (op->has_twist) {
+        set_error("lq_pf_force: the force of a twisted-mass operator is not provided");
+        return LQ_ERR_ARG;
+    }
     if (!op->gauge_set) {
         set_error("lq_pf_force: gauge field not set");
         return LQ_ERR_STATE;

@@ -58,6 +58,7 @@ struct lq_op {
     int device = 0;
     bool gauge_set = false;
     bool has_clover = false;
+    bool has_twist = false;              // twisted-mass Wilson operator (prm.twist != 0, no clover)
     bool even_inverted = false;          // A_ee^-1 computed for the current gauge field
     int hop_block[3] = {64, 64, 64};     // workgroup size of the hop kernel per precision
     // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
@@ -182,7 +183,10 @@ inline FieldView full_parity_view(char *base, int prec, const Geom &g, int nrhs,
 // on op's links and clover blocks (default launch shape, no mask, no
 // reduction partials).
 HopArgs hop_args(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, int clov_mode, bool inv,
-                 const FieldView *y, double coef, const FieldView *w);
+                 bool dag, const FieldView *y, double coef, const FieldView *w);
+// The twisted-mass factor on spins 0, 1 of A = 1 + i tau gamma_5 (inv: of A^-1;
+// dag: conjugated); spins 2, 3 take its conjugate.
+void twist_factor(const lq_op *op, bool inv, bool dag, double &re, double &im);
 // Freeze mask of the hopping kernel: the solver scalars sc of its right-hand sides.
 void set_hop_mask(HopArgs &a, const double *sc);
 

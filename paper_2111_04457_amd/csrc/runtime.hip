@@ -62,8 +62,23 @@ int log_level(const lq_op *op)
     return std::max(env, op ? op->log_level : 0);
 }
 
+void twist_factor(const lq_op *op, bool inv, bool dag, double &re, double &im)
+{
+    // A = 1 + i tau gamma_5 on spins 0, 1: 1 + i tau; A^-1: (1 - i tau) / (1 + tau^2);
+    // the dagger conjugates
+    const double t = op->prm.twist;
+    if (inv) {
+        re = 1.0 / (1.0 + t * t);
+        im = -t / (1.0 + t * t);
+    } else {
+        re = 1.0;
+        im = t;
+    }
+    if (dag) im = -im;
+}
+
 HopArgs hop_args(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_out, int clov_mode, bool inv,
-                 const FieldView *y, double coef, const FieldView *w)
+                 bool dag, const FieldView *y, double coef, const FieldView *w)
 {
     const Geom &g = op->g;
     HopArgs a{};
@@ -89,6 +104,8 @@ HopArgs hop_args(lq_op *op, int prec, const FieldView &out, const FieldView &in,
     a.links = op->hop_links(prec);
     if (clov_mode && op->has_clover)
         a.clov = (inv ? op->clovinv[prec].ptr : op->clov[prec].ptr) + (long)p_out * clover_bytes(prec, g.vh);
+    else if (clov_mode && op->has_twist)
+        twist_factor(op, inv, dag, a.tw_re, a.tw_im);
     a.coef = coef;
     return a;
 }
@@ -98,8 +115,8 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
 {
     if (out.tiles || in.tiles) throw Failure{LQ_ERR_STATE, "hop: a ragged field needs the batched hopping kernel"};
     const Geom &g = op->g;
-    HopArgs a = hop_args(op, prec, out, in, p_out, clov_mode, inv, y, coef, w);
-    if (clov_mode && !op->has_clover) clov_mode = 0;
+    HopArgs a = hop_args(op, prec, out, in, p_out, clov_mode, inv, dag, y, coef, w);
+    if (clov_mode && !op->has_clover && !op->has_twist) clov_mode = 0;
     if (op->hop_mask) set_hop_mask(a, op->hop_mask);
     if (red) {
         // one partial per 64-site wavefront and right-hand side, K <= 3
@@ -142,6 +159,12 @@ void set_hop_mask(HopArgs &a, const double *sc)
 
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s)
 {
+    if (!op->has_clover && op->has_twist) {
+        double re, im;
+        twist_factor(op, inv, false, re, im);
+        LQ_HIP(launch_twist_apply(op->g, re, im, out, in, s));
+        return;
+    }
     if (!op->has_clover) {
         if (out.base != in.base)
             for (int r = 0; r < in.nrhs; ++r)

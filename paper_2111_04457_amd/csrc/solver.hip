@@ -509,7 +509,8 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         LQ_HIP(launch_copy(c.irin, c.r64, c.sc, c.sps, true, c.s));
         // left preconditioning of the inner system: A_ee^-1 M e = A_ee^-1 r
         // (the outer loop keeps the true residual of M x = b)
-        const bool left = sp.left_precond && c.eo && !normal && sp.solver == LQ_BICGSTAB && c.group_op(0)->has_clover;
+        const bool left = sp.left_precond && c.eo && !normal && sp.solver == LQ_BICGSTAB &&
+                          (c.group_op(0)->has_clover || c.group_op(0)->has_twist);
         if (left)
             for (int g = 0; g < ng; ++g)
                 if (!gs[g].done) {
@@ -730,6 +731,10 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
     if (op->bound_nrhs && nrhs > op->bound_nrhs) {
         set_error("lq_solve: the bound workspace holds " + std::to_string(op->bound_nrhs) + " right-hand sides, " +
                   std::to_string(nrhs) + " requested");
+        return LQ_ERR_ARG;
+    }
+    if (op->has_twist && mode != LQ_D) {
+        set_error("lq_solve: a twisted-mass operator solves LQ_D only (its D^dag is gamma_5 D(-twist) gamma_5)");
         return LQ_ERR_ARG;
     }
     if (mode == LQ_DDAGD && use_x0) {

@@ -41,7 +41,7 @@ std::string tune_key(const lq_op *op, int prec, int nrhs, bool left)
     char buf[256];
     std::snprintf(buf, sizeof buf, "%s_red_%s_%dx%dx%dx%d_nl%d_%s_nrhs%d_gfx950", left ? "schur_left" : "schur",
                   pn[prec], op->g.L[0], op->g.L[1], op->g.L[2], op->g.L[3], op->nl(prec),
-                  op->has_clover ? "clover" : "wilson", nrhs);
+                  op->has_clover ? "clover" : op->has_twist ? "twisted" : "wilson", nrhs);
     return buf;
 }
 
@@ -152,7 +152,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
         hipEvent_t e0, e1;
         LQ_HIP(hipEventCreate(&e0));
         LQ_HIP(hipEventCreate(&e1));
-        const bool left = op->tune_form == 1 && op->has_clover;
+        const bool left = op->tune_form == 1 && (op->has_clover || op->has_twist);
         if (left) ensure_even_inverse(op, s);
         for (int prec = F64; prec <= F16; ++prec) {
             const std::string key = tune_key(op, prec, nrhs, left);
