@@ -144,6 +144,20 @@ typedef struct {
     int left_precond;     /* 1: each inner BiCGStab solve of the even-odd system runs on
                              A_ee^-1 M with the source A_ee^-1 r (clover only; the outer
                              FP64 loop keeps the residual of M x = b); default 0 */
+    int reliable;         /* 1: reliable updates -- after each FP64 residual replacement the
+                             inner Krylov solver continues its search directions (CG: p,
+                             BiCGStab: p, v and the shadow residual) on the new residual
+                             instead of starting a new space; a system whose last inner
+                             solve broke down, stopped at the iteration cap or made no
+                             iteration starts afresh.  0 (default): each inner solve
+                             starts from scratch (plain defect correction) */
+    int deflate;          /* 1: before each inner solve the outer loop projects the FP64
+                             residual with the operator's deflation space
+                             (lq_op_set_deflation): x += sum_k v_k v_k^dag M^dag r / lambda_k,
+                             r -= M of that (for M^dag M x = b: v_k^dag r and M^dag M).
+                             Even-odd solves of one operator (not lq_batch_solve); an
+                             operator without a deflation space is LQ_ERR_STATE.  0
+                             (default): no deflation */
 } lq_solver_params;
 
 /* Per-system solve statistics (nconv and diff of Fig. 1's invert). */
@@ -476,6 +490,20 @@ lq_status lq_eigs(lq_op *op, const lq_eig_params *p, const void *v0, double *eva
  * operator (freed with it).  Synchronizes the stream. */
 lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals, const void *evecs, const void *b, void *x0,
                             void *stream);
+
+/* Deflation space of the operator's solves (lq_solver_params.deflate):
+ * eigenpairs (lambda_k, v_k) of A = M^dag M, k < nvec <= 1024, evals on the
+ * host (finite, > 0), evecs device complex128 [nvec][V/2][4][3] (even
+ * sites in checkerboard order, orthonormal, as lq_eigs returns them).  The
+ * vectors are copied into device memory of the operator's own (nvec packed
+ * FP64 even fields, plus the solves' partial sums), so evecs may be freed
+ * after the call; nvec = 0 removes the space (the memory stays until the
+ * operator is destroyed).  The space belongs to the current operator:
+ * lq_op_set_gauge and lq_op_set_params remove it.  Operators bound to a caller's workspace
+ * (lq_op_bind) have no room for it: LQ_ERR_STATE.  The solve stays exact
+ * with any vectors (its residual update is an FP64 apply); poor ones only
+ * help less.  Synchronizes the stream. */
+lq_status lq_op_set_deflation(lq_op *op, int nvec, const double *evals, const void *evecs, void *stream);
 
 /* ------------------------------------------------------------------------
  * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the

@@ -35,7 +35,8 @@ class OpParams(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("even_odd", ctypes.c_int), ("left_precond", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("even_odd", ctypes.c_int), ("left_precond", ctypes.c_int),
+                ("reliable", ctypes.c_int), ("deflate", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -114,6 +115,7 @@ SIGNATURES = {
                         ctypes.POINTER(SolveStats), P]),
     "lq_eig_params_default": (None, [ctypes.POINTER(EigParams)]),
     "lq_deflated_guess": (I, [P, I, ctypes.POINTER(D), P, P, P, P]),
+    "lq_op_set_deflation": (I, [P, I, ctypes.POINTER(D), P, P]),
     "lq_eigs": (I, [P, ctypes.POINTER(EigParams), P, ctypes.POINTER(D), ctypes.POINTER(D), P,
                     ctypes.POINTER(EigStats), P]),
     "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),

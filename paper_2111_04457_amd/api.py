@@ -76,6 +76,8 @@ class SolverParams:
     check_every: int = 8
     even_odd: bool = True
     left_precond: bool = False   # inner BiCGStab on A_ee^-1 M (clover, even-odd)
+    reliable: bool = False       # keep the inner Krylov space across FP64 residual replacements
+    deflate: bool = False        # project each outer residual with the operator's deflation space
 
     def to_c(self) -> _lib.SolverParams:
         p = _lib.SolverParams()
@@ -89,6 +91,8 @@ class SolverParams:
         p.check_every = self.check_every
         p.even_odd = int(bool(self.even_odd))
         p.left_precond = int(bool(self.left_precond))
+        p.reliable = int(bool(self.reliable))
+        p.deflate = int(bool(self.deflate))
         return p
 
 
@@ -258,6 +262,21 @@ class Operator:
         check(load().lq_deflated_guess(self._h, nvec, ev, ctypes.c_void_p(evecs.data_ptr()),
                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x0.data_ptr()), _stream()))
         return x0
+
+    def set_deflation(self, evals, evecs: torch.Tensor | None) -> None:
+        """Give the operator's solves (SolverParams(deflate=True)) the
+        deflation space of lq_op_set_deflation: eigenpairs of M^dag M as eigs
+        returns them (evecs [nvec, V/2, 4, 3]: even fields in checkerboard
+        order, on the device); an empty evals removes it."""
+        nvec = len(evals) if evecs is not None else 0
+        if nvec == 0:
+            check(load().lq_op_set_deflation(self._h, 0, None, None, _stream()))
+            return
+        evecs = _dev(evecs, self.parity_shape, "evecs")
+        if evecs.numel() != nvec * 6 * self.V:
+            raise ValueError("set_deflation takes one even field per eigenvalue")
+        ev = (ctypes.c_double * nvec)(*[float(e) for e in evals])
+        check(load().lq_op_set_deflation(self._h, nvec, ev, ctypes.c_void_p(evecs.data_ptr()), _stream()))
 
     def tune(self, nrhs: int = 1, cache: str | None = None, left: bool = False) -> dict:
         """Autotune the hopping kernels (lq_tune) on the operator form the

@@ -102,6 +102,8 @@ void lq_solver_params_default(lq_solver_params *p)
     p->check_every = 8;
     p->even_odd = 1;
     p->left_precond = 0;
+    p->reliable = 0;
+    p->deflate = 0;
 }
 
 const char *lq_version(void) { return LQ_VERSION_STRING; }
@@ -217,6 +219,7 @@ static void set_gauge_device(lq_op *op, const double *U, hipStream_t s)
 {
     const Geom &g = op->g;
     op->gauge_set = false;
+    op->defl_n = 0;  // the deflation space belonged to the previous gauge field
     op->clear_graphs();
     op->links[F64].ensure(8 * link_bytes(F64, 18, g.vh));
     op->links[F32].ensure(8 * link_bytes(F32, op->prm.link_recon, g.vh));
@@ -275,6 +278,7 @@ lq_status lq_op_set_params(lq_op *op, double kappa, double csw, const double bc[
     return guarded([&]() -> lq_status {
         select_device(op);
         op->clear_graphs();
+        op->defl_n = 0;  // the deflation space belonged to the previous parameters
         op->prm.kappa = kappa;
         op->prm.csw = csw;
         op->has_clover = csw != 0.0;

@@ -153,8 +153,9 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
             k2.tile_off[j + 1] = k2.tile_off[j] + tiles;
         }
         const int recon = bt->ops[0]->prm.link_recon;
-        LQ_HIP(launch_hop_batch(k1, prec, recon, dag, clover ? 2 : 0, false, 0, c.s));
-        LQ_HIP(launch_hop_batch(k2, prec, recon, dag, clover ? (left ? 3 : 1) : 0, true, red, c.s));
+        const int tw = bt->ops[0]->has_twist ? kTwist : 0;  // every operator of a batch is of one kind
+        LQ_HIP(launch_hop_batch(k1, prec, recon, dag, clover ? (2 | tw) : 0, false, 0, c.s));
+        LQ_HIP(launch_hop_batch(k2, prec, recon, dag, clover ? ((left ? 3 : 1) | tw) : 0, true, red, c.s));
     }
 }
 
@@ -312,6 +313,10 @@ extern "C" lq_status lq_batch_solve(lq_batch *bt, const lq_solver_params *sp, vo
     std::string why;
     if (!valid_solver_params(sp, why)) {
         set_error("lq_batch_solve: invalid solver parameters: " + why);
+        return LQ_ERR_ARG;
+    }
+    if (sp->deflate) {
+        set_error("lq_batch_solve: deflation is a solve of one operator (lq_solve); a batch does not deflate");
         return LQ_ERR_ARG;
     }
     if (!sp->even_odd) {

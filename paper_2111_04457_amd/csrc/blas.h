@@ -27,8 +27,14 @@ enum ScalarSlot {
     SC_DOT_RE, SC_DOT_IM,
     SC_FORCE_BREAK,  // > 0: BiCGStab takes rho_new = 0 at this iteration (a breakdown forced from
                      // the host to exercise the restart path; 0 in every ordinary solve)
+    SC_REINIT,       // reliable updates: 1 = the system starts a new Krylov space at the next
+                     // restart (set by the host), 0 = it continues the one it has
+    SC_RR_PREV,      // CG: |r|^2 of the iteration before the last one
+    SC_RESCALE,      // reliable updates: |r| of the previous inner solve's source over the
+                     // current one's (the factor between the two normalisations)
     NSC = 24
 };
+static_assert(SC_RESCALE < NSC, "solver scalar slots exceed NSC");
 
 enum FinishOp {
     FIN_NORM = 0,       // K=1: SC_NORM2, SC_SCALE, SC_INVSCALE, SC_ODONE (vs SC_OTARGET2)
@@ -39,7 +45,12 @@ enum FinishOp {
     FIN_BICG_ALPHA,     // K=2: <rhat, v> -> alpha = rho / <rhat, v>
     FIN_BICG_OMEGA,     // K=3: <s, t>, |t|^2 -> omega = <t, s> / |t|^2
     FIN_BICG_RHO,       // K=3: <rhat, r>, |r|^2 -> beta, rho, rr, iter, done
-    FIN_DOT             // K=2: SC_DOT
+    FIN_DOT,            // K=2: SC_DOT
+    FIN_BICG_RESTART,   // K=3: <rhat, r>, |r|^2 of a replaced residual -> as FIN_INIT_BICG, but
+                        // beta and rho continue the Krylov space (SC_REINIT = 0)
+    FIN_CG_RESTART      // K=3: <p, r>, |r|^2 of a replaced residual -> as FIN_INIT_CG, and
+                        // beta, omega for p = r + beta (p - omega r), which continues the
+                        // search direction (SC_REINIT = 0)
 };
 
 // Per-slice reductions written to partial[(slice * nblocks + block) * K + k]
@@ -78,7 +89,12 @@ hipError_t launch_sub_scaled_norm(FieldView r64, FieldView e, const double *sc, 
 // CG: x += alpha p; r -= alpha q; partial |r|^2
 hipError_t launch_cg_xr(FieldView x, FieldView r, FieldView p, FieldView q, const double *sc, int sps,
                         double *partial, hipStream_t s);
-// CG: p = r + beta p
+// Reliable-update restarts: for the systems with SC_REINIT set (and the
+// outer residual not yet converged) a = src, b = src (if b.base) and z = 0
+// (if z.base); the other systems keep their vectors.
+hipError_t launch_reinit(FieldView a, FieldView b, FieldView z, FieldView src, const double *sc, int sps,
+                         hipStream_t s);
+// CG: p = r + beta p (frozen systems keep p)
 hipError_t launch_cg_p(FieldView p, FieldView r, const double *sc, int sps, hipStream_t s);
 // BiCGStab: s = r - alpha v
 hipError_t launch_bicg_s(FieldView sv, FieldView r, FieldView v, const double *sc, int sps, hipStream_t s);

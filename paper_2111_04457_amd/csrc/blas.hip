@@ -194,6 +194,7 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
             sc[SC_BETA_RE] = 0.0;
         } else {
             sc[SC_BETA_RE] = rr / sc[SC_RR];
+            sc[SC_RR_PREV] = sc[SC_RR];
             sc[SC_RR] = rr;
             sc[SC_ITER] += 1.0;
             if (rr <= sc[SC_TARGET2]) sc[SC_DONE] = 1.0;
@@ -203,10 +204,14 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
         break;
     }
     case FIN_BICG_ALPHA: {
+        // a frozen system keeps alpha and omega of its last iteration (a
+        // reliable-update restart continues from them; no kernel reads the
+        // scalars of a frozen system)
+        if (fz) break;
         const double dr = tot[0], di = tot[1];
         const double d2 = dr * dr + di * di;
-        if (fz || !(d2 > 0) || !(d2 < 1e300)) {
-            if (!fz) sc[SC_BREAK] = 1.0;
+        if (!(d2 > 0) || !(d2 < 1e300)) {
+            sc[SC_BREAK] = 1.0;
             sc[SC_ALPHA_RE] = sc[SC_ALPHA_IM] = 0.0;
         } else {
             const double rr_ = sc[SC_RHO_RE], ri = sc[SC_RHO_IM];
@@ -218,7 +223,8 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
     case FIN_BICG_OMEGA: {
         // tot = <s, t> (re, im), |t|^2 ; omega = <t, s> / |t|^2 = conj(<s, t>) / |t|^2
         const double tt = tot[2];
-        if (fz || !(tt > 0)) {
+        if (fz) break;
+        if (!(tt > 0)) {
             sc[SC_OMEGA_RE] = sc[SC_OMEGA_IM] = 0.0;
         } else {
             sc[SC_OMEGA_RE] = tot[0] / tt;
@@ -262,6 +268,64 @@ __global__ __launch_bounds__(FT) void finish_kernel(const double *partial, int s
         sc[SC_DOT_RE] = tot[0];
         sc[SC_DOT_IM] = tot[1];
         break;
+    case FIN_BICG_RESTART:
+    case FIN_CG_RESTART: {
+        // the residual r was replaced by the true one, in the normalisation
+        // of this inner solve; the stored scalars are those of the last
+        // iteration before the replacement (its x and r update done, the
+        // search direction not yet updated)
+        const double rr = tot[2];
+        const bool fresh = sc[SC_REINIT] != 0.0;
+        sc[SC_TARGET2] *= rr;  // relative -> absolute
+        sc[SC_ITER] = 0;
+        sc[SC_BREAK] = 0;
+        sc[SC_DONE] = (sc[SC_ODONE] != 0.0 || rr <= sc[SC_TARGET2] || !(rr > 0)) ? 1.0 : 0.0;
+        double br = 0.0, bi = 0.0;
+        if (op == FIN_CG_RESTART) {
+            // p = r + beta (p - c r): the search direction first loses its
+            // component along the replaced residual (c = <r, p> / |r|^2; in
+            // exact arithmetic r is orthogonal to p), then beta = |r|^2 /
+            // |r_old|^2 with |r_old|^2 and p taken into the new normalisation
+            // (factors SC_RESCALE^2, SC_RESCALE).  tot = <p, r>, |r|^2.
+            const double den = sc[SC_RESCALE] * sc[SC_RR_PREV];
+            if (!fresh && den > 0 && den < 1e300 && rr > 0) {
+                br = rr / den;
+                sc[SC_OMEGA_RE] = tot[0] / rr;
+                sc[SC_OMEGA_IM] = -tot[1] / rr;
+            } else {
+                sc[SC_OMEGA_RE] = sc[SC_OMEGA_IM] = 0.0;
+            }
+            sc[SC_ALPHA_RE] = sc[SC_ALPHA_IM] = 0.0;
+        } else {
+            // beta = (rho_new / rho) (alpha / omega) as in FIN_BICG_RHO; rho,
+            // p and v change normalisation by the same factor, which cancels.
+            // A fresh system, or one whose last scalars admit no
+            // continuation, takes beta = 0 (p = r)
+            const double pr = fresh ? rr : tot[0], pi = fresh ? 0.0 : tot[1];
+            const double om2 = sc[SC_OMEGA_RE] * sc[SC_OMEGA_RE] + sc[SC_OMEGA_IM] * sc[SC_OMEGA_IM];
+            const double rho2 = sc[SC_RHO_RE] * sc[SC_RHO_RE] + sc[SC_RHO_IM] * sc[SC_RHO_IM];
+            if (!fresh && om2 > 0 && rho2 > 0 && om2 < 1e300 && rho2 < 1e300) {
+                const double qr = (pr * sc[SC_RHO_RE] + pi * sc[SC_RHO_IM]) / rho2;
+                const double qi = (pi * sc[SC_RHO_RE] - pr * sc[SC_RHO_IM]) / rho2;
+                const double ar = (sc[SC_ALPHA_RE] * sc[SC_OMEGA_RE] + sc[SC_ALPHA_IM] * sc[SC_OMEGA_IM]) / om2;
+                const double ai = (sc[SC_ALPHA_IM] * sc[SC_OMEGA_RE] - sc[SC_ALPHA_RE] * sc[SC_OMEGA_IM]) / om2;
+                br = qr * ar - qi * ai;
+                bi = qr * ai + qi * ar;
+            }
+            if (!(br == br) || !(bi == bi)) br = bi = 0.0;
+            if (fresh) {
+                sc[SC_ALPHA_RE] = sc[SC_OMEGA_RE] = 1.0;
+                sc[SC_ALPHA_IM] = sc[SC_OMEGA_IM] = 0.0;
+            }
+            sc[SC_RHO_RE] = pr;
+            sc[SC_RHO_IM] = pi;
+        }
+        if (!(br == br)) br = 0.0;
+        sc[SC_BETA_RE] = br;
+        sc[SC_BETA_IM] = bi;
+        sc[SC_RR] = rr;
+        break;
+    }
     }
 }
 
@@ -414,7 +478,7 @@ __global__ __launch_bounds__(BT) void cg_p_kernel(FieldView p, FieldView x /* r 
     using R = typename PT<P>::R;
     LQ_SITE
     const double *s = sc + (slice / sps) * NSC;
-    if (s[SC_BREAK] != 0.0) return;
+    if (frozen(s)) return;
     const R be = (R)s[SC_BETA_RE];
     const Spinor<R> rv = load_spinor<P>(at(x, L), i, L.n);
     Spinor<R> pv = load_spinor<P>(at(p, L), i, L.n);
@@ -510,6 +574,27 @@ __global__ __launch_bounds__(BT) void bicg_p_kernel(FieldView p, FieldView x /* 
     store_spinor<P>(at(p, L), i, L.n, pv);
 }
 
+// a = src, b = src, z = 0 on the systems starting a new Krylov space (all
+// operands in precision P; b and z optional)
+template <int P>
+__global__ __launch_bounds__(BT) void reinit_kernel(FieldView a, FieldView b, FieldView z, FieldView x /* src */,
+                                                   const double *sc, int sps)
+{
+    using R = typename PT<P>::R;
+    LQ_SITE
+    const double *s = sc + (slice / sps) * NSC;
+    if (s[SC_REINIT] == 0.0 || s[SC_ODONE] != 0.0) return;
+    const Spinor<R> v = load_spinor<P>(at(x, L), i, L.n);
+    store_spinor<P>(at(a, L), i, L.n, v);
+    if (b.base) store_spinor<P>(at(b, L), i, L.n, v);
+    if (z.base) {
+        Spinor<R> o;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o.c[k] = cx<R>{0, 0};
+        store_spinor<P>(at(z, L), i, L.n, o);
+    }
+}
+
 template <int P> __global__ __launch_bounds__(BT) void gamma5_kernel(FieldView x)
 {
     using R = typename PT<P>::R;
@@ -534,6 +619,13 @@ static dim3 grid_of(const FieldView &x) { return x.tiles ? dim3(x.ntiles) : dim3
     return hipGetLastError();
 
 hipError_t launch_zero(FieldView x, hipStream_t s) { LQ_BY_PREC(x.prec, zero_kernel, x) }
+
+hipError_t launch_reinit(FieldView a, FieldView b, FieldView z, FieldView x, const double *sc, int sps,
+                         hipStream_t s)
+{
+    if (a.prec != x.prec || (b.base && b.prec != x.prec) || (z.base && z.prec != x.prec)) return hipErrorInvalidValue;
+    LQ_BY_PREC(x.prec, reinit_kernel, a, b, z, x, sc, sps)
+}
 
 hipError_t launch_copy(FieldView y, FieldView x, const double *sc, int sps, bool scaled, hipStream_t s)
 {

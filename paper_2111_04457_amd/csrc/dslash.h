@@ -15,12 +15,14 @@
 
 namespace lq {
 
-// Epilogue applied to res = coef * (H in):
+// Epilogue applied to res = coef * (H in), clover mode CLOV = clov & 3:
 //   CLOV == 3: res = C res (before the axpy)
 //   XPAY:      res = (CLOV == 1 ? C y : y) + res
 //   CLOV == 2: res = C res
 // where C is the packed clover block field of the output parity (A or A^-1),
-// or (clov null) the twisted-mass diagonal A = 1 + i tau gamma_5 or its inverse.
+// or, with the bit kTwist in clov (clov null), the twisted-mass diagonal
+// A = 1 + i tau gamma_5 or its inverse (one right-hand side per thread).
+constexpr int kTwist = 4;
 struct HopArgs {
     Geom g;
     int p_out;           // output parity

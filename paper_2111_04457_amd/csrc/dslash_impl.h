@@ -210,22 +210,30 @@ template <int P, int CLOV> struct CachePolicy {
     static constexpr int value = (P == F16 && CLOV == 0) ? 2 : 3;
 };
 
-// The site-local factor C of the epilogue: a clover block (A or A^-1, two
-// 6x6 Hermitian blocks, already loaded into craw), or, for the twisted-mass
-// Wilson operator (no clover block), the scalar tw on spins 0, 1 and its
-// conjugate on spins 2, 3 (A = 1 + i tau gamma_5 or its inverse, conjugated
-// for the dagger).
-template <typename S, typename R>
+// The epilogue's site-local factor C is chosen at compile time: the clover
+// mode (CLOV & 3: 0 none, 1 on y, 2 on the result, 3 on the hopping term
+// before the axpy) and, with bit kTwist, the twisted-mass factor in place of
+// a clover block.  A runtime choice between the two costs the FP64 clover
+// kernels their register budget (the 72-real block is then loaded under a
+// branch, next to the other path's registers).
+template <int CLOV> constexpr int clov_mode() { return CLOV & 3; }
+template <int CLOV> constexpr bool has_block() { return (CLOV & 3) != 0 && (CLOV & kTwist) == 0; }
+
+// C v: a clover block (A or A^-1, two 6x6 Hermitian blocks, already loaded
+// into craw), or, for the twisted-mass Wilson operator, the scalar tw on
+// spins 0, 1 and its conjugate on spins 2, 3 (A = 1 + i tau gamma_5 or its
+// inverse, conjugated for the dagger).
+template <int CLOV, typename S, typename R>
 __device__ __forceinline__ void diag_mul(const HopArgs &a, const S *__restrict__ craw, Spinor<R> &v)
 {
-    if (a.clov) {
-        clover_mul_raw(craw, v);
-    } else {
+    if constexpr ((CLOV & kTwist) != 0) {
         const cx<R> c = cx<R>{(R)a.tw_re, (R)a.tw_im};
 #pragma unroll
         for (int i = 0; i < 6; ++i) v.c[i] = c * v.c[i];
 #pragma unroll
         for (int i = 6; i < 12; ++i) v.c[i] = conj(c) * v.c[i];
+    } else {
+        clover_mul_raw(craw, v);
     }
 }
 
@@ -246,14 +254,14 @@ __device__ __forceinline__ void epilogue(const HopArgs &a, int cb, int rhs0, int
             Spinor<R> res;
 #pragma unroll
             for (int i = 0; i < 12; ++i) res.c[i] = unit ? acc[r][i] : coef * acc[r][i];
-            if constexpr (CLOV == 3) diag_mul(a, craw, res);
+            if constexpr (clov_mode<CLOV>() == 3) diag_mul<CLOV>(a, craw, res);
             if constexpr (XPAY) {
                 Spinor<R> yv = load_spinor<P>(a.y + rhs * a.y_rs, cb, a.y_n);
-                if constexpr (CLOV == 1) diag_mul(a, craw, yv);
+                if constexpr (clov_mode<CLOV>() == 1) diag_mul<CLOV>(a, craw, yv);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) res.c[i] = yv.c[i] + res.c[i];
             }
-            if constexpr (CLOV == 2) diag_mul(a, craw, res);
+            if constexpr (clov_mode<CLOV>() == 2) diag_mul<CLOV>(a, craw, res);
             store_spinor<P, (CACHE & 2) != 0>(a.out + rhs * a.out_rs, cb, a.out_n, res);
             if constexpr (RED != 0) {
                 // <w, out> (and |out|^2) of the values as stored
@@ -345,10 +353,8 @@ __device__ __forceinline__ void hop_body(const HopArgs &a, const int id)
         HalfRaw<P, NL, NR> slot[PF];
         prologue<P, NL, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot);
         pipeline<P, NL, DAG, NR, PF, 0, (CACHE & 1) != 0>(a, in, nr, cb, c, slot, acc);
-        S craw[CLOV ? 72 : 1];
-        if constexpr (CLOV != 0) {
-            if (a.clov) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
-        }
+        S craw[has_block<CLOV>() ? 72 : 1];
+        if constexpr (has_block<CLOV>()) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
         epilogue<P, CLOV, XPAY, RED, NR, CACHE>(a, cb, rhs0, nr, craw, acc, red0, red1, red2);
     }
     if constexpr (RED != 0) {
@@ -549,10 +555,8 @@ __global__ __launch_bounds__(256) void hop_halo_kernel(HopArgs a, HaloTile h)
     halo_half<P, NL, DAG, 5>(a, h, smem, nsites, halo_slot(h, ry, rz - 1, rt), j, link[5], wrap[5], acc);
     halo_half<P, NL, DAG, 6>(a, h, smem, nsites, halo_slot(h, ry, rz, rt + 1), j, link[6], wrap[6], acc);
     halo_half<P, NL, DAG, 7>(a, h, smem, nsites, halo_slot(h, ry, rz, rt - 1), j, link[7], wrap[7], acc);
-    S craw[CLOV ? 72 : 1];
-    if constexpr (CLOV != 0) {
-            if (a.clov) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
-        }
+    S craw[has_block<CLOV>() ? 72 : 1];
+    if constexpr (has_block<CLOV>()) load_planes<S, 72>(a.clov, cb, a.g.vh, craw);
     double red0[1] = {0.0}, red1[1] = {0.0}, red2[1] = {0.0};
     epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, 0, 1, craw, acc, red0, red1, red2);
     if constexpr (RED != 0) write_partials<RED, 1>(a, cb >> 6, 0, 1, red0, red1, red2);
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
     using Rt = typename PT<P>::R;
     using S = typename PT<P>::S;
     __shared__ S lk[8][NL][64];
-    __shared__ S lc[CLOV ? 72 : 1][64];
+    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
     // tiles (site block of 64, group of R right-hand sides), XCD-aware as in hop_body
     const int nbs = (a.g.vh + 63) / 64;
     const int ngr = (a.nrhs + R - 1) / R;
@@ -690,8 +694,8 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
     if (site_ok && rhs_ok) prologue_sp<P, NL, PF, 0>(a, in, cb, c, slot);
     if (site_ok) {
         stage_links<P, NL, 0, R, (CACHE & 1) != 0>(a, w, lane, cb, c, lk);
-        if constexpr (CLOV != 0) {
-            if (w == R - 1 && a.clov) {
+        if constexpr (has_block<CLOV>()) {
+            if (w == R - 1) {
                 S raw[72];
                 load_planes<S, 72>(a.clov, cb, a.g.vh, raw);
 #pragma unroll
@@ -706,12 +710,10 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
 #pragma unroll
         for (int i = 0; i < 12; ++i) acc[0][i] = cx<Rt>{0, 0};
         pipeline_sp<P, NL, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
-        S craw[CLOV ? 72 : 1];
-        if constexpr (CLOV != 0) {
-            if (a.clov) {
+        S craw[has_block<CLOV>() ? 72 : 1];
+        if constexpr (has_block<CLOV>()) {
 #pragma unroll
-                for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
-            }
+            for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
         }
         epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, rhs, 1, craw, acc, red0, red1, red2);
     }
@@ -763,9 +765,30 @@ static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 // The epilogue combinations the operators use:
 //   (clov, xpay, red) in {(0,0,0) plain hop, (2,0,0) C H x, (1,1,*) C y + c H x,
 //                         (0,1,*) y + c H x, (2,1,0) C (y + c H x), (3,1,*) y + C (c H x)}
+// The twisted-mass epilogues (clov | kTwist), one right-hand side per thread.
+template <int P, int NL, bool DAG>
+static hipError_t launch_epi_tw(const HopArgs &a, int clov, bool xpay, int red, int block, hipStream_t s)
+{
+    constexpr int T = kTwist;
+    if (!xpay && red == 0 && clov == 2) return launch_nt<P, NL, DAG, T | 2, false, 0, 1>(a, block, s);
+    if (xpay) {
+        if (clov == 1 && red == 0) return launch_nt<P, NL, DAG, T | 1, true, 0, 1>(a, block, s);
+        if (clov == 1 && red == 2) return launch_nt<P, NL, DAG, T | 1, true, 2, 1>(a, block, s);
+        if (clov == 1 && red == 3) return launch_nt<P, NL, DAG, T | 1, true, 3, 1>(a, block, s);
+        if (clov == 2 && red == 0) return launch_nt<P, NL, DAG, T | 2, true, 0, 1>(a, block, s);
+        if constexpr (!DAG) {
+            if (clov == 3 && red == 0) return launch_nt<P, NL, DAG, T | 3, true, 0, 1>(a, block, s);
+            if (clov == 3 && red == 2) return launch_nt<P, NL, DAG, T | 3, true, 2, 1>(a, block, s);
+            if (clov == 3 && red == 3) return launch_nt<P, NL, DAG, T | 3, true, 3, 1>(a, block, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int P, int NL, bool DAG>
 static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
+    if (clov & kTwist) return launch_epi_tw<P, NL, DAG>(a, clov & 3, xpay, red, block, s);
     if (!xpay && red == 0) {
         if (clov == 0) return launch_nr<P, NL, DAG, 0, false, 0>(a, nr, block, s);
         if (clov == 2) return launch_nr<P, NL, DAG, 2, false, 0>(a, nr, block, s);
@@ -798,6 +821,22 @@ static hipError_t launch_batch1(const HopBatch &b, hipStream_t s)
 template <int P, int NL, bool DAG>
 static hipError_t launch_epi_batch(const HopBatch &b, int clov, bool xpay, int red, hipStream_t s)
 {
+    if (clov & kTwist) {
+        constexpr int T = kTwist;
+        clov &= 3;
+        if (!xpay && red == 0 && clov == 2) return launch_batch1<P, NL, DAG, T | 2, false, 0>(b, s);
+        if (xpay) {
+            if (clov == 1 && red == 0) return launch_batch1<P, NL, DAG, T | 1, true, 0>(b, s);
+            if (clov == 1 && red == 2) return launch_batch1<P, NL, DAG, T | 1, true, 2>(b, s);
+            if (clov == 1 && red == 3) return launch_batch1<P, NL, DAG, T | 1, true, 3>(b, s);
+            if constexpr (!DAG) {
+                if (clov == 3 && red == 0) return launch_batch1<P, NL, DAG, T | 3, true, 0>(b, s);
+                if (clov == 3 && red == 2) return launch_batch1<P, NL, DAG, T | 3, true, 2>(b, s);
+                if (clov == 3 && red == 3) return launch_batch1<P, NL, DAG, T | 3, true, 3>(b, s);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if (!xpay && red == 0) {
         if (clov == 0) return launch_batch1<P, NL, DAG, 0, false, 0>(b, s);
         if (clov == 2) return launch_batch1<P, NL, DAG, 2, false, 0>(b, s);

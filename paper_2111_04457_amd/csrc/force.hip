@@ -404,6 +404,10 @@ lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_
         set_error("lq_pf_force: the force of a twisted-mass operator is not provided");
         return LQ_ERR_ARG;
     }
+    if (sp->deflate && (variant != 0 || op->defl_n == 0)) {
+        set_error("lq_pf_force: deflate = 1 needs the even-odd variant and the operator's deflation space");
+        return LQ_ERR_STATE;
+    }
     if (!op->gauge_set) {
         set_error("lq_pf_force: gauge field not set");
         return LQ_ERR_STATE;
@@ -420,6 +424,7 @@ lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_
         const auto t0 = std::chrono::steady_clock::now();
         SolveCtx c;
         make_ctx(c, op, 1, eo, sp->inner, s);
+        c.deflate = sp->deflate != 0 && eo;
         // phi packed into the solve space (FP64)
         FieldView phiv = c.aux64;
         if (eo) LQ_HIP(launch_pack_spinor(g, 0, 1, static_cast<const double *>(phi), phiv, s));

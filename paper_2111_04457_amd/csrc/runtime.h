@@ -81,6 +81,9 @@ struct lq_op {
     lq::Buf tmp[8];
     lq::Buf force_ws;                    // clover-force insertions ([parity][plane], FP64)
     lq::Buf defl_ws[3];                  // deflated guess: packed fields, even fields, partial sums
+    lq::Buf defl_vecs;                   // deflation space: packed FP64 eigenvectors, then 1 / lambda
+    lq::Buf defl_part;                   // deflation: partial sums and coefficients of the projection
+    int defl_n = 0;                      // vectors of the deflation space (0: none)
     lq::Buf md_G;                        // molecular dynamics: the force on every link
     lq::Buf md_partial;                  // molecular dynamics: per-wavefront partial sums
     lq::Buf md_X[3];                     // molecular dynamics: previous solutions and the next guess
@@ -126,7 +129,8 @@ struct lq_op {
     // reduction partials, solver, force, eigensolver and MD workspaces)
     size_t work_bytes() const
     {
-        size_t n = force_ws.bytes + md_G.bytes + md_partial.bytes + partial.bytes + solver_ws.bytes + solver_sc.bytes;
+        size_t n = force_ws.bytes + md_G.bytes + md_partial.bytes + partial.bytes + solver_ws.bytes + solver_sc.bytes +
+                   defl_vecs.bytes + defl_part.bytes;
         for (const auto &b : tmp) n += b.bytes;
         for (const auto &b : defl_ws) n += b.bytes;
         for (const auto &b : md_X) n += b.bytes;
@@ -137,7 +141,7 @@ struct lq_op {
     size_t owned_bytes() const
     {
         size_t n = links64r.owned() + flag.owned() + force_ws.owned() + md_G.owned() + md_partial.owned() +
-                   partial.owned() + solver_ws.owned() + solver_sc.owned();
+                   partial.owned() + solver_ws.owned() + solver_sc.owned() + defl_vecs.owned() + defl_part.owned();
         for (int p = 0; p < 3; ++p) n += links[p].owned() + clov[p].owned() + clovinv[p].owned();
         for (const auto &b : tmp) n += b.owned();
         for (const auto &b : defl_ws) n += b.owned();

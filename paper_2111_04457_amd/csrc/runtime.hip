@@ -117,6 +117,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     const Geom &g = op->g;
     HopArgs a = hop_args(op, prec, out, in, p_out, clov_mode, inv, dag, y, coef, w);
     if (clov_mode && !op->has_clover && !op->has_twist) clov_mode = 0;
+    if (clov_mode && op->has_twist) clov_mode |= kTwist;
     if (op->hop_mask) set_hop_mask(a, op->hop_mask);
     if (red) {
         // one partial per 64-site wavefront and right-hand side, K <= 3
@@ -125,7 +126,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     }
     // neighbour spinors staged in LDS (binary16, one right-hand side)
     HaloTile tile;
-    if (op->halo[prec] && prec == F16 && in.nrhs == 1 && halo_tile(g, tile)) {
+    if (op->halo[prec] && prec == F16 && in.nrhs == 1 && !(clov_mode & kTwist) && halo_tile(g, tile)) {
         LQ_HIP(launch_hop_halo(a, tile, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, s));
         return;
     }
@@ -141,7 +142,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     // right-hand sides per thread (2, no reductions), or 4 per workgroup
     // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)
     int nr = 1;
-    if (in.nrhs > 1) {
+    if (in.nrhs > 1 && !(clov_mode & kTwist)) {
         const int want = op->rhs_per_thread[prec];
         if (want == 2 && red == 0) nr = 2;
         else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;

@@ -77,6 +77,7 @@ struct SolveCtx {
     bool left = false;   // inner applies use the A_ee^-1-preconditioned Schur operator
     int force_break = 0; // > 0: the first inner BiCGStab solve breaks down at this iteration
     int log = 0;         // progress lines on stderr: 0 none, 1 per solve, 2 per outer step
+    bool deflate = false;  // project each outer residual with the operator's deflation space
     // FP64 vectors of the solve space
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
@@ -229,6 +230,16 @@ void bicg_iter(SolveCtx &c);
 void cg_init(SolveCtx &c, bool normal_rhs);
 void cg_iter(SolveCtx &c);
 bool all_frozen(const SolveCtx &c);
+// Reliable-update restarts of the inner solvers: the residual replaced by
+// the new source c.irin, the search directions kept (SC_REINIT = 0).
+void bicg_restart(SolveCtx &c);
+void cg_restart(SolveCtx &c, bool normal_rhs);
+
+// Deflation of the outer residual r (c.r64) with the operator's deflation
+// space: x += e, r -= A e for e = sum_k v_k v_k^dag y / lambda_k, y = M^dag r
+// (A = M) or r (normal: A = M^dag M); then FIN_NORM of the new r.  Uses
+// c.y64 and c.t64.  One operator, even-odd space.
+void deflate_residual(SolveCtx &c, bool normal);
 
 // Host-side validation of solver parameters; why holds the reason.
 bool valid_solver_params(const lq_solver_params *sp, std::string &why);

@@ -82,6 +82,32 @@ void cg_iter(SolveCtx &c)
     LQ_HIP(launch_cg_p(c.ip, c.ir, c.sc, c.sps, c.s));
 }
 
+// Reliable-update restarts: the inner residual is replaced by the new
+// normalised FP64 residual rin, the inner solution restarts from zero (the
+// outer loop has added it to x), and the search directions of the last
+// inner solve continue (systems with SC_REINIT set start afresh, as after
+// bicg_init / cg_init).  The stored scalars are those of each system's last
+// iteration, which ended after its x and r update (a system freezes before
+// its search direction is updated).
+void bicg_restart(SolveCtx &c)
+{
+    LQ_HIP(launch_zero(c.ix, c.s));
+    LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    LQ_HIP(launch_reinit(c.irhat, c.ip, c.iv, c.irin, c.sc, c.sps, c.s));
+    c.reduce_finish(c.irhat, c.ir, RED_DOT_NORM, FIN_BICG_RESTART);  // <rhat, r>, |r|^2
+    LQ_HIP(launch_bicg_p(c.ip, c.ir, c.iv, c.sc, c.sps, c.s));     // p = r + beta (p - omega v)
+}
+
+void cg_restart(SolveCtx &c, bool normal_rhs)
+{
+    LQ_HIP(launch_zero(c.ix, c.s));
+    if (normal_rhs) LQ_HIP(launch_copy(c.ir, c.irin, c.sc, c.sps, false, c.s));
+    else c.apply(c.ir, c.irin, true);
+    LQ_HIP(launch_reinit(c.ip, FieldView{}, FieldView{}, c.ir, c.sc, c.sps, c.s));
+    c.reduce_finish(c.ip, c.ir, RED_DOT_NORM, FIN_CG_RESTART);  // <p, r>, |r|^2
+    LQ_HIP(launch_bicg_p(c.ip, c.ir, c.ir, c.sc, c.sps, c.s));  // p = r + beta (p - omega r)
+}
+
 bool all_frozen(const SolveCtx &c)
 {
     for (int i = 0; i < c.nsys; ++i) {
@@ -122,15 +148,17 @@ int inner_loop(SolveCtx &c, int kind, int max_iter, ChunkPlan &plan)
     return it;
 }
 
-int inner_bicgstab(SolveCtx &c, int max_iter, ChunkPlan &plan)
+int inner_bicgstab(SolveCtx &c, int max_iter, ChunkPlan &plan, bool restart)
 {
-    bicg_init(c);
+    if (restart) bicg_restart(c);
+    else bicg_init(c);
     return inner_loop(c, 1, max_iter, plan);
 }
 
-int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, ChunkPlan &plan)
+int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, ChunkPlan &plan, bool restart)
 {
-    cg_init(c, normal_rhs);
+    if (restart) cg_restart(c, normal_rhs);
+    else cg_init(c, normal_rhs);
     return inner_loop(c, 2, max_iter, plan);
 }
 
@@ -458,6 +486,9 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         return m;
     };
     bool first_inner = true;
+    // reliable updates: |r| of each system's last inner source (the factor
+    // between two normalisations of the inner solve)
+    std::vector<double> last_scale(nsys, 0.0);
     for (int step = 0; step <= sp.max_outer; ++step) {
         for (int g = 0; g < ng; ++g) {
             Group &G = gs[g];
@@ -484,6 +515,12 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
             else finished = false;
         }
         if (finished) break;
+        // deflation: the residual loses its components along the deflation
+        // space's modes before the inner solve (the solution gains them)
+        if (c.deflate) {
+            deflate_residual(c, normal);
+            read_norms();
+        }
         // relative target of this inner solve, per system
         for (int g = 0; g < ng; ++g) {
             Group &G = gs[g];
@@ -498,12 +535,20 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
                 if (h[SC_ODONE] == 0.0) G.last_rel = std::min(G.last_rel, rel);
                 h[SC_TARGET2] = rel * rel;  // relative; FIN_INIT_* makes it absolute
                 h[SC_FORCE_BREAK] = first_inner ? c.force_break : 0;
+                // a system continues its Krylov space if its last inner solve
+                // converged after at least one iteration
+                const bool cont = !first_inner && h[SC_DONE] != 0.0 && h[SC_BREAK] == 0.0 && h[SC_ITER] > 0 &&
+                                  last_scale[i] > 0 && rn > 0;
+                h[SC_REINIT] = cont ? 0.0 : 1.0;
+                h[SC_RESCALE] = cont ? last_scale[i] / rn : 1.0;
+                last_scale[i] = rn;
                 if (h[SC_ODONE] == 0.0) os.outer[i]++;
             }
             if (c.log >= 2)
                 std::fprintf(stderr, "lq: outer step %d, lattice %d: |r| / |b| max %.3e (%s), inner target %.1e\n",
                              step, g, max_rel_residual(g), G.update ? "updated" : "FP64", G.last_rel);
         }
+        const bool restart = sp.reliable && !first_inner;
         first_inner = false;
         c.push();
         LQ_HIP(launch_copy(c.irin, c.r64, c.sc, c.sps, true, c.s));
@@ -524,9 +569,9 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         const int budget = std::min(sp.max_iter - total_inner, kInnerCap);
         plan.start(sp.check_every);
         int it;
-        if (normal) it = inner_cg(c, true, budget, plan);
-        else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, plan);
-        else it = inner_bicgstab(c, budget, plan);
+        if (normal) it = inner_cg(c, true, budget, plan, restart);
+        else if (sp.solver == LQ_CGNE) it = inner_cg(c, false, budget, plan, restart);
+        else it = inner_bicgstab(c, budget, plan, restart);
         c.left = false;
         total_inner += it;
         for (int i = 0; i < nsys; ++i) {
@@ -567,6 +612,7 @@ lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x6
     make_ctx(c, op, nsys, sp.even_odd != 0, sp.inner, s);
     c.force_break = op->break_at;
     op->break_at = 0;  // once
+    c.deflate = sp.deflate != 0 && op->defl_n > 0;
     c.log = log_level(op);
     const auto t0 = std::chrono::steady_clock::now();
 
@@ -656,6 +702,18 @@ bool valid_solver_params(const lq_solver_params *sp, std::string &why)
         why = "left_precond must be 0 or 1";
         return false;
     }
+    if (sp->reliable != 0 && sp->reliable != 1) {
+        why = "reliable must be 0 or 1";
+        return false;
+    }
+    if (sp->deflate != 0 && sp->deflate != 1) {
+        why = "deflate must be 0 or 1";
+        return false;
+    }
+    if (sp->deflate && !sp->even_odd) {
+        why = "deflation needs the even-odd solve";
+        return false;
+    }
     return true;
 }
 
@@ -743,6 +801,10 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
     }
     if (!op->gauge_set) {
         set_error("lq_solve: gauge field not set");
+        return LQ_ERR_STATE;
+    }
+    if (sp->deflate && op->defl_n == 0) {
+        set_error("lq_solve: deflate = 1 but the operator has no deflation space (lq_op_set_deflation)");
         return LQ_ERR_STATE;
     }
     try {
