@@ -75,6 +75,7 @@ extern "C" {
 typedef struct lq_op lq_op;
 typedef struct lq_field lq_field;
 typedef struct lq_batch lq_batch;
+typedef struct lq_mg lq_mg;
 
 typedef enum {
     LQ_OK = 0,
@@ -504,6 +505,69 @@ lq_status lq_deflated_guess(lq_op *op, int nvec, const double *evals, const void
  * with any vectors (its residual update is an FP64 apply); poor ones only
  * help less.  Synchronizes the stream. */
 lq_status lq_op_set_deflation(lq_op *op, int nvec, const double *evals, const void *evecs, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Two-level multigrid for D x = b (Sec. 1 cites adaptive multigrid for
+ * lattice QCD, Sec. 4 lists multigrid among the solvers; read as
+ * adaptive aggregation with a Galerkin coarse operator):
+ *   - aggregates: blocks of block[0] x .. x block[3] sites; every coarse
+ *     extent L_mu / block_mu must be even and >= 2 (each block_mu >= 2);
+ *   - the prolongator P: nvec near-null vectors, each split by chirality
+ *     (spins 0, 1 and spins 2, 3) and orthonormalised per aggregate and
+ *     chirality (modified Gram-Schmidt in vector order), so P^dag P = 1 and
+ *     P commutes with gamma_5; coarse degree of freedom r = chi * nvec + k;
+ *   - the coarse operator D_c = P^dag D P, a 9-point stencil of
+ *     (2 nvec)^2 complex blocks per coarse site: d = 0 the aggregate
+ *     itself, d = 1 + 2 mu the coupling to the aggregate at +mu, d = 2 + 2 mu
+ *     to the one at -mu (boundary phases included), stored in FP32;
+ *   - the solve: FP64 defect correction around flexible GCR (FP32, restart
+ *     gcr_restart) preconditioned by one cycle per iteration: coarse
+ *     correction P D_c^-1 P^dag r (BiCGStab on D_c to coarse_tol), then
+ *     smooth_steps minimal-residual steps on the fine residual.
+ * Near-null vectors: the caller's random start vectors v0, each improved
+ * by setup_iters inverse iterations v <- D^-1 v (the operator's own mixed
+ * solve to setup_tol, then normalised). */
+typedef struct {
+    int block[4];         /* aggregate extents (x, y, z, t) */
+    int nvec;             /* near-null vectors, 1..32 (coarse dof per site 2 nvec) */
+    int setup_iters;      /* inverse iterations per vector (>= 0) */
+    double setup_tol;     /* relative residual of those solves, in (0, 1) */
+    int smooth_steps;     /* minimal-residual steps of the post-smoother (>= 0) */
+    double coarse_tol;    /* relative residual of the coarse solve, in (0, 1) */
+    int coarse_max_iter;  /* iteration cap of the coarse solve (>= 1) */
+    int gcr_restart;      /* flexible GCR basis length, 1..32 */
+} lq_mg_params;
+
+void lq_mg_params_default(lq_mg_params *p);
+/* Build the two-level hierarchy for op's current gauge field and
+ * parameters (the setup above; it uses the operator's solver).  v0: device
+ * complex128 [nvec][V][4][3] start vectors (read only).  The hierarchy keeps
+ * a pointer to op (which must outlive it) and its own device memory: nvec
+ * FP32 full fields, the coarse operator (9 (2 nvec)^2 complex FP32 per
+ * aggregate) and the solver's vectors (2 gcr_restart + 8 FP32 full fields,
+ * 3 FP64 full fields).  A new gauge field or new parameters of op need a new
+ * hierarchy.  Synchronizes the stream. */
+lq_status lq_mg_create(lq_op *op, const lq_mg_params *p, const void *v0, lq_mg **mg, void *stream);
+lq_status lq_mg_destroy(lq_mg *mg);
+/* D x = b for one right-hand side (device complex128 [V][4][3]; x is
+ * written) to the true FP64 residual sp->tol (sp->inner_tol: relative
+ * target of each FP32 GCR solve; sp->max_iter caps the GCR iterations,
+ * sp->max_outer the FP64 steps; the other fields are not used).  stats:
+ * nconv = GCR iterations (one multigrid cycle each), nouter, diff, time.
+ * Returns LQ_NOT_CONVERGED if the cap is reached first. */
+lq_status lq_mg_solve(lq_mg *mg, const lq_solver_params *sp, void *x, const void *b, lq_solve_stats *stats,
+                      void *stream);
+/* Parts of the hierarchy, for checks against a reference: the
+ * orthonormalised vectors (device complex128 [nvec][V][4][3]); the coarse
+ * operator (host complex128 [ncoarse][9][2 nvec][2 nvec], coarse sites
+ * lexicographic with x fastest); restriction P^dag f (device complex128
+ * fine [V][4][3] -> coarse [ncoarse][2 nvec]), prolongation P c, and
+ * y = D_c x on device complex128 coarse vectors.  ncoarse = prod(L / block). */
+lq_status lq_mg_vectors(const lq_mg *mg, void *out, void *stream);
+lq_status lq_mg_coarse_op(const lq_mg *mg, double *out);
+lq_status lq_mg_restrict(lq_mg *mg, const void *fine, void *coarse, void *stream);
+lq_status lq_mg_prolong(lq_mg *mg, const void *coarse, void *fine, void *stream);
+lq_status lq_mg_coarse_apply(lq_mg *mg, const void *x, void *y, void *stream);
 
 /* ------------------------------------------------------------------------
  * Molecular dynamics of the Monte Carlo gauge-field generation (Sec. 2: the

@@ -7,13 +7,14 @@ include/lq.h; this package only marshals torch tensors and streams to it.
 from ._lib import LQError, load  # noqa: F401
 
 __all__ = ["Operator", "Field", "Batch", "SolverParams", "SolveStats", "apply_field", "pf_force", "PseudofermionAction",
-           "MDParams", "MDStats", "gauge_force", "md_trajectory", "hmc_step", "workspace_bytes", "bandwidth_probe", "LQError", "load"]
+           "MDParams", "MDStats", "gauge_force", "md_trajectory", "hmc_step", "workspace_bytes", "bandwidth_probe",
+           "Multigrid", "MGParams", "LQError", "load"]
 
 
 def __getattr__(name):
     if name in ("Operator", "Field", "Batch", "SolverParams", "SolveStats", "apply_field", "pf_force",
                 "PseudofermionAction", "MDParams", "MDStats", "gauge_force", "md_trajectory", "hmc_step",
-                "workspace_bytes", "bandwidth_probe"):
+                "workspace_bytes", "bandwidth_probe", "Multigrid", "MGParams"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

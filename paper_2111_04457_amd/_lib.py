@@ -74,6 +74,12 @@ class EigStats(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double)]
 
 
+class MGParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int * 4), ("nvec", ctypes.c_int), ("setup_iters", ctypes.c_int),
+                ("setup_tol", ctypes.c_double), ("smooth_steps", ctypes.c_int), ("coarse_tol", ctypes.c_double),
+                ("coarse_max_iter", ctypes.c_int), ("gcr_restart", ctypes.c_int)]
+
+
 # name -> (restype, argtypes)
 P = ctypes.c_void_p
 I = ctypes.c_int
@@ -116,6 +122,15 @@ SIGNATURES = {
     "lq_eig_params_default": (None, [ctypes.POINTER(EigParams)]),
     "lq_deflated_guess": (I, [P, I, ctypes.POINTER(D), P, P, P, P]),
     "lq_op_set_deflation": (I, [P, I, ctypes.POINTER(D), P, P]),
+    "lq_mg_params_default": (None, [ctypes.POINTER(MGParams)]),
+    "lq_mg_create": (I, [P, ctypes.POINTER(MGParams), P, ctypes.POINTER(P), P]),
+    "lq_mg_destroy": (I, [P]),
+    "lq_mg_solve": (I, [P, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolveStats), P]),
+    "lq_mg_vectors": (I, [P, P, P]),
+    "lq_mg_coarse_op": (I, [P, ctypes.POINTER(D)]),
+    "lq_mg_restrict": (I, [P, P, P, P]),
+    "lq_mg_prolong": (I, [P, P, P, P]),
+    "lq_mg_coarse_apply": (I, [P, P, P, P]),
     "lq_eigs": (I, [P, ctypes.POINTER(EigParams), P, ctypes.POINTER(D), ctypes.POINTER(D), P,
                     ctypes.POINTER(EigStats), P]),
     "lq_md_params_default": (None, [ctypes.POINTER(MDParams)]),

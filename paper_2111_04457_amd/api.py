@@ -459,6 +459,114 @@ class Batch:
 
 
 @dataclass
+class MGParams:
+    """Two-level multigrid parameters (lq_mg_params)."""
+    block: tuple = (4, 4, 4, 4)   # aggregate extents (x, y, z, t)
+    nvec: int = 12                # near-null vectors (coarse dof per aggregate 2 nvec)
+    setup_iters: int = 3          # inverse iterations per vector
+    setup_tol: float = 1e-2
+    smooth_steps: int = 8         # minimal-residual post-smoothing steps
+    coarse_tol: float = 0.05
+    coarse_max_iter: int = 200
+    gcr_restart: int = 16
+
+    def to_c(self) -> _lib.MGParams:
+        p = _lib.MGParams()
+        load().lq_mg_params_default(ctypes.byref(p))
+        for i in range(4):
+            p.block[i] = int(self.block[i])
+        p.nvec = self.nvec
+        p.setup_iters = self.setup_iters
+        p.setup_tol = self.setup_tol
+        p.smooth_steps = self.smooth_steps
+        p.coarse_tol = self.coarse_tol
+        p.coarse_max_iter = self.coarse_max_iter
+        p.gcr_restart = self.gcr_restart
+        return p
+
+
+class Multigrid:
+    """Two-level multigrid for D x = b on an operator (lq_mg_*): v0 are the
+    caller's random start vectors [nvec, Lt, Lz, Ly, Lx, 4, 3] (complex128,
+    CUDA) of the near-null vector setup."""
+
+    def __init__(self, op: Operator, v0: torch.Tensor, params: MGParams | None = None):
+        self.op = op
+        self.params = params or MGParams()
+        v0 = _dev(v0, op.full_shape, "v0")
+        if v0.numel() != self.params.nvec * 12 * op.V:
+            raise ValueError("v0 must hold nvec full fields")
+        cp = self.params.to_c()
+        h = ctypes.c_void_p()
+        check(load().lq_mg_create(op.handle, ctypes.byref(cp), ctypes.c_void_p(v0.data_ptr()), ctypes.byref(h),
+                                  _stream()))
+        self._h = h
+        self.ncoarse = 1
+        for L, b in zip(op.dims, self.params.block):
+            self.ncoarse *= L // b
+        self.n2 = 2 * self.params.nvec
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lq_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b: torch.Tensor, params: SolverParams | None = None):
+        """x = D^-1 b (one right-hand side [Lt, Lz, Ly, Lx, 4, 3]); returns (x, SolveStats)."""
+        params = params or SolverParams()
+        b = _dev(b, self.op.full_shape, "b")
+        if b.numel() != 12 * self.op.V:
+            raise ValueError("Multigrid.solve takes one right-hand side")
+        x = torch.empty_like(b)
+        st = _lib.SolveStats()
+        cp = params.to_c()
+        check(load().lq_mg_solve(self._h, ctypes.byref(cp), ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(b.data_ptr()), ctypes.byref(st), _stream()), allow_not_converged=True)
+        return x, SolveStats(st.nconv, st.nouter, st.restarts, bool(st.converged), st.diff, st.t_solve_ms,
+                             st.hop_bytes, st.n_hop)
+
+    def vectors(self) -> torch.Tensor:
+        """The orthonormalised near-null vectors [nvec, Lt, Lz, Ly, Lx, 4, 3]."""
+        out = torch.empty((self.params.nvec,) + self.op.full_shape, dtype=torch.complex128, device="cuda")
+        check(load().lq_mg_vectors(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def coarse_op(self):
+        """The coarse operator as a numpy array [ncoarse, 9, 2 nvec, 2 nvec] (complex128)."""
+        import numpy as np
+        out = np.zeros((self.ncoarse, 9, self.n2, self.n2), dtype=np.complex128)
+        check(load().lq_mg_coarse_op(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def restrict(self, f: torch.Tensor) -> torch.Tensor:
+        f = _dev(f, self.op.full_shape, "f")
+        out = torch.empty((self.ncoarse, self.n2), dtype=torch.complex128, device="cuda")
+        check(load().lq_mg_restrict(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream()))
+        return out
+
+    def prolong(self, c: torch.Tensor) -> torch.Tensor:
+        c = _dev(c, (self.ncoarse, self.n2), "c")
+        out = torch.empty(self.op.full_shape, dtype=torch.complex128, device="cuda")
+        check(load().lq_mg_prolong(self._h, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   _stream()))
+        return out
+
+    def coarse_apply(self, x: torch.Tensor) -> torch.Tensor:
+        x = _dev(x, (self.ncoarse, self.n2), "x")
+        out = torch.empty_like(x)
+        check(load().lq_mg_coarse_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        _stream()))
+        return out
+
+
+@dataclass
 class MDParams:
     """Molecular-dynamics parameters (lq_md_params)."""
     beta: float = 5.6

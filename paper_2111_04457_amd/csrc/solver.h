@@ -78,6 +78,12 @@ struct SolveCtx {
     int force_break = 0; // > 0: the first inner BiCGStab solve breaks down at this iteration
     int log = 0;         // progress lines on stderr: 0 none, 1 per solve, 2 per outer step
     bool deflate = false;  // project each outer residual with the operator's deflation space
+    // another operator than the fine one (the multigrid coarse operator):
+    // apply() calls coarse_apply, which reads coarse; key_extra enters the
+    // graph keys (an id of the coarse operator's buffers)
+    void (*coarse_apply)(SolveCtx &c, const FieldView &out, const FieldView &in) = nullptr;
+    const void *coarse = nullptr;
+    long key_extra = 0;
     // FP64 vectors of the solve space
     FieldView x64, r64, y64, t64, aux64;
     // inner vectors
@@ -157,7 +163,7 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
     // the graph replays the chunk with the masking state it was captured with
     const long masked_key = masked ? 1 : 0;
     std::vector<long> key = {kind, chunk, nsys, eo ? 1 : 0, pin, px, (long)partial, (long)sc, (long)(void *)s,
-                             masked_key, left ? 1L : 0L};
+                             masked_key, left ? 1L : 0L, key_extra};
     if (bt) {
         // every pointer and launch setting the batched kernels read
         key.push_back((long)bt->ws.ptr);
@@ -234,12 +240,22 @@ bool all_frozen(const SolveCtx &c);
 // the new source c.irin, the search directions kept (SC_REINIT = 0).
 void bicg_restart(SolveCtx &c);
 void cg_restart(SolveCtx &c, bool normal_rhs);
+// One inner BiCGStab solve from e = 0 on c's operator with source c.irin
+// (SC_TARGET2 set relative, SC_ODONE clear): chunks of check_every
+// iterations after a first one of hint (updated to the iterations needed);
+// returns the iterations launched.
+int bicgstab_solve(SolveCtx &c, int max_iter, int check_every, int &hint);
 
 // Deflation of the outer residual r (c.r64) with the operator's deflation
 // space: x += e, r -= A e for e = sum_k v_k v_k^dag y / lambda_k, y = M^dag r
 // (A = M) or r (normal: A = M^dag M); then FIN_NORM of the new r.  Uses
 // c.y64 and c.t64.  One operator, even-odd space.
 void deflate_residual(SolveCtx &c, bool normal);
+
+// Solve D x = b for nsys systems on full packed FP64 fields ([rhs][parity])
+// with the operator's mixed-precision solver (stats per system).
+lq_status solve_packed(lq_op *op, const lq_solver_params &sp, int nsys, char *x64, const char *b64, bool use_x0,
+                       lq_solve_stats *stats, hipStream_t s);
 
 // Host-side validation of solver parameters; why holds the reason.
 bool valid_solver_params(const lq_solver_params *sp, std::string &why);

@@ -164,6 +164,16 @@ int inner_cg(SolveCtx &c, bool normal_rhs, int max_iter, ChunkPlan &plan, bool r
 
 }  // namespace
 
+int bicgstab_solve(SolveCtx &c, int max_iter, int check_every, int &hint)
+{
+    ChunkPlan plan;
+    plan.hint = hint;
+    plan.start(check_every);
+    const int it = inner_bicgstab(c, max_iter, plan, false);
+    if (plan.hint > 0) hint = plan.hint;
+    return it;
+}
+
 void ChunkPlan::learn(const SolveCtx &c)
 {
     int most = 0;
@@ -257,6 +267,11 @@ void SolveCtx::apply_group(int g, const FieldView &out, const FieldView &in, boo
 
 void SolveCtx::apply(const FieldView &out, const FieldView &in, bool dag)
 {
+    if (coarse_apply) {
+        if (dag) throw Failure{LQ_ERR_STATE, "the coarse operator has no dagger form here"};
+        coarse_apply(*this, out, in);
+        return;
+    }
     const int p = in.prec;
     if (bt) {
         batch_schur(*this, p, out, in, space(odd_tmp[p], p), dag, eo && left, 0, nullptr);
