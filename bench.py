@@ -256,6 +256,7 @@ def _extras(lq, torch):
 
     out.update(_forces(lq, torch))
     out.update(_eigs(lq, torch))
+    out.update(_solver_variants(lq, torch))
     return out
 
 
@@ -347,6 +348,54 @@ def _eigs(lq, torch):
             out["eigs_%s_lowest" % name] = [float(e) for e in ev]
     op.close()
     print("bench: eigs %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
+def _solver_variants(lq, torch):
+    """The solver variants on a near-critical Wilson lattice, 16^3x32 with
+    smooth links (exp(i 0.1 H), kappa 0.1248, antiperiodic in time), one
+    Gaussian source, true residual 1e-10, each timed once after a warm-up
+    call: mixed BiCGStab (binary16 and FP32 storage), CG on the normal
+    equations with FP32 storage restarted at every FP64 residual or with
+    reliable updates, deflated by the 16 lowest eigenpairs of M^dag M, and
+    the two-level multigrid (4^4 aggregates, 12 near-null vectors; the setup
+    timed separately)."""
+    from lattice_inputs import ANTIPERIODIC_T, gauge_exp, gaussian_parity_spinor, gaussian_spinor
+    d, kappa = (16, 16, 16, 32), 0.1248
+    tag = "wilson_16x16x16x32_k1248"
+    op = lq.Operator(d, kappa, 0.0, ANTIPERIODIC_T, link_recon=12)
+    op.set_gauge(torch.from_numpy(gauge_exp(d, 0.1, 4242)).cuda())
+    b = torch.from_numpy(gaussian_spinor(d, 4243)).cuda()
+    out = {}
+
+    def run(name, fn):
+        fn()
+        (_, st), ms = _timed(torch, fn)
+        st = st[0] if isinstance(st, list) else st
+        out["%s_%s_ms" % (tag, name)] = ms
+        out["%s_%s_iters" % (tag, name)] = st.nconv
+        out["%s_%s_diff" % (tag, name)] = st.diff
+
+    run("bicgstab_f16", lambda: op.solve(b, "D", lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3)))
+    run("bicgstab_f32", lambda: op.solve(b, "D", lq.SolverParams(tol=1e-10, inner="f32", inner_tol=1e-5)))
+    for rel in (False, True):
+        run("cgne_f32_itol0.1%s" % ("_reliable" if rel else ""),
+            lambda: op.solve(b, "D", lq.SolverParams(solver="cgne", tol=1e-10, inner="f32", inner_tol=0.1,
+                                                     reliable=rel)))
+    v0 = torch.from_numpy(gaussian_parity_spinor(d, 4245)).cuda()
+    (ev, res, X, st), ms = _timed(torch, lambda: op.eigs(16, 64, v0=v0, tol=1e-8, vectors=True))
+    out["%s_eigs16_ms" % tag] = ms
+    op.set_deflation(ev, X)
+    run("cgne_f32_deflated16", lambda: op.solve(b, "D", lq.SolverParams(solver="cgne", tol=1e-10, inner="f32",
+                                                                          inner_tol=1e-5, deflate=True)))
+    op.set_deflation([], None)
+    v0m = torch.from_numpy(gaussian_spinor(d, 4244, 12)).cuda()
+    mg, ms = _timed(torch, lambda: lq.Multigrid(op, v0m, lq.MGParams()))
+    out["%s_mg_setup_ms" % tag] = ms
+    run("mg_gcr", lambda: mg.solve(b, lq.SolverParams(tol=1e-10, inner_tol=1e-5)))
+    mg.close()
+    op.close()
+    print("bench: solver variants %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
 
 

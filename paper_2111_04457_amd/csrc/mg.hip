@@ -157,33 +157,60 @@ __global__ __launch_bounds__(MT) void mg_orth_kernel(MgGeom m, char *V)
 }
 
 // coarse[A][chi * nv + k] = sum over A's sites of v_k(x)_chi^dag f(x)_chi
-// (f an FP32 full packed field)
+// (f an FP32 full packed field): one pass over the aggregate's sites per 8
+// vectors, each site's f loaded once; per-wavefront sums, then the waves in
+// order.
 __global__ __launch_bounds__(MT) void mg_restrict_kernel(MgGeom m, const char *V, const char *f, char *coarse)
 {
     const int A = blockIdx.x;
     int a[4];
     agg_coords(m, A, a);
-    __shared__ double lds[MT / 64];
+    __shared__ double red[MT / 64][2][16];
     const long fbytes = spinor_field_bytes(F32, m.g.vh);
-    for (int r = 0; r < m.n2; ++r) {
-        const int chi = r / m.nv, k = r % m.nv, c0 = 6 * chi;
-        double re = 0, im = 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < m.nv; k0 += 8) {
+        double re[16], im[16];  // index chi * 8 + q for vector k0 + q
+#pragma unroll
+        for (int i = 0; i < 16; ++i) re[i] = im[i] = 0.0;
         for (int l = threadIdx.x; l < m.asz; l += MT) {
             int c[4];
             agg_site(m, a, l, c);
             const int p = parity_of(c), cb = cb_index(m.g, c);
-            const Spinor<float> v = load_spinor<F32>(vec_site(m, V, k, p), cb, m.g.vh);
             const Spinor<float> x = load_spinor<F32>(f + p * fbytes, cb, m.g.vh);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                const cx<float> u = v.c[c0 + i], w = x.c[c0 + i];
-                re += (double)u.re * w.re + (double)u.im * w.im;
-                im += (double)u.re * w.im - (double)u.im * w.re;
+            for (int q = 0; q < 8; ++q) {
+                if (k0 + q >= m.nv) break;
+                const Spinor<float> v = load_spinor<F32>(vec_site(m, V, k0 + q, p), cb, m.g.vh);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    const cx<float> u = v.c[i], w = x.c[i];
+                    const int slot = (i / 6) * 8 + q;
+                    re[slot] += (double)u.re * w.re + (double)u.im * w.im;
+                    im[slot] += (double)u.re * w.im - (double)u.im * w.re;
+                }
             }
         }
-        re = block_sum<MT>(re, lds);
-        im = block_sum<MT>(im, lds);
-        if (threadIdx.x == 0) *celem(coarse, (long)A * m.n2 + r) = make_float2((float)re, (float)im);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const double sr = wave_sum(re[i]), si = wave_sum(im[i]);
+            if (lane == 0) {
+                red[wv][0][i] = sr;
+                red[wv][1][i] = si;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            const int i = threadIdx.x, chi = i / 8, k = k0 + i % 8;
+            if (k < m.nv) {
+                double sr = 0, si = 0;
+                for (int w = 0; w < MT / 64; ++w) {
+                    sr += red[w][0][i];
+                    si += red[w][1][i];
+                }
+                *celem(coarse, (long)A * m.n2 + chi * m.nv + k) = make_float2((float)sr, (float)si);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -216,34 +243,51 @@ __global__ __launch_bounds__(MT) void mg_prolong_kernel(MgGeom m, const char *V,
 }
 
 // y[A][r] = sum_d sum_c Dc[A][d][r][c] x[nbr(A, d)][c]; nothing if the
-// system is frozen (mask: its solver scalars)
-__global__ __launch_bounds__(64) void mg_capply_kernel(MgGeom m, const float2 *__restrict__ Dc, const char *x,
+// system is frozen (mask: its solver scalars).  One workgroup per
+// aggregate: the nine neighbours' coarse vectors in LDS, one thread per
+// (d, r) row product (rows contiguous in memory across the threads), then
+// the sum over d in order.
+__global__ __launch_bounds__(MT) void mg_capply_kernel(MgGeom m, const float2 *__restrict__ Dc, const char *x,
                                                       char *y, const double *mask)
 {
     if (mask && (mask[SC_DONE] != 0.0 || mask[SC_BREAK] != 0.0)) return;
-    const long e = (long)blockIdx.x * 64 + threadIdx.x;
-    if (e >= (long)m.nagg * m.n2) return;
-    const int A = (int)(e / m.n2), r = (int)(e % m.n2);
+    __shared__ float2 xs[9][64];
+    __shared__ float2 part[9][64];
+    const int A = blockIdx.x, n2 = m.n2;
     int a[4];
     agg_coords(m, A, a);
-    float ar = 0.0f, ai = 0.0f;
-    for (int d = 0; d < 9; ++d) {
+    for (int q = threadIdx.x; q < 9 * n2; q += MT) {
+        const int d = q / n2, c = q % n2;
         int b[4] = {a[0], a[1], a[2], a[3]};
         if (d > 0) {
             const int mu = (d - 1) >> 1;
             b[mu] = (d & 1) ? (b[mu] + 1) % m.lc[mu] : (b[mu] + m.lc[mu] - 1) % m.lc[mu];
         }
-        const long xb = (long)agg_index(m, b) * m.n2;
-        const float2 *row = Dc + (((long)A * 9 + d) * m.n2 + r) * m.n2;
-        for (int c = 0; c < m.n2; ++c) {
-            const float2 u = row[c], v = cget(x, xb + c);
+        xs[d][c] = cget(x, (long)agg_index(m, b) * n2 + c);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 9 * n2; q += MT) {
+        const int d = q / n2, r = q % n2;
+        const float2 *row = Dc + (((long)A * 9 + d) * n2 + r) * n2;
+        float ar = 0.0f, ai = 0.0f;
+        for (int c = 0; c < n2; ++c) {
+            const float2 u = row[c], v = xs[d][c];
             ar = __builtin_fmaf(u.x, v.x, ar);
             ar = __builtin_fmaf(-u.y, v.y, ar);
             ai = __builtin_fmaf(u.x, v.y, ai);
             ai = __builtin_fmaf(u.y, v.x, ai);
         }
+        part[d][r] = make_float2(ar, ai);
     }
-    *celem(y, e) = make_float2(ar, ai);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n2; r += MT) {
+        float sr = 0.0f, si = 0.0f;
+        for (int d = 0; d < 9; ++d) {
+            sr += part[d][r].x;
+            si += part[d][r].y;
+        }
+        *celem(y, (long)A * n2 + r) = make_float2(sr, si);
+    }
 }
 
 // Z_j (FP64 full fields): column col0 + j of P (chirality half chi of v_k,
@@ -584,9 +628,8 @@ int fine_nb(const lq_mg *mg) { return (mg->m.g.vh + MT - 1) / MT; }
 void coarse_apply_fn(SolveCtx &c, const FieldView &out, const FieldView &in)
 {
     const lq_mg *mg = static_cast<const lq_mg *>(c.coarse);
-    const long n = (long)mg->m.nagg * mg->m.n2;
-    mg_capply_kernel<<<(unsigned)((n + 63) / 64), 64, 0, c.s>>>(mg->m, reinterpret_cast<const float2 *>(mg->dc.ptr),
-                                                                in.base, out.base, c.masked ? c.sc : nullptr);
+    mg_capply_kernel<<<mg->m.nagg, MT, 0, c.s>>>(mg->m, reinterpret_cast<const float2 *>(mg->dc.ptr), in.base,
+                                                 out.base, c.masked ? c.sc : nullptr);
     LQ_HIP(hipGetLastError());
 }
 
@@ -1119,8 +1162,8 @@ lq_status lq_mg_coarse_apply(lq_mg *mg, const void *xin, void *yout, void *strea
         mg_cimport_kernel<<<(unsigned)((n + MT - 1) / MT), MT, 0, s>>>(n, static_cast<const double *>(xin),
                                                                        cvec(mg, 0));
         LQ_HIP(hipGetLastError());
-        mg_capply_kernel<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(m, reinterpret_cast<const float2 *>(mg->dc.ptr),
-                                                                  cvec(mg, 0), cvec(mg, 1), nullptr);
+        mg_capply_kernel<<<m.nagg, MT, 0, s>>>(m, reinterpret_cast<const float2 *>(mg->dc.ptr), cvec(mg, 0),
+                                               cvec(mg, 1), nullptr);
         LQ_HIP(hipGetLastError());
         mg_cexport_kernel<<<(unsigned)((n + MT - 1) / MT), MT, 0, s>>>(n, cvec(mg, 1), static_cast<double *>(yout));
         LQ_HIP(hipGetLastError());
