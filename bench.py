@@ -429,8 +429,10 @@ def _profile(lq, torch, args):
             fin, fout = lq.Field(op, "f16", nrhs), lq.Field(op, "f16", nrhs)
             src = torch.from_numpy(workload_source(name, nrhs=nrhs if nrhs > 1 else None)).cuda()
             fin.load(src.reshape(nrhs, -1, 4, 3)[:, : V // 2].contiguous().reshape((nrhs,) + op.parity_shape))
-            if not args.no_tune:  # counter runs take the default shape (tuning under counters is not timing)
+            if not args.no_tune:  # counter runs take a fixed shape (tuning under counters is not timing)
                 op.tune(nrhs, left=args.left_precond)
+            elif args.xcd_remap is not None:
+                op.set_option("xcd_remap_f16", args.xcd_remap)
             kind = "schur_left" if args.left_precond else "schur"
             us = _graph_time_us(torch, lambda: lq.apply_field(op, kind, fout, fin), args.kernel_reps)
             b2, _ = op.traffic("f16", nrhs, clover=True)
@@ -492,6 +494,9 @@ def main(argv=None):
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32-inner reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
+    ap.add_argument("--xcd-remap", type=int, default=None,
+                    help="--profile with --no-tune: the binary16 workgroup order to use (0 plain, 1 XCD-aware, "
+                         "2 XCD-aware with time slices interleaved)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 12-RHS propagator, ragged batch and force measurements")
     ap.add_argument("--force-only", action="store_true",
