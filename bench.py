@@ -72,9 +72,10 @@ def _timed(torch, fn):
     return out, 1e3 * (time.perf_counter() - t)
 
 
-def _graph_time_us(torch, fn, reps):
+def _graph_time_us(torch, fn, reps, replays=5):
     """Average duration of fn's launches: reps calls captured in one graph,
-    replayed between two HIP events on the stream the kernels run on."""
+    each replay timed between two HIP events on the stream the kernels run
+    on; the median of `replays` timed replays (after one untimed)."""
     for _ in range(3):
         fn()
     torch.cuda.synchronize()
@@ -86,12 +87,16 @@ def _graph_time_us(torch, fn, reps):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    g.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
+    times = []
+    for _ in range(replays):
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
     del g
-    return 1e3 * e0.elapsed_time(e1) / reps
+    times.sort()
+    return 1e3 * times[len(times) // 2] / reps
 
 
 def _kernels(lq, torch, op, b_d, V, recon, reps, left):
@@ -431,8 +436,8 @@ def _profile(lq, torch, args):
             fin.load(src.reshape(nrhs, -1, 4, 3)[:, : V // 2].contiguous().reshape((nrhs,) + op.parity_shape))
             if not args.no_tune:  # counter runs take a fixed shape (tuning under counters is not timing)
                 op.tune(nrhs, left=args.left_precond)
-            elif args.xcd_remap is not None:
-                op.set_option("xcd_remap_f16", args.xcd_remap)
+            else:  # the given order, else the automatic one, made explicit for the report
+                op.set_option("xcd_remap_f16", args.xcd_remap if args.xcd_remap is not None else (0 if nrhs == 1 else 2))
             kind = "schur_left" if args.left_precond else "schur"
             us = _graph_time_us(torch, lambda: lq.apply_field(op, kind, fout, fin), args.kernel_reps)
             b2, _ = op.traffic("f16", nrhs, clover=True)

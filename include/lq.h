@@ -294,13 +294,15 @@ lq_status lq_op_apply_field(lq_op *op, lq_kind kind, lq_field *out, const lq_fie
 lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
 
 /* Other execution options (none changes a result bit):
- *   "xcd_remap" 0|1|2  order of the hopping kernel's workgroups: 0 plain
- *                    (default), 1 XCD-aware (each XCD takes a contiguous
- *                    range of site blocks), 2 XCD-aware with the blocks of
- *                    neighbouring time slices visited one after another
- *                    (used when a time slice of one parity is a whole number
- *                    of workgroups, else as 1); all precisions;
- *                    "xcd_remap_f64" / "_f32" / "_f16" per precision;
+ *   "xcd_remap" -1|0|1|2  order of the hopping kernel's workgroups: 0 plain,
+ *                    1 XCD-aware (each XCD takes a contiguous range of site
+ *                    blocks), 2 XCD-aware with the blocks of neighbouring
+ *                    time slices visited one after another (used when a time
+ *                    slice of one parity is a whole number of workgroups,
+ *                    else as 1); -1 (default) automatic: 0 for one
+ *                    right-hand side, 2 for several (measured: plain order is
+ *                    fastest alone and 15-45 % slower with several); all
+ *                    precisions; "xcd_remap_f64" / "_f32" / "_f16" per precision;
  *   "graphs"    0|1  capture the solvers' inner-iteration chunks in hipGraphs (default 1);
  *   "tune_form" 0|1  the operator form lq_tune times: 0 M (default), 1 A_ee^-1 M
  *                    (clover operators; as 0 without clover);
@@ -312,9 +314,10 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *   "log_level" 0|1|2  progress lines of solves on stderr: 1 one per solve (outer
  *                    steps, iterations, restarts, residual), 2 also one per outer
  *                    step; the environment variable LQ_LOG_LEVEL sets a floor;
- *   "rhs_per_thread" 1|2|4  how the hopping kernel shares links between
- *                    right-hand sides applied together: 1 (default) one per
- *                    thread, the right-hand sides of one site block in
+ *   "rhs_per_thread" 0|1|2|4  how the hopping kernel shares links between
+ *                    right-hand sides applied together (0, the default:
+ *                    automatic, 4 in FP32 with at least 4 right-hand sides,
+ *                    else 1): 1 one per thread, the right-hand sides of one site block in
  *                    adjacent workgroups sharing the links through the L2;
  *                    2 two per thread (each loaded link used for both; not
  *                    with the fused dot products, where 1 is used); 4 four

@@ -510,16 +510,17 @@ lq_status lq_op_set_option(lq_op *op, const char *name, int value)
 {
     if (!op || !name) return arg_error("lq_op_set_option: null argument");
     const std::string n(name);
-    const bool order_ok = value >= 0 && value <= 2;
+    const bool order_ok = value >= -1 && value <= 2;  // -1: automatic
+    const bool nr_ok = value == 0 || value == 1 || value == 2 || value == 4;  // 0: automatic
     if (n == "xcd_remap" && order_ok) op->xcd_remap[0] = op->xcd_remap[1] = op->xcd_remap[2] = value;
     else if (n == "xcd_remap_f64" && order_ok) op->xcd_remap[F64] = value;
     else if (n == "xcd_remap_f32" && order_ok) op->xcd_remap[F32] = value;
     else if (n == "xcd_remap_f16" && order_ok) op->xcd_remap[F16] = value;
-    else if (n == "rhs_per_thread" && (value == 1 || value == 2 || value == 4))
+    else if (n == "rhs_per_thread" && nr_ok)
         op->rhs_per_thread[0] = op->rhs_per_thread[1] = op->rhs_per_thread[2] = value;
-    else if (n == "rhs_per_thread_f64" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F64] = value;
-    else if (n == "rhs_per_thread_f32" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F32] = value;
-    else if (n == "rhs_per_thread_f16" && (value == 1 || value == 2 || value == 4)) op->rhs_per_thread[F16] = value;
+    else if (n == "rhs_per_thread_f64" && nr_ok) op->rhs_per_thread[F64] = value;
+    else if (n == "rhs_per_thread_f32" && nr_ok) op->rhs_per_thread[F32] = value;
+    else if (n == "rhs_per_thread_f16" && nr_ok) op->rhs_per_thread[F16] = value;
     else if (n == "graphs" && (value == 0 || value == 1)) op->use_graphs = value;
     else if (n == "halo" && (value == 0 || value == 1)) op->halo[0] = op->halo[1] = op->halo[2] = value;
     else if (n == "halo_f16" && (value == 0 || value == 1)) op->halo[F16] = value;

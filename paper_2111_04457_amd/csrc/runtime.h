@@ -62,12 +62,12 @@ struct lq_op {
     bool even_inverted = false;          // A_ee^-1 computed for the current gauge field
     int hop_block[3] = {64, 64, 64};     // workgroup size of the hop kernel per precision
     // workgroup order of the hop kernel per precision: 0 plain, 1 XCD-aware,
-    // 2 XCD-aware and time slices interleaved
-    int xcd_remap[3] = {0, 0, 0};
+    // 2 XCD-aware and time slices interleaved; -1 automatic (eff_remap)
+    int xcd_remap[3] = {-1, -1, -1};
     int tune_form = 0;                   // operator form lq_tune times: 0 M, 1 A_ee^-1 M
     int break_at = 0;                    // > 0: the next solve's first inner BiCGStab breaks down here
     int log_level = 0;                   // progress lines of solves on stderr (also $LQ_LOG_LEVEL)
-    int rhs_per_thread[3] = {1, 1, 1};   // right-hand sides per thread of the hop kernel (nrhs > 1)
+    int rhs_per_thread[3] = {0, 0, 0};   // right-hand sides per thread of the hop kernel (nrhs > 1); 0 automatic
     int halo[3] = {0, 0, 0};             // 1: neighbour spinors staged in LDS (binary16, one rhs, if a tile fits)
     int inner_hint = 0;                  // iterations the last inner solve needed (first chunk length)
     lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
@@ -215,6 +215,14 @@ void apply_temp_bytes(lq_kind kind, int prec, const Geom &g, int nrhs, size_t &t
 void clover_apply(lq_op *op, int prec, int p, bool inv, const FieldView &out, const FieldView &in, hipStream_t s);
 
 bool kind_is_full(lq_kind k);
+
+// The launch settings in effect for nrhs right-hand sides of precision prec:
+// the option's value, or, automatic (-1 / 0), plain order for one right-hand
+// side and XCD-aware order with the time slices interleaved for several;
+// four right-hand sides per workgroup in FP32 with at least four, else one
+// per thread (the measured best untuned shapes on 24^3 x 48 and 32^3 x 64).
+int eff_remap(const lq_op *op, int prec, int nrhs);
+int eff_nr(const lq_op *op, int prec, int nrhs);
 
 // Progress output level of solves: the larger of $LQ_LOG_LEVEL (read once)
 // and the operator's "log_level" option.

@@ -130,9 +130,10 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         LQ_HIP(launch_hop_halo(a, tile, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, s));
         return;
     }
-    a.xcd_remap = op->xcd_remap[prec] != 0 ? 1 : 0;
+    const int remap = eff_remap(op, prec, in.nrhs);
+    a.xcd_remap = remap != 0 ? 1 : 0;
     const int block = op->hop_block[prec];
-    if (op->xcd_remap[prec] == 2) {
+    if (remap == 2) {
         const long slice = (long)g.L[0] * g.L[1] * g.L[2] / 2;  // sites of one parity per time slice
         if (slice % block == 0) {
             a.slice_tiles = (int)(slice / block);
@@ -143,11 +144,23 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)
     int nr = 1;
     if (in.nrhs > 1 && !(clov_mode & kTwist)) {
-        const int want = op->rhs_per_thread[prec];
+        const int want = eff_nr(op, prec, in.nrhs);
         if (want == 2 && red == 0) nr = 2;
         else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;
     }
     LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, nr, block, s));
+}
+
+int eff_remap(const lq_op *op, int prec, int nrhs)
+{
+    const int v = op->xcd_remap[prec];
+    return v >= 0 ? v : (nrhs > 1 ? 2 : 0);
+}
+
+int eff_nr(const lq_op *op, int prec, int nrhs)
+{
+    const int v = op->rhs_per_thread[prec];
+    return v > 0 ? v : (prec == F32 && nrhs >= 4 ? 4 : 1);
 }
 
 void set_hop_mask(HopArgs &a, const double *sc)

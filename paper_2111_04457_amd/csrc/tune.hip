@@ -193,7 +193,9 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 double best_us = 1e30, default_us = 1e30;
                 bool first = true;
                 std::vector<char> ref_host(b), cur_host(b);
-                const int def_nr = nrhs > 1 && (save_nr == 1 || save_nr == 4) ? save_nr : 1;
+                // the shape in effect before tuning (automatic settings resolved)
+                const int def_nr = nrhs > 1 ? eff_nr(op, prec, nrhs) : 1;
+                const int def_remap = eff_remap(op, prec, nrhs);
                 // candidates (right-hand sides per thread, workgroup size, order,
                 // LDS staging of the neighbours); two right-hand sides per thread
                 // are not swept: they cannot carry the fused reductions and need
@@ -248,7 +250,8 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         best.nr = cd.nr;
                         best.halo = cd.halo;
                     }
-                    if (cd.nr == def_nr && cd.block == save_block && cd.remap == save_remap && cd.halo == save_halo)
+                    if ((cd.nr == def_nr || (def_nr == 2 && cd.nr == 1)) && cd.block == save_block &&
+                        cd.remap == def_remap && cd.halo == save_halo)
                         default_us = us;
                 }
                 // the shape the operator had unless another is faster by more
@@ -256,8 +259,8 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 if (default_us <= 1.02 * best_us) {
                     best_us = default_us;
                     best.block = save_block;
-                    best.xcd = save_remap;
-                    best.nr = def_nr;
+                    best.xcd = def_remap;
+                    best.nr = def_nr == 2 ? 1 : def_nr;
                     best.halo = save_halo;
                 }
                 best.us = best_us;
