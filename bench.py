@@ -409,6 +409,26 @@ def _profile(lq, torch, args):
     from lattice_inputs import (ANTIPERIODIC_T, RAGGED_DIMS, WORKLOADS, gaussian_spinor, point_sources,
                                 workload_gauge, workload_source)
     out = {}
+    if args.profile == "mg":
+        from lattice_inputs import gauge_exp
+        d, kappa = (16, 16, 16, 32), 0.1248
+        op = lq.Operator(d, kappa, 0.0, ANTIPERIODIC_T, link_recon=12)
+        op.set_gauge(torch.from_numpy(gauge_exp(d, 0.1, 4242)).cuda())
+        b = torch.from_numpy(gaussian_spinor(d, 4243)).cuda()
+        mg, setup_ms = _timed(torch, lambda: lq.Multigrid(op, torch.from_numpy(gaussian_spinor(d, 4244, 12)).cuda(),
+                                                          lq.MGParams()))
+        prm = lq.SolverParams(tol=1e-10, inner_tol=1e-5)
+        for _ in range(args.warmup):
+            mg.solve(b, prm)
+        times = []
+        for _ in range(args.steps):
+            (_, st), ms = _timed(torch, lambda: mg.solve(b, prm))
+            times.append(ms)
+        out = {"workload": "wilson_16x16x16x32_k1248", "setup_ms": setup_ms, "solve_ms": times, "gcr_iters": st.nconv,
+               "diff": st.diff}
+        mg.close()
+        op.close()
+        return out
     if args.profile in ("schur_f16", "schur12_f16", "solve"):
         name = args.workload if args.profile != "schur12_f16" else "clover_24x24x24x48"
         w = WORKLOADS[name]
@@ -510,11 +530,12 @@ def main(argv=None):
                     help="only the eigensolver measurement; prints its JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
-    ap.add_argument("--profile", choices=["schur_f16", "schur12_f16", "solve", "ragged"], default=None,
+    ap.add_argument("--profile", choices=["schur_f16", "schur12_f16", "solve", "ragged", "mg"], default=None,
                     help="run one workload alone for a profiler: schur_f16 the roofline kernel pair on the "
                          "workload (kernel-reps graph-replayed applies), schur12_f16 the same operator with the "
                          "12 point sources of 24^3x48, solve the timed mixed solve (warmup + steps solves), ragged "
-                         "the ragged batch solve and its lattices' separate solves; prints its timings as JSON")
+                         "the ragged batch solve and its lattices' separate solves, mg the multigrid solve of the "
+                         "near-critical 16^3x32 Wilson lattice (warmup + steps solves); prints its timings as JSON")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
