@@ -51,11 +51,15 @@ def _h(T):
     return T.conj().transpose(-1, -2)
 
 
-def _site_blocks(U, dims, kappa, csw, traceless):
-    """Diagonal blocks A(x) = 1 + F(x), [Lt, Lz, Ly, Lx, 12, 12]."""
+def _site_blocks(U, dims, kappa, csw, traceless, twist=0.0):
+    """Diagonal blocks A(x) = 1 + F(x) (+ i twist gamma_5, the twisted-mass
+    term, which does not depend on the links), [Lt, Lz, Ly, Lx, 12, 12]."""
     g = _gammas()
     shape = U.shape[:4]
     A = torch.eye(12, dtype=torch.complex128).expand(*shape, 12, 12).clone()
+    if twist != 0.0:
+        g5 = torch.from_numpy(np.kron(np.diag([1.0, 1.0, -1.0, -1.0]), np.eye(3)).astype(np.complex128))
+        A = A + 1j * float(twist) * g5
     if csw == 0.0:
         return A
     Um = [U[..., mu, :, :] for mu in range(4)]
@@ -79,9 +83,10 @@ def _site_blocks(U, dims, kappa, csw, traceless):
     return A
 
 
-def dense_dirac_torch(U, dims, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True):
+def dense_dirac_torch(U, dims, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True, twist=0.0):
     """The N x N matrix D = A - kappa H of eq. (1) as a differentiable torch
-    tensor (index 12 * lex + 3 * spin + colour)."""
+    tensor (index 12 * lex + 3 * spin + colour); twist != 0 adds
+    i twist gamma_5 on every site."""
     dims = tuple(int(v) for v in dims)
     lx, ly, lz, lt = dims
     V = lx * ly * lz * lt
@@ -102,7 +107,7 @@ def dense_dirac_torch(U, dims, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True):
         cols_all.append(c.reshape(-1))
         vals_all.append(blocks.reshape(-1))
 
-    A = _site_blocks(U, dims, kappa, csw, traceless)
+    A = _site_blocks(U, dims, kappa, csw, traceless, twist)
     add(lex, lex, A)
     for mu in range(4):
         L = dims[mu]
@@ -121,8 +126,8 @@ def dense_dirac_torch(U, dims, kappa, csw=0.0, bc=(1, 1, 1, 1), traceless=True):
     return D.index_put((torch.cat(rows_all), torch.cat(cols_all)), torch.cat(vals_all), accumulate=True)
 
 
-def _action(U, dims, kappa, csw, bc, traceless, phi, variant):
-    D = dense_dirac_torch(U, dims, kappa, csw, bc, traceless)
+def _action(U, dims, kappa, csw, bc, traceless, phi, variant, twist=0.0):
+    D = dense_dirac_torch(U, dims, kappa, csw, bc, traceless, twist)
     if variant == "eo":
         ie = torch.from_numpy(_dense.parity_index(dims, 0))
         io = torch.from_numpy(_dense.parity_index(dims, 1))
@@ -135,7 +140,7 @@ def _action(U, dims, kappa, csw, bc, traceless, phi, variant):
     return (y.conj() * y).real.sum()
 
 
-def pf_force_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True):
+def pf_force_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True, twist=0.0):
     """(S, Mraw, G) for the even-odd ("eo", phi a parity field [V/2, 4, 3] on
     the even sites) or full-lattice ("full", phi [.., 4, 3] over all sites)
     action.  Mraw[t, z, y, x, mu] is the matrix with dS = sum Re tr(Mraw dU);
@@ -144,7 +149,7 @@ def pf_force_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True):
     dims = tuple(int(v) for v in dims)
     Ut = torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).clone().requires_grad_(True)
     ph = torch.from_numpy(np.ascontiguousarray(phi, dtype=np.complex128)).reshape(-1)
-    S = _action(Ut, dims, float(kappa), float(csw), bc, traceless, ph, variant)
+    S = _action(Ut, dims, float(kappa), float(csw), bc, traceless, ph, variant, twist)
     S.backward()
     # torch returns, for a real function of complex inputs, the gradient g
     # with dS = Re sum conj(g) dU (the conjugate Wirtinger derivative times 2);
@@ -155,13 +160,13 @@ def pf_force_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True):
     return float(S.detach()), Mraw, G
 
 
-def pf_action_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True):
+def pf_action_clover(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True, twist=0.0):
     """The action alone (no gradient)."""
     dims = tuple(int(v) for v in dims)
     with torch.no_grad():
         Ut = torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128))
         ph = torch.from_numpy(np.ascontiguousarray(phi, dtype=np.complex128)).reshape(-1)
-        return float(_action(Ut, dims, float(kappa), float(csw), bc, traceless, ph, variant))
+        return float(_action(Ut, dims, float(kappa), float(csw), bc, traceless, ph, variant, twist))
 
 
 def _hop_torch(U, psi, bc):
@@ -192,11 +197,12 @@ def _block_apply(A, psi):
     return torch.einsum("...ij,...j->...i", A, psi.reshape(*shape[:4], 12)).reshape(shape)
 
 
-def pf_force_clover_mf(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True, tol=1e-13):
+def pf_force_clover_mf(dims, U, kappa, csw, bc, phi, variant="eo", traceless=True, tol=1e-13, twist=0.0):
     """pf_force_clover without dense matrices: (S, Mraw, G) for the even-odd
-    or full-lattice clover (or, at c_sw = 0, Wilson) action."""
+    or full-lattice clover (or, at c_sw = 0, Wilson; with twist, twisted-mass)
+    action."""
     dims = tuple(int(v) for v in dims)
-    op = Operator(dims, U, kappa, csw, bc, traceless)
+    op = Operator(dims, U, kappa, csw, bc, traceless, twist=twist)
     if variant == "eo":
         X, _ = cg(op.schur_normal, np.ascontiguousarray(phi, dtype=np.complex128), tol)
         Y = op.schur(X)
@@ -208,7 +214,7 @@ def pf_force_clover_mf(dims, U, kappa, csw, bc, phi, variant="eo", traceless=Tru
     S = float(np.vdot(np.asarray(phi).reshape(-1), X.reshape(-1)).real)
     Ut = torch.from_numpy(np.ascontiguousarray(U, dtype=np.complex128)).clone().requires_grad_(True)
     Xt, Yt = torch.from_numpy(Xf), torch.from_numpy(Yf)
-    A = _site_blocks(Ut, dims, float(kappa), float(csw), traceless)
+    A = _site_blocks(Ut, dims, float(kappa), float(csw), traceless, twist)
     if variant == "eo":
         # M X = A_ee X - kappa^2 H_eo A_oo^-1 H_oe X with X on the even sites
         odd = torch.from_numpy(np.ascontiguousarray(_parity_mask(dims)))

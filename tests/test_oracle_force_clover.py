@@ -124,3 +124,29 @@ def test_matrix_free_reduces_to_wilson():
     Sw, Mw, Gw = oracle.pf_force_eo(ref, phi, tol=1e-13)
     assert abs(S - Sw) < 1e-11 * abs(Sw)
     assert np.linalg.norm(M - Mw) / np.linalg.norm(Mw) < 1e-10
+
+
+@pytest.mark.parametrize("variant", ["eo", "full"])
+def test_twisted_mass_force_matches_finite_differences(variant):
+    """Twisted mass (A = 1 + i tau gamma_5, no clover): the autograd force
+    of the dense action against central finite differences, and the
+    matrix-free force against the dense one; the twist term does not depend
+    on the links, so the force changes with tau only through X and Y."""
+    dims = (4, 4, 4, 4)
+    kappa, tau = 0.125, 0.3
+    U = gauge_exp(dims, 0.4, 191)
+    phi = gaussian_parity_spinor(dims, 192) if variant == "eo" else gaussian_spinor(dims, 192)
+    S, M, G = fc.pf_force_clover(dims, U, kappa, 0.0, BC, phi, variant, twist=tau)
+    X = random_su3_algebra(dims, 193)
+    eps = 1e-5
+    Sp = fc.pf_action_clover(dims, _expm_ah(eps * X) @ U, kappa, 0.0, BC, phi, variant, twist=tau)
+    Sm = fc.pf_action_clover(dims, _expm_ah(-eps * X) @ U, kappa, 0.0, BC, phi, variant, twist=tau)
+    fd = (Sp - Sm) / (2 * eps)
+    pred = float(np.sum(np.real(np.conj(G) * X)))
+    assert abs(fd - pred) < 1e-7 * max(1.0, abs(pred))
+    S2, M2, G2 = fc.pf_force_clover_mf(dims, U, kappa, 0.0, BC, phi, variant, twist=tau)
+    assert abs(S - S2) < 1e-12 * abs(S)
+    assert np.linalg.norm(G - G2) / np.linalg.norm(G) < 1e-11
+    # the twist changes the action and the force
+    S0, _, G0 = fc.pf_force_clover(dims, U, kappa, 0.0, BC, phi, variant)
+    assert abs(S0 - S) > 1e-3 * abs(S) and np.linalg.norm(G - G0) > 1e-3 * np.linalg.norm(G)
