@@ -126,10 +126,10 @@ typedef struct {
                              conj(row0 x row1), valid for SU(3) links only) */
     double twist;         /* twisted-mass Wilson operator D = 1 - kappa H + i twist gamma_5
                              (twist = 2 kappa mu for a twisted mass mu); 0 (default): none.
-                             Finite; not with the clover term (csw must be 0).  Twisted
-                             operators solve the modes LQ_D only (D^dag of a twisted
-                             operator is gamma_5 D(-twist) gamma_5), and have no force or
-                             molecular-dynamics calls */
+                             Finite; not with the clover term (csw must be 0).  D^dag of a
+                             twisted operator is gamma_5 D(-twist) gamma_5: the modes
+                             LQ_DDAG and LQ_DDAGD solve with the sign of twist flipped
+                             for the duration of the call (deflate = 1 needs LQ_D) */
 } lq_op_params;
 
 /* Solver parameters (params_solver of Fig. 1). */
@@ -344,7 +344,7 @@ lq_status lq_op_traffic(const lq_op *op, lq_prec prec, int nrhs, int clover, dou
                         double *flops_per_site);
 
 /* LQ_DDAGD solves D^dag y = b to tol / 2, then D x = y to tol |b| / (2 |D| |y|)
- * (|D| bounded by 1 + 16 kappa + 12 |c_sw| kappa), so that the normal residual
+ * (|D| bounded by 1 + |twist| + 16 kappa + 12 |c_sw| kappa), so that the normal residual
  * |b - D^dag D x| / |b| reported in diff meets tol; it starts from zero
  * (use_x0 = 1 is LQ_ERR_ARG). */
 /* Solve op x = b for mode LQ_D, LQ_DDAG or LQ_DDAGD (invert of Fig. 1) for
@@ -411,9 +411,10 @@ lq_status lq_bandwidth_probe(int mode, void *dst, const void *src, size_t bytes,
  *   variant 0 (even-odd):  S = phi^dag (M^dag M)^-1 phi,  M = A_ee - kappa^2 H_eo A_oo^-1 H_oe,
  *                          phi a device complex128 parity field [V/2][4][3] on even sites;
  *   variant 1 (full):      S = phi^dag (D^dag D)^-1 phi,  phi a full field [V][4][3].
- * Wilson (csw = 0, A = 1) and Wilson-clover operators (eq. (1)); the clover
- * term enters through the derivative of its leaves Q_{mu nu}(x), traceless or
- * not as the operator was built.
+ * Wilson (csw = 0, A = 1), Wilson-clover operators (eq. (1)) and twisted-mass
+ * Wilson operators (A = 1 + i twist gamma_5, independent of the links: only
+ * the inverses change); the clover term enters through the derivative of its
+ * leaves Q_{mu nu}(x), traceless or not as the operator was built.
  * The solve runs with sp (FP64 defect correction around sp->inner); the
  * hopping-term force kernel computes in force_prec (LQ_F64 or LQ_F32), the
  * clover part always in FP64 (on the FP64 solution).  Outputs (device
@@ -578,7 +579,7 @@ lq_status lq_mg_coarse_apply(lq_mg *mg, const void *x, void *y, void *stream);
  * Monte Carlo with the Wilson plaquette gauge action
  *   S_g = beta sum_x sum_{mu<nu} (1 - Re tr P_{mu nu}(x) / 3)
  * and the even-odd pseudofermion action of lq_pf_force (variant 0, the
- * operator's kappa, csw and boundary phases).  Momenta P_mu(x) are traceless
+ * operator's kappa, csw, twist and boundary phases).  Momenta P_mu(x) are traceless
  * anti-Hermitian, H = 1/2 sum tr(P^dag P) + S_g + S_f, and the equations of
  * motion dU/dt = P U, dP/dt = -G (G the su(3) force, -TA(U M) as for
  * lq_pf_force) are integrated with U <- exp(e P) U (FP64).

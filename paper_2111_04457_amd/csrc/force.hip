@@ -400,10 +400,6 @@ lq_status pf_force_guess(lq_op *op, const lq_solver_params *sp, int variant, lq_
         set_error("lq_pf_force: invalid solver parameters: " + why);
         return LQ_ERR_ARG;
     }
-    if (op->has_twist) {
-        set_error("lq_pf_force: the force of a twisted-mass operator is not provided");
-        return LQ_ERR_ARG;
-    }
     if (sp->deflate && (variant != 0 || op->defl_n == 0)) {
         set_error("lq_pf_force: deflate = 1 needs the even-odd variant and the operator's deflation space");
         return LQ_ERR_STATE;

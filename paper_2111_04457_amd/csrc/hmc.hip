@@ -339,10 +339,6 @@ extern "C" lq_status lq_md_trajectory(lq_op *op, const lq_md_params *mp, const l
         set_error("lq_md_trajectory: force precision must be LQ_F64 or LQ_F32");
         return LQ_ERR_ARG;
     }
-    if (mp->fermion && op->has_twist) {
-        set_error("lq_md_trajectory: the pseudofermion force of a twisted-mass operator is not provided");
-        return LQ_ERR_ARG;
-    }
     try {
         set_error("");
         LQ_HIP(hipSetDevice(op->device));

@@ -859,10 +859,6 @@ lq_status lq_mg_create(lq_op *op, const lq_mg_params *p, const void *v0, lq_mg *
         set_error("lq_mg_create: gauge field not set");
         return LQ_ERR_STATE;
     }
-    if (op->has_twist) {
-        set_error("lq_mg_create: the multigrid is provided for the Wilson and Wilson-clover operators");
-        return LQ_ERR_ARG;
-    }
     lq_mg *mg = new lq_mg;
     try {
         set_error("");

@@ -2,6 +2,7 @@
 // solvers, shared by the propagator solve and the pseudofermion force.
 #pragma once
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,16 @@ struct lq_batch {
 };
 
 namespace lq {
+
+// The bits of the twisted mass, for the graph keys (the hop kernels take the
+// twist factor as an argument captured into the graph).
+inline long twist_key(double t)
+{
+    long k;
+    static_assert(sizeof(k) == sizeof(t), "64-bit long");
+    std::memcpy(&k, &t, sizeof(k));
+    return k;
+}
 
 // Solver context: nsys systems on the solve space (even sites for the
 // even-odd Schur system, or the full lattice), workspace and scalars; of one
@@ -175,7 +186,7 @@ template <typename Body> void SolveCtx::run_chunk(int kind, int chunk, Body body
                            (long)op->hop_block[0], (long)op->hop_block[1], (long)op->hop_block[2],
                            (long)op->xcd_remap[0], (long)op->xcd_remap[1], (long)op->xcd_remap[2],
                            (long)op->rhs_per_thread[0], (long)op->rhs_per_thread[1], (long)op->rhs_per_thread[2],
-                           (long)op->halo[2]};
+                           (long)op->halo[2], twist_key(op->prm.twist)};
         key.insert(key.end(), k2, k2 + sizeof(k2) / sizeof(k2[0]));
     }
     std::vector<lq_op::GraphEntry> &graphs = bt ? bt->graphs : op->graphs;

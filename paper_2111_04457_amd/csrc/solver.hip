@@ -789,6 +789,18 @@ extern "C" lq_status lq_solve_host(lq_op *op, const lq_solver_params *sp, lq_kin
     }
 }
 
+// While in scope, the operator's twisted mass has the opposite sign: a
+// twisted-mass operator's D^dag is gamma_5 D(-tau) gamma_5.  The hop kernels
+// take the twist factor as an argument, and the captured solver graphs key
+// on its value, so nothing else needs rebuilding.
+struct TwistFlip {
+    lq_op *op;
+    explicit TwistFlip(lq_op *o) : op(o) { op->prm.twist = -op->prm.twist; }
+    ~TwistFlip() { op->prm.twist = -op->prm.twist; }
+    TwistFlip(const TwistFlip &) = delete;
+    TwistFlip &operator=(const TwistFlip &) = delete;
+};
+
 static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mode, int nrhs, void *x, const void *b,
                               int use_x0, lq_solve_stats *stats, void *stream)
 {
@@ -806,8 +818,9 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
                   std::to_string(nrhs) + " requested");
         return LQ_ERR_ARG;
     }
-    if (op->has_twist && mode != LQ_D) {
-        set_error("lq_solve: a twisted-mass operator solves LQ_D only (its D^dag is gamma_5 D(-twist) gamma_5)");
+    if (op->has_twist && mode != LQ_D && sp->deflate) {
+        set_error("lq_solve: deflate = 1 with a twisted-mass operator needs mode LQ_D (the deflation space belongs "
+                  "to the Schur operator of +twist, the dagger modes solve with -twist)");
         return LQ_ERR_ARG;
     }
     if (mode == LQ_DDAGD && use_x0) {
@@ -849,10 +862,14 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
         if (mode == LQ_D) {
             st = solve_packed(op, *sp, nrhs, xp, bp, use_x0, stats, s);
         } else if (mode == LQ_DDAG) {
-            // D^dag = gamma_5 D gamma_5: x = gamma_5 D^-1 gamma_5 b
+            // D^dag = gamma_5 D gamma_5: x = gamma_5 D^-1 gamma_5 b (twisted
+            // mass: D(tau)^dag = gamma_5 D(-tau) gamma_5)
             LQ_HIP(launch_gamma5(bfull, s));
             if (use_x0) LQ_HIP(launch_gamma5(xfull, s));
-            st = solve_packed(op, *sp, nrhs, xp, bp, use_x0, stats, s);
+            {
+                const TwistFlip flip(op);
+                st = solve_packed(op, *sp, nrhs, xp, bp, use_x0, stats, s);
+            }
             LQ_HIP(launch_gamma5(xfull, s));
         } else {
             // D^dag D x = b: y = (D^dag)^-1 b = gamma_5 D^-1 gamma_5 b, then x = D^-1 y.
@@ -864,11 +881,16 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
             // the six terms of F is c_sw kappa gamma_mu gamma_nu (norm 1) times
             // Fhat, whose norm is at most 2 ((Q - Q^dag) / 8 with Q four unitary
             // plaquettes, and at most as much again for the removed trace).
+            // The twisted-mass term i tau gamma_5 adds |tau| to the bound, and
+            // the first solve is with D(-tau).
             std::vector<lq_solve_stats> st1(nrhs);
             LQ_HIP(launch_gamma5(bfull, s));
             lq_solver_params sp1 = *sp;
             sp1.tol = sp->tol * 0.5;
-            st = solve_packed(op, sp1, nrhs, xp, bp, false, st1.data(), s);
+            {
+                const TwistFlip flip(op);
+                st = solve_packed(op, sp1, nrhs, xp, bp, false, st1.data(), s);
+            }
             if (st < 0) return st;
             LQ_HIP(launch_gamma5(xfull, s));  // y
             LQ_HIP(launch_gamma5(bfull, s));  // b restored
@@ -881,7 +903,8 @@ static lq_status solve_device(lq_op *op, const lq_solver_params *sp, lq_kind mod
             c.partial = reinterpret_cast<double *>(op->partial.ptr);
             const std::vector<double> bn2 = norms2(c, bfull, 2);
             const std::vector<double> yn2 = norms2(c, xfull, 2);
-            const double dnorm = 1.0 + std::fabs(op->prm.kappa) * (16.0 + 12.0 * std::fabs(op->prm.csw));
+            const double dnorm =
+                1.0 + std::fabs(op->prm.twist) + std::fabs(op->prm.kappa) * (16.0 + 12.0 * std::fabs(op->prm.csw));
             lq_solver_params sp2 = *sp;
             sp2.tol = 0.5 * sp->tol;
             for (int i = 0; i < nrhs; ++i)

@@ -3,14 +3,18 @@ HIP library against the oracle: every operator kind element by element in
 FP64 / FP32 / FP16 storage (tolerances as for the Wilson and clover
 operators: 1e-12, 1e-5, 5e-3), and mixed-precision solves of D x = b
 (BiCGStab on M and on the A_ee^-1-preconditioned system, CG on M^dag M)
-reaching the oracle's true residual and the oracle's solution; a ragged
-batch of twisted operators equals the separate solves bit for bit.
+reaching the oracle's true residual and the oracle's solution; the dagger
+modes (D^dag = gamma_5 D(-tau) gamma_5) against the oracle's D^dag and
+D^dag D; a ragged batch of twisted operators equals the separate solves bit
+for bit; the pseudofermion action and force against the oracle's gradient of
+the dense action; a twisted molecular-dynamics trajectory that is reversible
+and second order in the step.
 """
 import numpy as np
 import pytest
 
 import oracle
-from lattice_inputs import gauge_exp, gauge_haar, gaussian_parity_spinor, gaussian_spinor
+from lattice_inputs import gauge_exp, gauge_haar, gaussian_parity_spinor, gaussian_spinor, random_su3_algebra
 from tests.gpu_common import announce, have_gpu, rel_err, to_dev, to_host
 from tests.test_gpu_apply import KINDS, TOL, _reference
 
@@ -71,10 +75,107 @@ def test_twisted_solves_against_oracle(lq, case, solver, inner, left):
                  % (solver, inner, left, st[r].nconv, res, rel_err(x[r], xr)))
         assert st[r].converged and res <= 1.01e-10
         assert rel_err(x[r], xr) < 50 * 1e-10
-    # the other modes are refused for a twisted operator
-    with pytest.raises(lq.LQError, match="twisted"):
-        op.solve(to_dev(b[0]), "Ddag", prm)
     op.close()
+
+
+@pytest.mark.parametrize("mode", ["Ddag", "DdagD"])
+def test_twisted_dagger_modes_against_oracle(lq, case, mode):
+    """D^dag = gamma_5 D(-tau) gamma_5: the dagger modes solve with the sign
+    of the twist flipped for the call; the operator keeps +tau afterwards
+    (an LQ_D solve after them equals one before, bit for bit)."""
+    U, ref = case
+    announce("twisted mode %s" % mode)
+    b = gaussian_spinor(DIMS, 2621, 2)
+    op = lq.Operator(DIMS, KAPPA, 0.0, BC, link_recon=12, twist=TAU)
+    op.set_gauge(to_dev(U))
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3)
+    xd0, _ = op.solve(to_dev(b), "D", prm)
+    x, st = op.solve(to_dev(b), mode, prm)
+    x = to_host(x)
+    apply = ref.Ddag if mode == "Ddag" else ref.DdagD
+    for r in range(2):
+        res = np.linalg.norm(apply(x[r]) - b[r]) / np.linalg.norm(b[r])
+        announce("  rhs %d: iters %d outer %d oracle residual %.2e" % (r, st[r].nconv, st[r].nouter, res))
+        assert st[r].converged and res <= 1.01e-10
+    # the Hermitian-conjugate solve is not the plain one
+    assert rel_err(x[0], to_host(xd0)[0]) > 1e-3
+    xd1, _ = op.solve(to_dev(b), "D", prm)
+    assert np.array_equal(to_host(xd0), to_host(xd1))
+    # deflation belongs to +tau: refused in the dagger modes
+    with pytest.raises(lq.LQError, match="twisted"):
+        op.solve(to_dev(b), mode, lq.SolverParams(tol=1e-10, deflate=True))
+    op.close()
+
+
+_FREF = {}
+
+
+def _force_reference(dims, variant, seed):
+    pytest.importorskip("torch")
+    from oracle import force_clover as fc
+    key = (dims, variant, seed)
+    if key not in _FREF:
+        U = gauge_exp(dims, 0.4, seed)
+        phi = gaussian_parity_spinor(dims, seed + 1) if variant == "eo" else gaussian_spinor(dims, seed + 1)
+        S, M, G = fc.pf_force_clover(dims, U, KAPPA, 0.0, BC, phi, variant, twist=TAU)
+        _FREF[key] = (U, phi, S, M, G)
+    return _FREF[key]
+
+
+@pytest.mark.parametrize("dims,variant,prec", [
+    ((4, 4, 4, 4), "eo", "f64"), ((4, 4, 4, 4), "eo", "f32"),
+    ((4, 4, 4, 4), "full", "f64"), ((4, 4, 2, 6), "eo", "f64"),
+])
+def test_twisted_force_matches_oracle(lq, dims, variant, prec):
+    """Pseudofermion action and force of the twisted operator against the
+    oracle's autograd gradient of the dense action (the twist term does not
+    depend on the links; it enters through the inverses).  Tolerances as
+    for the Wilson force: 1e-9 (FP64) and 1e-5 (FP32 force kernel)."""
+    announce("twisted force: dims=%s variant=%s prec=%s" % (dims, variant, prec))
+    U, phi, S_ref, M_ref, G_ref = _force_reference(dims, variant, 3601)
+    op = lq.Operator(dims, KAPPA, 0.0, BC, twist=TAU)
+    op.set_gauge(to_dev(U))
+    prm = lq.SolverParams(solver="cgne", tol=1e-12, inner="f64" if prec == "f64" else "f32")
+    S, grad, G, _, st = lq.pf_force(op, to_dev(phi), prm, variant, prec)
+    grad, G = to_host(grad), to_host(G)
+    want_grad = np.conj(np.swapaxes(M_ref, -1, -2))
+    tol = 1e-9 if prec == "f64" else 1e-5
+    announce("  S %.12e (oracle %.12e) iters %d | grad err %.2e G err %.2e" %
+             (S, S_ref, st.nconv, rel_err(grad, want_grad), rel_err(G, G_ref)))
+    assert st.converged and st.diff <= 1e-12
+    assert abs(S - S_ref) < 1e-10 * abs(S_ref)
+    assert rel_err(grad, want_grad) < tol
+    assert rel_err(G, G_ref) < tol
+    op.close()
+
+
+def test_twisted_trajectory_reversible_and_second_order(lq):
+    """A molecular-dynamics trajectory with the twisted pseudofermion (its
+    force pinned above): flipping P and integrating back recovers the start,
+    and halving the leapfrog step quarters the energy violation."""
+    dims, beta = (8, 8, 8, 8), 5.5
+    announce("twisted trajectory %s" % (dims,))
+    U0 = gauge_exp(dims, 0.3, 3701)
+    P0 = random_su3_algebra(dims, 3702)
+    phi = gaussian_parity_spinor(dims, 3703)
+    prm = lq.SolverParams(solver="cgne", tol=1e-12, inner="f64")
+
+    def run(U, P, n):
+        op = lq.Operator(dims, KAPPA, 0.0, BC, twist=TAU)
+        Ud, Pd = to_dev(U).clone(), to_dev(P).clone()
+        md = lq.MDParams(beta=beta, tau=0.2, nsteps=n, integrator="leapfrog", fermion=True)
+        st = lq.md_trajectory(op, Ud, Pd, to_dev(phi), md, prm)
+        op.close()
+        return to_host(Ud), to_host(Pd), st
+
+    U1, P1, st = run(U0, P0, 8)
+    U2, P2, _ = run(U1, -P1, 8)
+    announce("  back: U err %.2e P err %.2e; Sf0 %.6e" % (rel_err(U2, U0), rel_err(P2, -P0), st.Sf0))
+    assert st.converged
+    assert rel_err(U2, U0) < 1e-10 and rel_err(P2, -P0) < 1e-10
+    dh8, dh16 = st.dH, run(U0, P0, 16)[2].dH
+    announce("  dH %.4e (8 steps) %.4e (16 steps)" % (dh8, dh16))
+    assert 3.5 < abs(dh8 / dh16) < 4.5
 
 
 def test_twisted_batch_and_argument_checks(lq):

@@ -12,6 +12,10 @@ fixes:
   gamma_5);
 - the matrix-free block columns equal the dense P^dag D P (dense D entry by
   entry from eq. (1), oracle/dense.py);
+- twisted mass: P^dag (D + i tau gamma_5) P = P^dag D P + i tau Gamma_5
+  (P^dag P = 1 and gamma_5 P = P Gamma_5), the twisted coarse operator
+  satisfies Gamma_5 D_c(tau) Gamma_5 = D_c(-tau)^dag, and its matrix-free
+  columns (oracle Operator with the twist) equal the dense ones;
 - free field (unit links, periodic), block-constant vectors e_{s,c}: the
   coarse operator in closed form -- on the aggregate itself
   1 - 2 kappa sum_mu (1 - 1/b_mu), to the aggregate at -mu (it couples
@@ -119,3 +123,24 @@ def test_free_field_coarse_operator_closed_form():
         assert np.allclose(cols[B], want, atol=1e-13), B
     # the x direction (coarse extent 4) separates the two sides
     assert mg.neighbour(cdims, A0, 1) != mg.neighbour(cdims, A0, 2)
+
+
+def test_twisted_galerkin_adds_i_tau_gamma5():
+    dims, block, nv = (4, 4, 4, 4), (2, 2, 2, 2), 2
+    kappa, tau = 0.125, 0.3
+    U = gauge_exp(dims, 0.5, 9251)
+    W = mg.block_orthonormalize(dims, block, gaussian_spinor(dims, 9252, nv))
+    P = mg.prolongator(dims, block, W)
+    Dc0 = mg.galerkin(dense_dirac(dims, U, kappa, 0.0, BC), P)
+    Dcp = mg.galerkin(dense_dirac(dims, U, kappa, 0.0, BC, twist=tau), P)
+    Dcm = mg.galerkin(dense_dirac(dims, U, kappa, 0.0, BC, twist=-tau), P)
+    nagg = P.shape[1] // (2 * nv)
+    G5c = np.kron(np.eye(nagg), np.diag([1.0] * nv + [-1.0] * nv))
+    assert np.allclose(Dcp, Dc0 + 1j * tau * G5c, atol=1e-12)
+    assert np.allclose(G5c @ Dcp @ G5c, Dcm.conj().T, atol=1e-12)
+    assert not np.allclose(G5c @ Dcp @ G5c, Dcp.conj().T, atol=1e-3)
+    ref = oracle.Operator(dims, U, kappa, 0.0, BC, twist=tau)
+    cols = mg.coarse_columns(ref.D, dims, block, W, 3)
+    n2 = 2 * nv
+    for B in range(nagg):
+        assert np.allclose(cols[B], Dcp[B * n2:(B + 1) * n2, 3 * n2:4 * n2], atol=1e-12)
