@@ -429,6 +429,29 @@ def _profile(lq, torch, args):
         mg.close()
         op.close()
         return out
+    if args.profile == "propagator":
+        # the 12 spin-colour point sources of one propagator as one solve
+        name = "clover_24x24x24x48"
+        w = WORKLOADS[name]
+        d = w["dims"]
+        op = lq.Operator(d, w["kappa"], w["csw"], ANTIPERIODIC_T, link_recon=args.recon)
+        op.set_gauge(torch.from_numpy(workload_gauge(name)).cuda())
+        if not args.no_tune:
+            op.tune(12, left=args.left_precond)
+        src = torch.from_numpy(point_sources(d)).cuda()
+        inner_tol = args.inner_tol or {"f16": 5e-3, "f32": 1e-5, "f64": 1e-5}[args.inner]
+        prm = lq.SolverParams(tol=args.tol, inner=args.inner, inner_tol=inner_tol, check_every=10,
+                              left_precond=args.left_precond)
+        for _ in range(args.warmup):
+            op.solve(src, "D", prm)
+        times = []
+        for _ in range(args.steps):
+            (_, st), ms = _timed(torch, lambda: op.solve(src, "D", prm))
+            times.append(ms)
+        out = {"workload": name, "nrhs": 12, "inner": args.inner, "solve_ms": times,
+               "iters": [s.nconv for s in st], "outer": [s.nouter for s in st]}
+        op.close()
+        return out
     if args.profile in ("schur_f16", "schur12_f16", "solve"):
         name = args.workload if args.profile != "schur12_f16" else "clover_24x24x24x48"
         w = WORKLOADS[name]
@@ -530,10 +553,12 @@ def main(argv=None):
                     help="only the eigensolver measurement; prints its JSON")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timings (the roofline kernels), no solves; prints their JSON")
-    ap.add_argument("--profile", choices=["schur_f16", "schur12_f16", "solve", "ragged", "mg"], default=None,
+    ap.add_argument("--profile", choices=["schur_f16", "schur12_f16", "solve", "propagator", "ragged", "mg"],
+                    default=None,
                     help="run one workload alone for a profiler: schur_f16 the roofline kernel pair on the "
                          "workload (kernel-reps graph-replayed applies), schur12_f16 the same operator with the "
-                         "12 point sources of 24^3x48, solve the timed mixed solve (warmup + steps solves), ragged "
+                         "12 point sources of 24^3x48, solve the timed mixed solve (warmup + steps solves), propagator "
+                         "the 12-RHS solve of those point sources (warmup + steps solves), ragged "
                          "the ragged batch solve and its lattices' separate solves, mg the multigrid solve of the "
                          "near-critical 16^3x32 Wilson lattice (warmup + steps solves); prints its timings as JSON")
     args = ap.parse_args(argv)

@@ -98,29 +98,37 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
     const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], FWD ? (R)a.g.bc_im[MU] : -(R)a.g.bc_im[MU]};
     if constexpr (PT<P>::scaled) {
         // binary16 storage (the kernels are bound by instruction issue as much
-        // as by memory): every arithmetic operation on a stored value is a
-        // multiply-add, so the conversions fold into mixed-precision
-        // multiply-adds; the spinor's scale is applied in the projection (6
-        // components, not 12), and the boundary phase only where it is not 1.
+        // as by memory): the projection is one packed binary16 add per
+        // complex component of the stored spinor, the colour product two
+        // binary16 dot products per complex multiply-add (FP32 sums), and the
+        // spinor's scale is folded into the reconstruction's multiply-adds;
+        // the boundary phase (a scalar, so it commutes with U) multiplies the
+        // product, only where it is not 1.  The third link row is rebuilt in
+        // FP32 from the converted entries and rounded to binary16.
+        h2 uh[9];
+#pragma unroll
+        for (int i = 0; i < NL / 2; ++i) uh[i] = h2{lnk[(2 * i) * LS], lnk[(2 * i + 1) * LS]};
         if constexpr (NL == 12) {
             u[6] = conj(cdet2(u[1], u[5], u[2], u[4]));
             u[7] = conj(cdet2(u[2], u[3], u[0], u[5]));
             u[8] = conj(cdet2(u[0], u[4], u[1], u[3]));
+#pragma unroll
+            for (int i = 6; i < 9; ++i) uh[i] = h2{(_Float16)u[i].re, (_Float16)u[i].im};
         }
         const bool phase = a.g.bc_re[MU] != 1.0 || a.g.bc_im[MU] != 0.0;  // the same for every thread
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            Spinor<R> ps;
+            h2 ps[12], hh[6], hs[6];
 #pragma unroll
-            for (int i = 0; i < 12; ++i) ps.c[i] = cx<R>{(R)h.sp[r][2 * i], (R)h.sp[r][2 * i + 1]};
-            cx<R> hh[6], o[6];
-            project16<MU, SG>(ps, h.scale[r], hh);
+            for (int i = 0; i < 12; ++i) ps[i] = h2{h.sp[r][2 * i], h.sp[r][2 * i + 1]};
+            cx<R> o[6];
+            project_h2<MU, SG>(ps, hh, hs);
+            su3_mul_h2<!FWD>(uh, hh, hs, o);
             if (phase && h.wrap) {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) hh[i] = ph * hh[i];
+                for (int i = 0; i < 6; ++i) o[i] = ph * o[i];
             }
-            su3_mul16<!FWD>(u, hh, o);
-            reconstruct<MU, SG>(acc[r], o);
+            reconstruct_sc<MU, SG>(acc[r], o, h.scale[r]);
         }
     } else {
         if constexpr (NL == 12) {

@@ -87,16 +87,6 @@ template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re 
 // one mixed-precision multiply-add (v_fma_mix_f32) instead of converting
 // first, which takes a conversion off every binary16 value used.
 __device__ __forceinline__ float mul16(float a, float b) { return __builtin_fmaf(a, b, 0.0f); }
-// a * b (complex) in the same form
-__device__ __forceinline__ cx<float> cmul16(cx<float> a, cx<float> b)
-{
-    return {fmar(a.re, b.re, fmar(-a.im, b.im, 0.0f)), fmar(a.re, b.im, fmar(a.im, b.re, 0.0f))};
-}
-// conj(a) * b in the same form
-__device__ __forceinline__ cx<float> cmulc16(cx<float> a, cx<float> b)
-{
-    return {fmar(a.re, b.re, fmar(a.im, b.im, 0.0f)), fmar(a.re, b.im, fmar(-a.im, b.re, 0.0f))};
-}
 
 // --------------------------------------------------------------- planes --
 

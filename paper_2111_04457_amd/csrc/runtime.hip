@@ -159,8 +159,14 @@ int eff_remap(const lq_op *op, int prec, int nrhs)
 
 int eff_nr(const lq_op *op, int prec, int nrhs)
 {
+    // measured at 24^3 x 48 and 32^3 x 64: four per workgroup from four
+    // right-hand sides on (FP16 and FP32), two per thread for two or three in
+    // FP16 (its dot-product arithmetic leaves the registers for them)
     const int v = op->rhs_per_thread[prec];
-    return v > 0 ? v : (prec == F32 && nrhs >= 4 ? 4 : 1);
+    if (v > 0) return v;
+    if (prec == F64) return 1;
+    if (nrhs >= 4) return 4;
+    return prec == F16 && nrhs >= 2 ? 2 : 1;
 }
 
 void set_hop_mask(HopArgs &a, const double *sc)

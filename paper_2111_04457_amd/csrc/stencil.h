@@ -29,26 +29,117 @@ __device__ __forceinline__ void project(const Spinor<R> &p, cx<R> h[6])
     }
 }
 
-// The same projection of a spinor held as binary16 values (converted, no
-// arithmetic yet) times its FP32 scale sc: h = sc psi_up + s sc B psi_dn,
-// two mixed-precision multiply-adds per real component.
+// ------------------------------------------ binary16 dot-product forms --
+//
+// With binary16 storage the colour products run on two-way dot products of
+// binary16 pairs accumulated in FP32 (each product of two binary16 values is
+// exact in FP32): a complex multiply-add is two dot products instead of
+// four multiply-adds.  The projection is taken in packed binary16 on the
+// stored (per-site normalised, |value| <= 1) spinor, so |h| <= 2; the
+// spinor's scale and the boundary phase are applied to the FP32 products.
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2 swp(h2 a) { return __builtin_shufflevector(a, a, 1, 0); }
+__device__ __forceinline__ h2 neg_hi(h2 a) { return h2{a.x, -a.y}; }
+__device__ __forceinline__ h2 neg_lo(h2 a) { return h2{-a.x, a.y}; }
+
+// a.x b.x + a.y b.y + c and a.x b.x - a.y b.y + c (the sign as an operand
+// modifier of the dot product), with c = 0 taken as an inline constant.
+__device__ __forceinline__ float dot2(h2 a, h2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+__device__ __forceinline__ float dot2_0(h2 a, h2 b)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ float dot2n(h2 a, h2 b, float c)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+__device__ __forceinline__ float dot2n_0(h2 a, h2 b)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+// The projected half spinor h = psi_up + s B psi_dn as (re, im) pairs, and
+// hs = (im, re) (one packed add each; the swaps and negations of B are
+// operand modifiers).
 template <int MU, int SG>
-__device__ __forceinline__ void project16(const Spinor<float> &p, float sc, cx<float> h[6])
+__device__ __forceinline__ void project_h2(const h2 p[12], h2 h[6], h2 hs[6])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        cx<float> b0, b1;
-        const cx<float> d2 = p.c[6 + a], d3 = p.c[9 + a];
-        if constexpr (MU == 0) { b0 = tmi(d3); b1 = tmi(d2); }
-        else if constexpr (MU == 1) { b0 = mk(-d3.re, -d3.im); b1 = d2; }
-        else if constexpr (MU == 2) { b0 = tmi(d2); b1 = ti(d3); }
+        h2 b0, b1;  // (s B psi_dn)_0, (s B psi_dn)_1 as (re, im)
+        const h2 d2 = p[6 + a], d3 = p[9 + a];
+        // -i d = (d.im, -d.re), i d = (-d.im, d.re)
+        if constexpr (MU == 0) { b0 = neg_hi(swp(d3)); b1 = neg_hi(swp(d2)); }
+        else if constexpr (MU == 1) { b0 = -d3; b1 = d2; }
+        else if constexpr (MU == 2) { b0 = neg_hi(swp(d2)); b1 = neg_lo(swp(d3)); }
         else { b0 = d2; b1 = d3; }
-        if constexpr (SG < 0) {
-            b0 = mk(-b0.re, -b0.im);
-            b1 = mk(-b1.re, -b1.im);
+        if constexpr (SG < 0) { b0 = -b0; b1 = -b1; }
+        const h2 u0 = p[a], u1 = p[3 + a];
+        h[a] = u0 + b0;
+        h[3 + a] = u1 + b1;
+        hs[a] = swp(u0) + swp(b0);
+        hs[3 + a] = swp(u1) + swp(b1);
+    }
+}
+
+// o = U h (DAGU = false) or U^dag h for the two spin rows, U as binary16
+// (re, im) pairs.  U h: re = sum Ur hr - Ui hi = <u, h> with the second
+// product negated, im = sum Ur hi + Ui hr = <u, hs>; U^dag h: re = <u, h>,
+// im = sum Ur hi - Ui hr = <u, hs> with the second product negated.
+template <bool DAGU>
+__device__ __forceinline__ void su3_mul_h2(const h2 u[9], const h2 h[6], const h2 hs[6], cx<float> o[6])
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re, im;
+            if constexpr (!DAGU) {
+                re = dot2n_0(u[a * 3], h[s * 3]);
+                im = dot2_0(u[a * 3], hs[s * 3]);
+#pragma unroll
+                for (int b = 1; b < 3; ++b) {
+                    re = dot2n(u[a * 3 + b], h[s * 3 + b], re);
+                    im = dot2(u[a * 3 + b], hs[s * 3 + b], im);
+                }
+            } else {
+                re = dot2_0(u[a], h[s * 3]);
+                im = dot2n_0(u[a], hs[s * 3]);
+#pragma unroll
+                for (int b = 1; b < 3; ++b) {
+                    re = dot2(u[b * 3 + a], h[s * 3 + b], re);
+                    im = dot2n(u[b * 3 + a], hs[s * 3 + b], im);
+                }
+            }
+            o[s * 3 + a] = mk(re, im);
         }
-        h[a] = mk(fmar(b0.re, sc, mul16(p.c[a].re, sc)), fmar(b0.im, sc, mul16(p.c[a].im, sc)));
-        h[3 + a] = mk(fmar(b1.re, sc, mul16(p.c[3 + a].re, sc)), fmar(b1.im, sc, mul16(p.c[3 + a].im, sc)));
+}
+
+// acc += sc (u, s B^dag u): reconstruct with the spinor's scale folded in.
+template <int MU, int SG>
+__device__ __forceinline__ void reconstruct_sc(cx<float> acc[12], const cx<float> u[6], float sc)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<float> u0 = u[a], u1 = u[3 + a];
+        cx<float> l0, l1;  // (B^dag u)_0, (B^dag u)_1
+        if constexpr (MU == 0) { l0 = ti(u1); l1 = ti(u0); }
+        else if constexpr (MU == 1) { l0 = u1; l1 = mk(-u0.re, -u0.im); }
+        else if constexpr (MU == 2) { l0 = ti(u0); l1 = tmi(u1); }
+        else { l0 = u0; l1 = u1; }
+        if constexpr (SG < 0) { l0 = mk(-l0.re, -l0.im); l1 = mk(-l1.re, -l1.im); }
+        acc[a] = mk(fmar(u0.re, sc, acc[a].re), fmar(u0.im, sc, acc[a].im));
+        acc[3 + a] = mk(fmar(u1.re, sc, acc[3 + a].re), fmar(u1.im, sc, acc[3 + a].im));
+        acc[6 + a] = mk(fmar(l0.re, sc, acc[6 + a].re), fmar(l0.im, sc, acc[6 + a].im));
+        acc[9 + a] = mk(fmar(l1.re, sc, acc[9 + a].re), fmar(l1.im, sc, acc[9 + a].im));
     }
 }
 
@@ -111,30 +202,6 @@ __device__ __forceinline__ void su3_mul(const cx<R> u[9], const cx<R> h[6], cx<R
                 acc = cmac(acc, u[a * 3 + 2], h[s * 3 + 2]);
             } else {
                 acc = cmulc(u[0 * 3 + a], h[s * 3 + 0]);
-                acc = cmacc(acc, u[1 * 3 + a], h[s * 3 + 1]);
-                acc = cmacc(acc, u[2 * 3 + a], h[s * 3 + 2]);
-            }
-            o[s * 3 + a] = acc;
-        }
-}
-
-// su3_mul with binary16 link entries (converted, no arithmetic yet): every
-// product is a multiply-add, so each entry is read by mixed-precision
-// multiply-adds without a conversion of its own.
-template <bool DAGU>
-__device__ __forceinline__ void su3_mul16(const cx<float> u[9], const cx<float> h[6], cx<float> o[6])
-{
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cx<float> acc;
-            if constexpr (!DAGU) {
-                acc = cmul16(u[a * 3 + 0], h[s * 3 + 0]);
-                acc = cmac(acc, u[a * 3 + 1], h[s * 3 + 1]);
-                acc = cmac(acc, u[a * 3 + 2], h[s * 3 + 2]);
-            } else {
-                acc = cmulc16(u[0 * 3 + a], h[s * 3 + 0]);
                 acc = cmacc(acc, u[1 * 3 + a], h[s * 3 + 1]);
                 acc = cmacc(acc, u[2 * 3 + a], h[s * 3 + 2]);
             }

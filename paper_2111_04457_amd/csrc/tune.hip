@@ -8,8 +8,9 @@
 // with the dot products the solver fuses into it (<w, out>, then <w, out>
 // and |out|^2).  Candidates: workgroup sizes {64, 128, 256} x the three
 // workgroup orders (plain, XCD-aware, XCD-aware with time slices
-// interleaved), with several right-hand sides four per workgroup with links
-// and clover blocks staged in LDS (binary16 / FP32), and with one
+// interleaved), with several right-hand sides two per thread (binary16) and
+// four per workgroup with links and clover blocks staged in LDS (binary16 /
+// FP32), and with one
 // right-hand side in binary16 the kernel with the neighbour spinors of a
 // tile staged in LDS (when a tile fits the lattice).  The output of
 // every candidate must be bitwise equal to the first candidate's (each
@@ -198,17 +199,21 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                 const int def_remap = eff_remap(op, prec, nrhs);
                 // candidates (right-hand sides per thread, workgroup size, order,
                 // LDS staging of the neighbours); two right-hand sides per thread
-                // are not swept: they cannot carry the fused reductions and need
-                // twice the registers
+                // (binary16 only: FP32 and FP64 need twice the registers for
+                // them) serve the kernels without fused reductions, the others
+                // run one per thread
                 struct Cand {
                     int nr, block, remap, halo;
                 };
                 std::vector<Cand> cands;
                 for (int block : {256, 128, 64})
                     for (int remap : {2, 1, 0}) cands.push_back({1, block, remap, 0});
-                // four right-hand sides per workgroup (links in LDS): 256 threads, plain or XCD order
+                if (prec == F16 && nrhs >= 2)
+                    for (int block : {128, 64})
+                        for (int remap : {2, 1, 0}) cands.push_back({2, block, remap, 0});
+                // four right-hand sides per workgroup (links in LDS): 256 threads, in each order
                 if (nrhs >= 4 && prec != F64)
-                    for (int remap : {1, 0}) cands.push_back({4, 64, remap, 0});
+                    for (int remap : {2, 1, 0}) cands.push_back({4, 64, remap, 0});
                 HaloTile tile;
                 if (prec == F16 && nrhs == 1 && halo_tile(g, tile)) cands.push_back({1, 64, 0, 1});
                 auto restore = [&]() {
@@ -250,8 +255,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         best.nr = cd.nr;
                         best.halo = cd.halo;
                     }
-                    if ((cd.nr == def_nr || (def_nr == 2 && cd.nr == 1)) && cd.block == save_block &&
-                        cd.remap == def_remap && cd.halo == save_halo)
+                    if (cd.nr == def_nr && cd.block == save_block && cd.remap == def_remap && cd.halo == save_halo)
                         default_us = us;
                 }
                 // the shape the operator had unless another is faster by more
@@ -260,7 +264,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     best_us = default_us;
                     best.block = save_block;
                     best.xcd = def_remap;
-                    best.nr = def_nr == 2 ? 1 : def_nr;
+                    best.nr = def_nr;
                     best.halo = save_halo;
                 }
                 best.us = best_us;
@@ -270,7 +274,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
             op->hop_block[prec] = best.block;
             op->xcd_remap[prec] = best.xcd;
             op->halo[prec] = best.halo;
-            if (nrhs > 1 && (best.nr == 1 || best.nr == 4)) op->rhs_per_thread[prec] = best.nr;
+            if (nrhs > 1) op->rhs_per_thread[prec] = best.nr;
             rep << (prec ? ", " : "") << "\"" << key << "\": {\"block\": " << best.block << ", \"xcd_remap\": " << best.xcd
                 << ", \"rhs_per_thread\": " << op->rhs_per_thread[prec] << ", \"halo\": " << op->halo[prec]
                 << ", \"us\": " << best.us << ", \"cached\": " << (found ? "true" : "false") << "}";

@@ -105,8 +105,9 @@ def test_tuner_times_the_solver_form(lq, inputs, tmp_path):
 
 def test_tuner_multi_rhs_shapes_bitwise(lq, inputs):
     """With several right-hand sides the tuner also sweeps the number of
-    right-hand sides per thread; every shape must give the same bits (the
-    tuner rejects the sweep otherwise), so the output is unchanged."""
+    right-hand sides per thread (two per thread in binary16, four per
+    workgroup in binary16 and FP32); every shape must give the same bits
+    (the tuner rejects the sweep otherwise), so the output is unchanged."""
     U, _ = inputs
     op = lq.Operator(DIMS, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
     op.set_gauge(to_dev(U))
@@ -115,7 +116,7 @@ def test_tuner_multi_rhs_shapes_bitwise(lq, inputs):
     rep = op.tune(5)
     announce("tune(5) report %s" % json.dumps(rep))
     for p in ("f64", "f32", "f16"):
-        assert op.get_option("rhs_per_thread_" + p) in ((1,) if p == "f64" else (1, 4))
+        assert op.get_option("rhs_per_thread_" + p) in {"f64": (1,), "f32": (1, 4), "f16": (1, 2, 4)}[p]
         assert np.array_equal(to_host(op.apply("schur", to_dev(xe), p)), before[p])
     for p, nr in (("f32", 1), ("f32", 2), ("f32", 4), ("f16", 1), ("f16", 2), ("f16", 4), ("f64", 2), ("f64", 4)):
         op.set_option("rhs_per_thread_" + p, nr)
