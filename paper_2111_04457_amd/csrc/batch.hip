@@ -126,10 +126,16 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
     const int n = (int)bt->ops.size();
     const bool clover = bt->ops[0]->has_clover || bt->ops[0]->has_twist;  // a site-local factor
     const int K = red == 2 ? 2 : 3;
+    // four right-hand sides per workgroup (links in LDS) where the operators'
+    // setting takes them for the fewest right-hand sides of the batch
+    int minr = bt->nrhs[0];
+    for (int g = 1; g < n; ++g) minr = std::min(minr, bt->nrhs[g]);
+    const int R = (prec != F64 && minr >= 4 && !bt->ops[0]->has_twist && eff_nr(bt->ops[0], prec, minr) == 4) ? 4 : 1;
     for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
         HopBatch k1{}, k2{};
         const int nl = std::min(kMaxBatch, n - g0);
         k1.nlat = k2.nlat = nl;
+        k1.nr = k2.nr = R;
         for (int j = 0; j < nl; ++j) {
             const int g = g0 + j;
             lq_op *o = bt->ops[g];
@@ -148,7 +154,7 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
             if (red) a2.partial = c.partial + bt->hop_part0[g] * K;
             k1.a[j] = a1;
             k2.a[j] = a2;
-            const int tiles = hop_blocks(o->g.vh, 64) * bt->nrhs[g];
+            const int tiles = hop_blocks(o->g.vh, 64) * ((bt->nrhs[g] + R - 1) / R);
             k1.tile_off[j + 1] = k1.tile_off[j] + tiles;
             k2.tile_off[j + 1] = k2.tile_off[j] + tiles;
         }

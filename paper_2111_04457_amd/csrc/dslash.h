@@ -71,13 +71,16 @@ hipError_t launch_hop(const HopArgs &a, int prec, int recon, bool dag, int clov,
 // The hopping term of up to kMaxBatch lattices in one launch: lattice i's
 // arguments a[i] (its geometry, links, clover blocks and field slices, the
 // right-hand sides of its systems) and its workgroups tile_off[i] ..
-// tile_off[i + 1] - 1 (hop_blocks(vh_i, 64) * nrhs_i of them).  64 threads
-// per workgroup, one right-hand side per thread, the tiles in plain order.
+// tile_off[i + 1] - 1 (hop_blocks(vh_i, 64) * ceil(nrhs_i / nr) of them), in
+// plain order.  nr = 1: 64 threads per workgroup, one right-hand side per
+// thread; nr = 4 (FP16 / FP32): 256 threads, four right-hand sides of a site
+// block per workgroup with its links and clover blocks staged in LDS.
 constexpr int kMaxBatch = 8;
 struct HopBatch {
     HopArgs a[kMaxBatch];
     int tile_off[kMaxBatch + 1];
     int nlat;
+    int nr;
 };
 // (passed by value as the kernel's argument, within the 4 KiB of kernel arguments)
 static_assert(sizeof(HopBatch) <= 4096, "HopBatch exceeds the kernel argument space");

@@ -665,20 +665,20 @@ __device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__rest
     }
 }
 
+// One workgroup (tile `id`: a site block of 64 and a group of R right-hand
+// sides) with the links and clover blocks in the LDS arrays lk and lc.
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R, int PF = Prefetch<P, 1>::value,
           int CACHE = CachePolicy<P, CLOV>::value>
-__global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
+__device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, typename PT<P>::S (*lk)[NL][64],
+                                                typename PT<P>::S (*lc)[64])
 {
     using Rt = typename PT<P>::R;
     using S = typename PT<P>::S;
-    __shared__ S lk[8][NL][64];
-    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
     // tiles (site block of 64, group of R right-hand sides), XCD-aware as in hop_body
     const int nbs = (a.g.vh + 63) / 64;
     const int ngr = (a.nrhs + R - 1) / R;
     const int total = nbs * ngr;
     const int full = a.xcd_remap ? (total / 8) * 8 : 0;
-    const int id = blockIdx.x;
     const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
     const int k = t / ngr;
     const int rhs0 = (t - k * ngr) * R;
@@ -732,6 +732,29 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
     if constexpr (RED != 0) {
         if (rhs_ok) write_partials<RED, 1>(a, k, rhs, 1, red0, red1, red2);
     }
+}
+
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
+__global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
+{
+    using S = typename PT<P>::S;
+    __shared__ S lk[8][NL][64];
+    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
+    hop_shared_body<P, NL, DAG, CLOV, XPAY, RED, R>(a, blockIdx.x, lk, lc);
+}
+
+// The same for a ragged batch: the workgroups tile_off[i] .. tile_off[i + 1] - 1
+// run lattice i's tiles (groups of R right-hand sides).
+template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
+__global__ __launch_bounds__(64 * R) void hop_shared_batch_kernel(HopBatch b)
+{
+    using S = typename PT<P>::S;
+    __shared__ S lk[8][NL][64];
+    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
+    const int t = blockIdx.x;
+    int i = 0;
+    while (i + 1 < b.nlat && t >= b.tile_off[i + 1]) ++i;
+    hop_shared_body<P, NL, DAG, CLOV, XPAY, RED, R>(b.a[i], t - b.tile_off[i], lk, lc);
 }
 
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
@@ -825,6 +848,13 @@ static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
 static hipError_t launch_batch1(const HopBatch &b, hipStream_t s)
 {
+    if constexpr (P != F64) {
+        if (b.nr == 4) {
+            hop_shared_batch_kernel<P, NL, DAG, CLOV, XPAY, RED, 4><<<dim3(b.tile_off[b.nlat]), 256, 0, s>>>(b);
+            return hipGetLastError();
+        }
+    }
+    if (b.nr != 1) return hipErrorInvalidValue;
     hop_batch_kernel<P, NL, DAG, CLOV, XPAY, RED><<<dim3(b.tile_off[b.nlat]), 64, 0, s>>>(b);
     return hipGetLastError();
 }

@@ -8,7 +8,9 @@
   over all lattices' systems, every chunk of inner iterations captured in
   one hipGraph) equals the per-lattice solves bit for bit, and every system
   reaches its true FP64 residual (oracle's D).  Batches of more lattices
-  than one launch takes (8) run in groups of 8 with the same result.
+  than one launch takes (8) run in groups of 8 with the same result; with
+  four or more right-hand sides per lattice the batched kernels take four
+  per workgroup (links in LDS) with the same bits.
 """
 import numpy as np
 import pytest
@@ -116,6 +118,44 @@ def test_ragged_batch_of_nine_lattices_left_preconditioned(lq):
             assert oracle.true_residual(ref, xb[r], bb[r]) <= 1.01e-10, (d, r)
         k += nr[i]
     announce("nine-lattice batch iters %s" % [s.nconv for s in st])
+    batch.close()
+    for op in ops:
+        op.close()
+
+
+def test_ragged_batch_lds_groups_bitwise(lq):
+    """With at least four right-hand sides per lattice the batched hopping
+    kernels take four per workgroup with the links in LDS (groups that do
+    not fill the workgroup included): the same bits as the separate solves,
+    and as the batch with one right-hand side per thread."""
+    dims_list = [(4, 4, 4, 4), (6, 4, 4, 8), (8, 8, 8, 8)]
+    nr = [4, 5, 6]
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=4, left_precond=True)
+    ops, bs, Us = [], [], []
+    for i, d in enumerate(dims_list):
+        U = gauge_exp(d, EPS, 1961 + i)
+        op = lq.Operator(d, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
+        op.set_gauge(to_dev(U))
+        ops.append(op)
+        Us.append(U)
+        bs.append(gaussian_spinor(d, 2961 + i, nr[i]))
+    batch = lq.Batch(ops, nr)
+    xs, st = batch.solve([to_dev(b) for b in bs], prm)
+    k = 0
+    for i, (op, d) in enumerate(zip(ops, dims_list)):
+        x1, s1 = op.solve(to_dev(bs[i]), "D", prm)
+        assert np.array_equal(to_host(xs[i]), to_host(x1)), d
+        assert [s.nconv for s in s1] == [s.nconv for s in st[k:k + nr[i]]]
+        ref = oracle.Operator(d, Us[i], KAPPA, CSW, ANTIPERIODIC_T)
+        xb = to_host(xs[i])
+        for r in range(nr[i]):
+            assert oracle.true_residual(ref, xb[r], bs[i][r]) <= 1.01e-10, (d, r)
+        k += nr[i]
+    ops[0].set_option("rhs_per_thread", 1)  # the batch then runs one per thread
+    xs1, _ = batch.solve([to_dev(b) for b in bs], prm)
+    for i in range(len(ops)):
+        assert np.array_equal(to_host(xs1[i]), to_host(xs[i]))
+    announce("LDS-group batch iters %s" % [s.nconv for s in st])
     batch.close()
     for op in ops:
         op.close()
