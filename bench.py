@@ -479,8 +479,9 @@ def _profile(lq, torch, args):
             fin.load(src.reshape(nrhs, -1, 4, 3)[:, : V // 2].contiguous().reshape((nrhs,) + op.parity_shape))
             if not args.no_tune:  # counter runs take a fixed shape (tuning under counters is not timing)
                 op.tune(nrhs, left=args.left_precond)
-            else:  # the given order, else the automatic one, made explicit for the report
+            else:  # the given order, else the automatic shape, made explicit for the report
                 op.set_option("xcd_remap_f16", args.xcd_remap if args.xcd_remap is not None else (0 if nrhs == 1 else 2))
+                op.set_option("rhs_per_thread_f16", 1 if nrhs == 1 else 4)
             kind = "schur_left" if args.left_precond else "schur"
             us = _graph_time_us(torch, lambda: lq.apply_field(op, kind, fout, fin), args.kernel_reps)
             b2, _ = op.traffic("f16", nrhs, clover=True)

@@ -680,8 +680,10 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
     const int total = nbs * ngr;
     const int full = a.xcd_remap ? (total / 8) * 8 : 0;
     const int t = id < full ? (id % 8) * (full / 8) + id / 8 : id;
-    const int k = t / ngr;
-    const int rhs0 = (t - k * ngr) * R;
+    const int kt = t / ngr;
+    const int rhs0 = (t - kt * ngr) * R;
+    // site block, in the slice order where it applies (64-site tiles)
+    const int k = a.slice_tiles > 0 ? slice_order(kt, a.slice_tiles, a.tgroup, a.g.L[3]) : kt;
     const int nrg = min(R, a.nrhs - rhs0);
     // a group whose right-hand sides are all frozen exits at once (uniformly)
     if (a.mask) {

@@ -130,16 +130,6 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         LQ_HIP(launch_hop_halo(a, tile, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, s));
         return;
     }
-    const int remap = eff_remap(op, prec, in.nrhs);
-    a.xcd_remap = remap != 0 ? 1 : 0;
-    const int block = op->hop_block[prec];
-    if (remap == 2) {
-        const long slice = (long)g.L[0] * g.L[1] * g.L[2] / 2;  // sites of one parity per time slice
-        if (slice % block == 0) {
-            a.slice_tiles = (int)(slice / block);
-            a.tgroup = std::max(1, g.L[3] / 8);  // one group of slices per XCD
-        }
-    }
     // right-hand sides per thread (2, no reductions), or 4 per workgroup
     // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)
     int nr = 1;
@@ -147,6 +137,17 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         const int want = eff_nr(op, prec, in.nrhs);
         if (want == 2 && red == 0) nr = 2;
         else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;
+    }
+    const int remap = eff_remap(op, prec, in.nrhs);
+    a.xcd_remap = remap != 0 ? 1 : 0;
+    const int block = op->hop_block[prec];
+    if (remap == 2) {
+        const long slice = (long)g.L[0] * g.L[1] * g.L[2] / 2;  // sites of one parity per time slice
+        const int sb = nr == 4 ? 64 : block;                     // sites per tile
+        if (slice % sb == 0) {
+            a.slice_tiles = (int)(slice / sb);
+            a.tgroup = std::max(1, g.L[3] / 8);  // one group of slices per XCD
+        }
     }
     LQ_HIP(launch_hop(a, prec, op->nl(prec), dag, clov_mode, y != nullptr, red, nr, block, s));
 }

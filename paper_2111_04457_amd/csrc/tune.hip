@@ -206,14 +206,15 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     int nr, block, remap, halo;
                 };
                 std::vector<Cand> cands;
+                const std::vector<int> orders = {2, 1, 0};
                 for (int block : {256, 128, 64})
-                    for (int remap : {2, 1, 0}) cands.push_back({1, block, remap, 0});
+                    for (int remap : orders) cands.push_back({1, block, remap, 0});
                 if (prec == F16 && nrhs >= 2)
                     for (int block : {128, 64})
-                        for (int remap : {2, 1, 0}) cands.push_back({2, block, remap, 0});
+                        for (int remap : orders) cands.push_back({2, block, remap, 0});
                 // four right-hand sides per workgroup (links in LDS): 256 threads, in each order
                 if (nrhs >= 4 && prec != F64)
-                    for (int remap : {2, 1, 0}) cands.push_back({4, 64, remap, 0});
+                    for (int remap : orders) cands.push_back({4, 64, remap, 0});
                 HaloTile tile;
                 if (prec == F16 && nrhs == 1 && halo_tile(g, tile)) cands.push_back({1, 64, 0, 1});
                 auto restore = [&]() {
