@@ -316,14 +316,16 @@ lq_status lq_op_set_block(lq_op *op, lq_prec prec, int block);
  *                    step; the environment variable LQ_LOG_LEVEL sets a floor;
  *   "rhs_per_thread" 0|1|2|4  how the hopping kernel shares links between
  *                    right-hand sides applied together (0, the default:
- *                    automatic: 4 in FP16 and FP32 with at least 4
- *                    right-hand sides, 2 in FP16 with 2 or 3, else 1): 1 one per thread, the right-hand sides of one site block in
- *                    adjacent workgroups sharing the links through the L2;
- *                    2 two per thread (each loaded link used for both; not
- *                    with the fused dot products, where 1 is used); 4 four
- *                    per workgroup of 64 sites, one wavefront each, the
- *                    links and clover blocks staged once in LDS (FP16 and
- *                    FP32 storage with at least 4 right-hand sides, else 1);
+ *                    automatic: 4 with at least 4 right-hand sides, 2 in
+ *                    FP16 with 2 or 3, else 1): 1 one per thread, the
+ *                    right-hand sides of one site block in adjacent
+ *                    workgroups sharing the links through the L2; 2 two per
+ *                    thread (each loaded link used for both; not with the
+ *                    fused dot products, where 1 is used); 4 four per
+ *                    workgroup of 64 sites, one wavefront each, the links
+ *                    staged once in LDS, and the clover blocks too in FP16
+ *                    and FP32 storage (with at least 4 right-hand sides,
+ *                    else 1);
  *                    per precision "rhs_per_thread_f64" / "_f32" / "_f16".
  * lq_op_get_option also reads "hop_block_f64", "hop_block_f32", "hop_block_f16", and
  * "work_kib": the KiB of device work buffers the operator holds (temporaries,

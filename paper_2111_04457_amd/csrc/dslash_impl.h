@@ -230,6 +230,10 @@ template <int P, int CLOV> struct CachePolicy {
 // branch, next to the other path's registers).
 template <int CLOV> constexpr int clov_mode() { return CLOV & 3; }
 template <int CLOV> constexpr bool has_block() { return (CLOV & 3) != 0 && (CLOV & kTwist) == 0; }
+// the four-per-workgroup kernel stages the clover block in LDS next to the
+// links in binary16 and FP32; the FP64 block (36 KB per 64 sites) is read by
+// each wavefront from the caches instead, so that two workgroups fit a CU
+template <int P, int CLOV> constexpr bool stage_block() { return has_block<CLOV>() && P != F64; }
 
 // C v: a clover block (A or A^-1, two 6x6 Hermitian blocks, already loaded
 // into craw), or, for the twisted-mass Wilson operator, the scalar tw on
@@ -708,7 +712,7 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
     if (site_ok && rhs_ok) prologue_sp<P, NL, PF, 0>(a, in, cb, c, slot);
     if (site_ok) {
         stage_links<P, NL, 0, R, (CACHE & 1) != 0>(a, w, lane, cb, c, lk);
-        if constexpr (has_block<CLOV>()) {
+        if constexpr (stage_block<P, CLOV>()) {
             if (w == R - 1) {
                 S raw[72];
                 load_planes<S, 72, true>(a.clov, cb, a.g.vh, raw);
@@ -725,9 +729,11 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
         for (int i = 0; i < 12; ++i) acc[0][i] = cx<Rt>{0, 0};
         pipeline_sp<P, NL, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
         S craw[has_block<CLOV>() ? 72 : 1];
-        if constexpr (has_block<CLOV>()) {
+        if constexpr (stage_block<P, CLOV>()) {
 #pragma unroll
             for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
+        } else if constexpr (has_block<CLOV>()) {
+            load_planes<S, 72, true>(a.clov, cb, a.g.vh, craw);
         }
         epilogue<P, CLOV, XPAY, RED, 1, CACHE>(a, cb, rhs, 1, craw, acc, red0, red1, red2);
     }
@@ -741,7 +747,7 @@ __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
 {
     using S = typename PT<P>::S;
     __shared__ S lk[8][NL][64];
-    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
+    __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
     hop_shared_body<P, NL, DAG, CLOV, XPAY, RED, R>(a, blockIdx.x, lk, lc);
 }
 
@@ -752,7 +758,7 @@ __global__ __launch_bounds__(64 * R) void hop_shared_batch_kernel(HopBatch b)
 {
     using S = typename PT<P>::S;
     __shared__ S lk[8][NL][64];
-    __shared__ S lc[has_block<CLOV>() ? 72 : 1][64];
+    __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
     const int t = blockIdx.x;
     int i = 0;
     while (i + 1 < b.nlat && t >= b.tile_off[i + 1]) ++i;
@@ -788,10 +794,7 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED>
 static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 {
     // nr == 4: four right-hand sides per workgroup sharing links in LDS
-    // (binary16 and FP32 storage; the FP64 blocks would not fit)
-    if constexpr (P != F64) {
-        if (nr == 4) return launch_shared<P, NL, DAG, CLOV, XPAY, RED, 4>(a, s);
-    }
+    if (nr == 4) return launch_shared<P, NL, DAG, CLOV, XPAY, RED, 4>(a, s);
     if constexpr (RED == 0) {
         if (nr == 2) return launch_nt<P, NL, DAG, CLOV, XPAY, RED, 2>(a, block, s);
     }

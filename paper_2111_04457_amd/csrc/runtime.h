@@ -219,7 +219,7 @@ bool kind_is_full(lq_kind k);
 // The launch settings in effect for nrhs right-hand sides of precision prec:
 // the option's value, or, automatic (-1 / 0), plain order for one right-hand
 // side and XCD-aware order with the time slices interleaved for several;
-// four right-hand sides per workgroup in FP16 and FP32 with at least four,
+// four right-hand sides per workgroup with at least four,
 // two per thread in FP16 with two or three, else one per thread (the
 // measured best untuned shapes on 24^3 x 48 and 32^3 x 64).
 int eff_remap(const lq_op *op, int prec, int nrhs);

@@ -131,12 +131,12 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
         return;
     }
     // right-hand sides per thread (2, no reductions), or 4 per workgroup
-    // sharing the links in LDS (FP16 / FP32, at least 4 right-hand sides)
+    // sharing the links in LDS (at least 4 right-hand sides)
     int nr = 1;
     if (in.nrhs > 1 && !(clov_mode & kTwist)) {
         const int want = eff_nr(op, prec, in.nrhs);
         if (want == 2 && red == 0) nr = 2;
-        else if (want == 4 && prec != F64 && in.nrhs >= 4) nr = 4;
+        else if (want == 4 && in.nrhs >= 4) nr = 4;
     }
     const int remap = eff_remap(op, prec, in.nrhs);
     a.xcd_remap = remap != 0 ? 1 : 0;
@@ -161,11 +161,10 @@ int eff_remap(const lq_op *op, int prec, int nrhs)
 int eff_nr(const lq_op *op, int prec, int nrhs)
 {
     // measured at 24^3 x 48 and 32^3 x 64: four per workgroup from four
-    // right-hand sides on (FP16 and FP32), two per thread for two or three in
-    // FP16 (its dot-product arithmetic leaves the registers for them)
+    // right-hand sides on (every precision), two per thread for two or three
+    // in FP16 (its dot-product arithmetic leaves the registers for them)
     const int v = op->rhs_per_thread[prec];
     if (v > 0) return v;
-    if (prec == F64) return 1;
     if (nrhs >= 4) return 4;
     return prec == F16 && nrhs >= 2 ? 2 : 1;
 }

@@ -9,8 +9,8 @@
 // and |out|^2).  Candidates: workgroup sizes {64, 128, 256} x the three
 // workgroup orders (plain, XCD-aware, XCD-aware with time slices
 // interleaved), with several right-hand sides two per thread (binary16) and
-// four per workgroup with links and clover blocks staged in LDS (binary16 /
-// FP32), and with one
+// four per workgroup with links (and, in binary16 / FP32, clover blocks)
+// staged in LDS, and with one
 // right-hand side in binary16 the kernel with the neighbour spinors of a
 // tile staged in LDS (when a tile fits the lattice).  The output of
 // every candidate must be bitwise equal to the first candidate's (each
@@ -213,7 +213,7 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     for (int block : {128, 64})
                         for (int remap : orders) cands.push_back({2, block, remap, 0});
                 // four right-hand sides per workgroup (links in LDS): 256 threads, in each order
-                if (nrhs >= 4 && prec != F64)
+                if (nrhs >= 4)
                     for (int remap : orders) cands.push_back({4, 64, remap, 0});
                 HaloTile tile;
                 if (prec == F16 && nrhs == 1 && halo_tile(g, tile)) cands.push_back({1, 64, 0, 1});

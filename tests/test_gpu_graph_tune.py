@@ -116,7 +116,7 @@ def test_tuner_multi_rhs_shapes_bitwise(lq, inputs):
     rep = op.tune(5)
     announce("tune(5) report %s" % json.dumps(rep))
     for p in ("f64", "f32", "f16"):
-        assert op.get_option("rhs_per_thread_" + p) in {"f64": (1,), "f32": (1, 4), "f16": (1, 2, 4)}[p]
+        assert op.get_option("rhs_per_thread_" + p) in {"f64": (1, 4), "f32": (1, 4), "f16": (1, 2, 4)}[p]
         assert np.array_equal(to_host(op.apply("schur", to_dev(xe), p)), before[p])
     for p, nr in (("f32", 1), ("f32", 2), ("f32", 4), ("f16", 1), ("f16", 2), ("f16", 4), ("f64", 2), ("f64", 4)):
         op.set_option("rhs_per_thread_" + p, nr)
@@ -126,17 +126,18 @@ def test_tuner_multi_rhs_shapes_bitwise(lq, inputs):
 
 @pytest.mark.parametrize("dims,nrhs", [((8, 4, 8, 8), 4), ((8, 4, 8, 8), 6), ((6, 4, 4, 10), 12), ((4, 4, 2, 6), 5)])
 def test_lds_shared_rhs_bitwise(lq, dims, nrhs):
-    """Four right-hand sides per workgroup with the links and clover blocks
-    staged in LDS give the bits of one right-hand side per thread: every
-    kind of the hopping kernel (plain, clover on the result, clover on y
-    with the axpy, the Schur operator and its dagger), FP16 and FP32, with
+    """Four right-hand sides per workgroup with the links (and, in FP16 and
+    FP32, the clover blocks) staged in LDS give the bits of one right-hand
+    side per thread: every kind of the hopping kernel (plain, clover on the
+    result, clover on y with the axpy, the Schur operator and its dagger),
+    FP16, FP32 and FP64, with
     groups of right-hand sides that do not fill the workgroup and site
     blocks that are cut by the lattice's end (480 and 96 sites per parity)."""
     U = gauge_exp(dims, 0.4, 1611)
     op = lq.Operator(dims, KAPPA, CSW, ANTIPERIODIC_T, link_recon=12)
     op.set_gauge(to_dev(U))
     xe = to_dev(np.stack([gaussian_parity_spinor(dims, 2620 + i) for i in range(nrhs)]))
-    for p in ("f16", "f32"):
+    for p in ("f16", "f32", "f64"):
         for kind in ("hop_eo", "hop_oe_dag", "clover_inv_o", "schur", "schur_dag", "schur_normal", "schur_left"):
             op.set_option("rhs_per_thread_" + p, 1)
             ref = to_host(op.apply(kind, xe, p))
