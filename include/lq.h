@@ -544,6 +544,8 @@ typedef struct {
     int gcr_restart;      /* flexible GCR basis length, 1..32 */
 } lq_mg_params;
 
+/* block 4^4, nvec 12, setup_iters 3, setup_tol 1e-2, smooth_steps 8,
+ * coarse_tol 0.2, coarse_max_iter 200, gcr_restart 16 */
 void lq_mg_params_default(lq_mg_params *p);
 /* Build the two-level hierarchy for op's current gauge field and
  * parameters (the setup above; it uses the operator's solver).  v0: device

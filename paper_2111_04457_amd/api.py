@@ -466,7 +466,7 @@ class MGParams:
     setup_iters: int = 3          # inverse iterations per vector
     setup_tol: float = 1e-2
     smooth_steps: int = 8         # minimal-residual post-smoothing steps
-    coarse_tol: float = 0.05
+    coarse_tol: float = 0.2
     coarse_max_iter: int = 200
     gcr_restart: int = 16
 

@@ -838,7 +838,7 @@ void lq_mg_params_default(lq_mg_params *p)
     p->setup_iters = 3;
     p->setup_tol = 1e-2;
     p->smooth_steps = 8;
-    p->coarse_tol = 0.05;
+    p->coarse_tol = 0.2;
     p->coarse_max_iter = 200;
     p->gcr_restart = 16;
 }

@@ -45,6 +45,16 @@ def test_version_and_defaults(lib):
     s = _lib.SolverParams()
     lib.lq_solver_params_default(ctypes.byref(s))
     assert s.solver == _lib.BICGSTAB and s.tol == 1e-10 and s.even_odd == 1
+    assert s.reliable == 0 and s.deflate == 0
+    m = _lib.MGParams()
+    lib.lq_mg_params_default(ctypes.byref(m))
+    assert list(m.block) == [4, 4, 4, 4] and m.nvec == 12 and m.setup_iters == 3 and m.setup_tol == 1e-2
+    assert m.smooth_steps == 8 and m.coarse_tol == 0.2 and m.coarse_max_iter == 200 and m.gcr_restart == 16
+    # the Python defaults are the library's
+    from paper_2111_04457_amd.api import MGParams
+    d = MGParams().to_c()
+    assert [getattr(d, f) for f, _ in _lib.MGParams._fields_ if f != "block"] == \
+        [getattr(m, f) for f, _ in _lib.MGParams._fields_ if f != "block"]
 
 
 def _params(**kw):
