@@ -470,8 +470,9 @@ void lq_eig_params_default(lq_eig_params *p);
  * the residual norms |A x - lambda x| / |x| computed on the GPU, evecs (may
  * be NULL; device complex128 [nev][V/2][4][3]) the unit Ritz vectors, stats
  * (may be NULL) the counts above.  A workspace of about (2m + 2) V/2 192
- * bytes plus four packed fields is allocated for the call and freed before
- * it returns.  When the Krylov space of v0 is invariant with fewer than nev
+ * bytes plus four packed fields (and two pinned host doubles) stays with
+ * the operator: grown when a call needs more, reused by later calls, freed
+ * with the operator (counted in the "work_kib" option).  When the Krylov space of v0 is invariant with fewer than nev
  * dimensions, the missing pairs are NaN in evals and resid and their evecs
  * slots are not written.  LQ_ERR_ARG for invalid parameters, a zero start
  * vector or a degree with d arccosh((hi + lo) / (hi - lo)) > 600 (T_d would

@@ -362,7 +362,9 @@ struct Lanczos {
     Vec vec;
     long n;
     int m;
-    Buf basis, ritz, work, packed, part, mpart, coef, ydev;
+    // the workspace stays with the operator (grown as needed, reused by the
+    // next call)
+    Buf &basis, &ritz, &work, &packed, &part, &mpart, &coef, &ydev;
     double *hres = nullptr;
     long applies = 0;  // applications of A
 
@@ -370,7 +372,9 @@ struct Lanczos {
     double *X(int i) { return reinterpret_cast<double *>(ritz.ptr) + (size_t)i * 2 * n; }
     double *P(int i) { return reinterpret_cast<double *>(packed.ptr + (size_t)i * fb(F64, op->g)); }
 
-    Lanczos(lq_op *o, hipStream_t st, int m_) : op(o), s(st), n(12L * o->g.vh), m(m_)
+    Lanczos(lq_op *o, hipStream_t st, int m_)
+        : op(o), s(st), n(12L * o->g.vh), m(m_), basis(o->eig_ws[0]), ritz(o->eig_ws[1]), work(o->eig_ws[2]),
+          packed(o->eig_ws[3]), part(o->eig_ws[4]), mpart(o->eig_ws[5]), coef(o->eig_ws[6]), ydev(o->eig_ws[7])
     {
         const size_t vbytes = sizeof(double) * 2 * (size_t)n;
         basis.ensure(vbytes * (size_t)(m + 1));
@@ -382,12 +386,10 @@ struct Lanczos {
         mpart.ensure(sizeof(double) * 2 * DOT_WG * (size_t)m);
         coef.ensure(sizeof(double) * 2 * 2 * (size_t)m * (size_t)(m + 1));
         ydev.ensure(sizeof(double) * (size_t)m * (size_t)m);
-        LQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&hres), 2 * sizeof(double), hipHostMallocDefault));
+        if (!op->eig_host)
+            LQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&op->eig_host), 2 * sizeof(double), hipHostMallocDefault));
+        hres = op->eig_host;
         vec = Vec{s, n, reinterpret_cast<double *>(part.ptr), hres};
-    }
-    ~Lanczos()
-    {
-        if (hres) (void)hipHostFree(hres);
     }
     Lanczos(const Lanczos &) = delete;
     Lanczos &operator=(const Lanczos &) = delete;

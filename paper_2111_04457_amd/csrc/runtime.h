@@ -87,6 +87,9 @@ struct lq_op {
     lq::Buf md_G;                        // molecular dynamics: the force on every link
     lq::Buf md_partial;                  // molecular dynamics: per-wavefront partial sums
     lq::Buf md_X[3];                     // molecular dynamics: previous solutions and the next guess
+    lq::Buf eig_ws[8];                   // eigensolver: Krylov basis, Ritz vectors, work vector, packed
+                                         // fields, partial sums, projections, coefficients, rotation
+    double *eig_host = nullptr;          // eigensolver: pinned host scalars
     lq::Buf partial;                     // reduction partial sums
     lq::Buf solver_ws;                   // solver work vectors
     lq::Buf solver_sc;                   // solver scalars (device)
@@ -121,6 +124,7 @@ struct lq_op {
     {
         clear_graphs();
         if (host_sc) (void)hipHostFree(host_sc);
+        if (eig_host) (void)hipHostFree(eig_host);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (stream) (void)hipStreamDestroy(stream);
@@ -134,6 +138,7 @@ struct lq_op {
         for (const auto &b : tmp) n += b.bytes;
         for (const auto &b : defl_ws) n += b.bytes;
         for (const auto &b : md_X) n += b.bytes;
+        for (const auto &b : eig_ws) n += b.bytes;
         return n;
     }
     // device bytes the library allocated itself for this operator (not
@@ -146,6 +151,7 @@ struct lq_op {
         for (const auto &b : tmp) n += b.owned();
         for (const auto &b : defl_ws) n += b.owned();
         for (const auto &b : md_X) n += b.owned();
+        for (const auto &b : eig_ws) n += b.owned();
         return n;
     }
     // link format of the hop kernels (the clover build and the force use the

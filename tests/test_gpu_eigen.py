@@ -123,10 +123,17 @@ def test_eigs_8x8x8x8_properties(lq, degree):
         Av = op.apply("schur_normal", v, "f64")
         rq = float(torch.vdot(v.reshape(-1), Av.reshape(-1)).real / torch.vdot(v.reshape(-1), v.reshape(-1)).real)
         assert ev[0] < rq
-    # the other variant agrees on the eigenvalues
+    # the other variant agrees on the eigenvalues; it reuses the workspace
+    # the first call left with the operator
+    kib = op.get_option("work_kib")
     ev2, _, _, st2 = op.eigs(8, 40, v0=to_dev(gaussian_parity_spinor(dims, 7305)), tol=1e-8,
                              cheb_degree=16 - degree)
     assert st2["nconv"] == 8 and np.allclose(ev, ev2, rtol=1e-12, atol=0)
+    assert op.get_option("work_kib") == kib > 0
+    # a repeated call on the kept workspace gives the same bits
+    ev3, res3, X3, _ = op.eigs(8, 40, v0=to_dev(gaussian_parity_spinor(dims, 7302)), tol=1e-8, vectors=True,
+                               cheb_degree=degree)
+    assert list(ev3) == list(ev) and list(res3) == list(res) and np.array_equal(to_host(X3), to_host(X))
     op.close()
 
 
