@@ -69,7 +69,8 @@ struct lq_op {
     int log_level = 0;                   // progress lines of solves on stderr (also $LQ_LOG_LEVEL)
     int rhs_per_thread[3] = {0, 0, 0};   // right-hand sides per thread of the hop kernel (nrhs > 1); 0 automatic
     int halo[3] = {0, 0, 0};             // 1: neighbour spinors staged in LDS (binary16, one rhs, if a tile fits)
-    int inner_hint = 0;                  // iterations the last inner solve needed (first chunk length)
+    std::vector<int> inner_hints;        // iterations the k-th inner solve of the last solve needed
+                                         // (first chunk length of the next solve's k-th)
     lq::Buf links[3];                    // packed links per precision ([parity][mu]); FP64 always 18 reals
     lq::Buf links64r;                    // FP64 links with 12 reals (hop kernels) when link_recon == 12
     lq::Buf clov[3];                     // A = 1 + F per precision ([parity])

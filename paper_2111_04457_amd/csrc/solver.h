@@ -29,7 +29,7 @@ struct lq_batch {
     lq::Buf ws, sc, partial;      // solver vectors, scalars, partial sums
     double *host_sc = nullptr;    // pinned mirror of the scalars
     size_t host_sc_n = 0;
-    int inner_hint = 0;
+    std::vector<int> inner_hints;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<lq_op::GraphEntry> graphs;
@@ -138,10 +138,10 @@ struct SolveCtx {
 // the scalars back after each chunk; a system that converges inside a chunk
 // is masked for the rest of it, so the lengths change only how many masked
 // (nearly empty) iterations are launched, never a result.  The first chunk
-// is the iteration count of the previous inner solve (of the same outer
-// loop, or of the operator's previous solve: every inner solve reduces its
-// residual by about the same factor), then one short chunk, then
-// check_every.
+// is the iteration count of the same-numbered inner solve of the operator's
+// previous solve (the first inner solve starts from b, the later ones from
+// residuals an inner solve already reduced), else of the previous inner
+// solve of this one; then one short chunk, then check_every.
 struct ChunkPlan {
     int hint = 0;   // iterations the previous inner solve needed (0: none yet)
     int every = 10;

@@ -428,8 +428,12 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
     os.r2.assign(nsys, 0.0);
     int total_inner = 0;
     ChunkPlan plan;
-    int &hint = c.bt ? c.bt->inner_hint : c.op->inner_hint;
-    plan.hint = hint;  // from the previous solve
+    // first chunk of the k-th inner solve: what the k-th inner solve of the
+    // previous solve needed (the first inner solve starts from b, the later
+    // ones from smaller residuals), else what the last inner solve needed
+    std::vector<int> &hints = c.bt ? c.bt->inner_hints : c.op->inner_hints;
+    size_t k_inner = 0;
+    plan.hint = hints.empty() ? 0 : hints[0];
     // the outer target of each system (FIN_NORM flags systems below it)
     c.pull();
     for (int i = 0; i < nsys; ++i) c.hsc[i * NSC + SC_OTARGET2] = target2[i];
@@ -582,6 +586,7 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         // kInnerCap iterations (a restart from the current FP64 iterate)
         constexpr int kInnerCap = 1000;
         const int budget = std::min(sp.max_iter - total_inner, kInnerCap);
+        if (k_inner < hints.size() && hints[k_inner] > 0) plan.hint = hints[k_inner];
         plan.start(sp.check_every);
         int it;
         if (normal) it = inner_cg(c, true, budget, plan, restart);
@@ -589,6 +594,11 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         else it = inner_bicgstab(c, budget, plan, restart);
         c.left = false;
         total_inner += it;
+        if (plan.hint > 0 && k_inner < 64) {
+            if (k_inner < hints.size()) hints[k_inner] = plan.hint;
+            else hints.push_back(plan.hint);
+        }
+        ++k_inner;
         for (int i = 0; i < nsys; ++i) {
             const double *h = c.hsc + i * NSC;
             if (h[SC_ODONE] == 0.0) {
@@ -599,7 +609,6 @@ OuterStats defect_correction(SolveCtx &c, const lq_solver_params &sp, bool norma
         // x += |r| e
         LQ_HIP(launch_accum(c.x64, c.ix, c.sc, c.sps, true, c.s));
     }
-    if (plan.hint > 0) hint = plan.hint;
     if (c.log >= 1)
         for (int g = 0; g < ng; ++g) {
             int it = 0, outer = 0, rst = 0;
