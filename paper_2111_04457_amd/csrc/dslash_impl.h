@@ -82,6 +82,24 @@ __device__ __forceinline__ void gather(const HopArgs &a, const char *__restrict_
     }
 }
 
+// The third row of an SU(3) link from its first two rows (u[0..5] as
+// converted from storage): conj(row0 x row1).  Binary16 storage forms it
+// with the multiply-adds of cdet2; FP32 / FP64 with the complex products.
+// Every kernel that rebuilds a row calls this, so all round alike.
+template <int P>
+__device__ __forceinline__ void third_row(cx<typename PT<P>::R> u[9])
+{
+    if constexpr (PT<P>::scaled) {
+        u[6] = conj(cdet2(u[1], u[5], u[2], u[4]));
+        u[7] = conj(cdet2(u[2], u[3], u[0], u[5]));
+        u[8] = conj(cdet2(u[0], u[4], u[1], u[3]));
+    } else {
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
 // Half K on the link at lnk[i * LS] (i = 0 .. NL - 1).
 template <int P, int NL, bool DAG, int NR, int K, int LS>
 __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT<P>::S *lnk,
@@ -109,11 +127,9 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
 #pragma unroll
         for (int i = 0; i < NL / 2; ++i) uh[i] = h2{lnk[(2 * i) * LS], lnk[(2 * i + 1) * LS]};
         if constexpr (NL == 12) {
-            u[6] = conj(cdet2(u[1], u[5], u[2], u[4]));
-            u[7] = conj(cdet2(u[2], u[3], u[0], u[5]));
-            u[8] = conj(cdet2(u[0], u[4], u[1], u[3]));
+            third_row<P>(u);
 #pragma unroll
-            for (int i = 6; i < 9; ++i) uh[i] = h2{(_Float16)u[i].re, (_Float16)u[i].im};
+            for (int i = 6; i < 9; ++i) uh[i] = h2{to_f16(u[i].re), to_f16(u[i].im)};
         }
         const bool phase = a.g.bc_re[MU] != 1.0 || a.g.bc_im[MU] != 0.0;  // the same for every thread
 #pragma unroll
@@ -131,11 +147,7 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
             reconstruct_sc<MU, SG>(acc[r], o, h.scale[r]);
         }
     } else {
-        if constexpr (NL == 12) {
-            u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-            u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-            u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-        }
+        if constexpr (NL == 12) third_row<P>(u);
         // FP32 / FP64 are bound by memory: a branch-free multiply by the
         // boundary phase keeps the loads of the pipeline free to move (a
         // branch here measured slower)
@@ -629,11 +641,15 @@ static hipError_t launch_pd_halo(const HopArgs &a, const HaloTile &h, int recon,
 // operations are those of hop_body, so the results are the same bits; the
 // links and clover blocks are read from memory once per R right-hand sides.
 
+// Links of NL reals are staged as 18: the third row of a 12-real link is
+// rebuilt once here (third_row, rounded to the storage type as the hop
+// kernels round it) instead of by every wavefront that reads it.
 template <int P, int NL, int K, int R, bool NTL>
 __device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, int cb, const int c[4],
-                                            typename PT<P>::S (*lk)[NL][64])
+                                            typename PT<P>::S (*lk)[18][64])
 {
     using S = typename PT<P>::S;
+    using Rt = typename PT<P>::R;
     if constexpr (K < 8) {
         if (K % R == w) {
             bool wrap;
@@ -642,30 +658,50 @@ __device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, i
             load_half_link<P, NL, K, NTL>(a, cb, nb, raw);
 #pragma unroll
             for (int i = 0; i < NL; ++i) lk[K][i][lane] = raw[i];
+            if constexpr (NL == 12) {
+                cx<Rt> u[9];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) u[i] = cx<Rt>{(Rt)raw[2 * i], (Rt)raw[2 * i + 1]};
+                third_row<P>(u);
+#pragma unroll
+                for (int i = 6; i < 9; ++i) {
+                    // rounded as consume_link rounds it: to FP32, then to
+                    // the storage type (to_f16 keeps the compiler from
+                    // fusing the last multiply-add with the conversion)
+                    if constexpr (PT<P>::scaled) {
+                        lk[K][2 * i][lane] = to_f16(u[i].re);
+                        lk[K][2 * i + 1][lane] = to_f16(u[i].im);
+                    } else {
+                        lk[K][2 * i][lane] = (S)u[i].re;
+                        lk[K][2 * i + 1][lane] = (S)u[i].im;
+                    }
+                }
+            }
         }
         stage_links<P, NL, K + 1, R, NTL>(a, w, lane, cb, c, lk);
     }
 }
 
-template <int P, int NL, int PF, int K>
+template <int P, int PF, int K>
 __device__ __forceinline__ void prologue_sp(const HopArgs &a, const char *__restrict__ in, int cb, const int c[4],
-                                            HalfRaw<P, NL, 1> (&slot)[PF])
+                                            HalfRaw<P, 18, 1> (&slot)[PF])
 {
     if constexpr (K < PF) {
-        gather<P, NL, 1, K, false, false>(a, in, 1, cb, c, slot[K]);
-        prologue_sp<P, NL, PF, K + 1>(a, in, cb, c, slot);
+        gather<P, 18, 1, K, false, false>(a, in, 1, cb, c, slot[K]);
+        prologue_sp<P, PF, K + 1>(a, in, cb, c, slot);
     }
 }
 
-template <int P, int NL, bool DAG, int PF, int K>
+// (links read from LDS as 18 reals, whatever the storage format)
+template <int P, bool DAG, int PF, int K>
 __device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__restrict__ in, int lane, int cb,
-                                            const int c[4], typename PT<P>::S (*lk)[NL][64],
-                                            HalfRaw<P, NL, 1> (&slot)[PF], cx<typename PT<P>::R> (&acc)[1][12])
+                                            const int c[4], typename PT<P>::S (*lk)[18][64],
+                                            HalfRaw<P, 18, 1> (&slot)[PF], cx<typename PT<P>::R> (&acc)[1][12])
 {
     if constexpr (K < 8) {
-        consume_link<P, NL, DAG, 1, K, 64>(a, &lk[K][0][lane], slot[K % PF], acc);
-        if constexpr (K + PF < 8) gather<P, NL, 1, K + PF, false, false>(a, in, 1, cb, c, slot[K % PF]);
-        pipeline_sp<P, NL, DAG, PF, K + 1>(a, in, lane, cb, c, lk, slot, acc);
+        consume_link<P, 18, DAG, 1, K, 64>(a, &lk[K][0][lane], slot[K % PF], acc);
+        if constexpr (K + PF < 8) gather<P, 18, 1, K + PF, false, false>(a, in, 1, cb, c, slot[K % PF]);
+        pipeline_sp<P, DAG, PF, K + 1>(a, in, lane, cb, c, lk, slot, acc);
     }
 }
 
@@ -673,7 +709,7 @@ __device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__rest
 // sides) with the links and clover blocks in the LDS arrays lk and lc.
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R, int PF = Prefetch<P, 1>::value,
           int CACHE = CachePolicy<P, CLOV>::value>
-__device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, typename PT<P>::S (*lk)[NL][64],
+__device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, typename PT<P>::S (*lk)[18][64],
                                                 typename PT<P>::S (*lc)[64])
 {
     using Rt = typename PT<P>::R;
@@ -707,9 +743,9 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
     int c[4] = {0, 0, 0, 0};
     if (site_ok) cb_coords(a.g, a.p_out, cb, c);
     const char *in = a.in + (long)(rhs_ok ? rhs : rhs0) * a.in_rs;
-    HalfRaw<P, NL, 1> slot[PF];
+    HalfRaw<P, 18, 1> slot[PF];  // spinors only (the links come from LDS)
     // the first neighbour spinors are requested before the staging barrier
-    if (site_ok && rhs_ok) prologue_sp<P, NL, PF, 0>(a, in, cb, c, slot);
+    if (site_ok && rhs_ok) prologue_sp<P, PF, 0>(a, in, cb, c, slot);
     if (site_ok) {
         stage_links<P, NL, 0, R, (CACHE & 1) != 0>(a, w, lane, cb, c, lk);
         if constexpr (stage_block<P, CLOV>()) {
@@ -727,7 +763,7 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
         cx<Rt> acc[1][12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) acc[0][i] = cx<Rt>{0, 0};
-        pipeline_sp<P, NL, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
+        pipeline_sp<P, DAG, PF, 0>(a, in, lane, cb, c, lk, slot, acc);
         S craw[has_block<CLOV>() ? 72 : 1];
         if constexpr (stage_block<P, CLOV>()) {
 #pragma unroll
@@ -746,7 +782,7 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
 __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
 {
     using S = typename PT<P>::S;
-    __shared__ S lk[8][NL][64];
+    __shared__ S lk[8][18][64];
     __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
     hop_shared_body<P, NL, DAG, CLOV, XPAY, RED, R>(a, blockIdx.x, lk, lc);
 }
@@ -757,7 +793,7 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
 __global__ __launch_bounds__(64 * R) void hop_shared_batch_kernel(HopBatch b)
 {
     using S = typename PT<P>::S;
-    __shared__ S lk[8][NL][64];
+    __shared__ S lk[8][18][64];
     __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
     const int t = blockIdx.x;
     int i = 0;

@@ -247,7 +247,10 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         first = false;
                     } else if (cur_host != ref_host) {
                         restore();
-                        throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results"};
+                        throw Failure{LQ_ERR_STATE, "lq_tune: launch shapes gave different results (precision " +
+                                                        std::to_string(prec) + ", right-hand sides per thread " +
+                                                        std::to_string(cd.nr) + ", block " + std::to_string(cd.block) +
+                                                        ", order " + std::to_string(cd.remap) + ")"};
                     }
                     if (us < best_us) {
                         best_us = us;

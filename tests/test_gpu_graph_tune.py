@@ -143,7 +143,7 @@ def test_lds_shared_rhs_bitwise(lq, dims, nrhs):
             ref = to_host(op.apply(kind, xe, p))
             op.set_option("rhs_per_thread_" + p, 4)
             got = to_host(op.apply(kind, xe, p))
-            assert np.array_equal(got, ref), (p, kind)
+            assert np.array_equal(got, ref), (p, kind, float(np.abs(got - ref).max()))
     # a multi-RHS solve with the fused dot products in the shared kernel
     b = to_dev(gaussian_spinor(dims, 2630, nrhs))
     prm = lq.SolverParams(solver="bicgstab", tol=1e-10, inner="f16", inner_tol=1e-2, check_every=4)
