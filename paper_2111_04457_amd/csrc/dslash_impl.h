@@ -100,8 +100,10 @@ __device__ __forceinline__ void third_row(cx<typename PT<P>::R> u[9])
     }
 }
 
-// Half K on the link at lnk[i * LS] (i = 0 .. NL - 1).
-template <int P, int NL, bool DAG, int NR, int K, int LS>
+// Half K on the link with real and imaginary part of entry j at
+// lnk[2 j LS] and lnk[2 j LS + IM] (IM = LS: reals LS apart; IM = 1:
+// (re, im) pairs 2 LS apart).
+template <int P, int NL, bool DAG, int NR, int K, int LS, int IM = LS>
 __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT<P>::S *lnk,
                                              const HalfRaw<P, NL, NR> &h, cx<typename PT<P>::R> (&acc)[NR][12])
 {
@@ -112,7 +114,7 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
     constexpr int SG = (FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1));
     cx<R> u[9];
 #pragma unroll
-    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)lnk[(2 * i) * LS], (R)lnk[(2 * i + 1) * LS]};
+    for (int i = 0; i < NL / 2; ++i) u[i] = cx<R>{(R)lnk[(2 * i) * LS], (R)lnk[(2 * i) * LS + IM]};
     const cx<R> ph = cx<R>{(R)a.g.bc_re[MU], FWD ? (R)a.g.bc_im[MU] : -(R)a.g.bc_im[MU]};
     if constexpr (PT<P>::scaled) {
         // binary16 storage (the kernels are bound by instruction issue as much
@@ -125,7 +127,7 @@ __device__ __forceinline__ void consume_link(const HopArgs &a, const typename PT
         // FP32 from the converted entries and rounded to binary16.
         h2 uh[9];
 #pragma unroll
-        for (int i = 0; i < NL / 2; ++i) uh[i] = h2{lnk[(2 * i) * LS], lnk[(2 * i + 1) * LS]};
+        for (int i = 0; i < NL / 2; ++i) uh[i] = h2{lnk[(2 * i) * LS], lnk[(2 * i) * LS + IM]};
         if constexpr (NL == 12) {
             third_row<P>(u);
 #pragma unroll
@@ -646,7 +648,7 @@ static hipError_t launch_pd_halo(const HopArgs &a, const HaloTile &h, int recon,
 // kernels round it) instead of by every wavefront that reads it.
 template <int P, int NL, int K, int R, bool NTL>
 __device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, int cb, const int c[4],
-                                            typename PT<P>::S (*lk)[18][64])
+                                            typename PT<P>::S (*lk)[9][64][2])
 {
     using S = typename PT<P>::S;
     using Rt = typename PT<P>::R;
@@ -657,7 +659,7 @@ __device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, i
             S raw[NL];
             load_half_link<P, NL, K, NTL>(a, cb, nb, raw);
 #pragma unroll
-            for (int i = 0; i < NL; ++i) lk[K][i][lane] = raw[i];
+            for (int i = 0; i < NL; ++i) lk[K][i / 2][lane][i % 2] = raw[i];
             if constexpr (NL == 12) {
                 cx<Rt> u[9];
 #pragma unroll
@@ -669,11 +671,11 @@ __device__ __forceinline__ void stage_links(const HopArgs &a, int w, int lane, i
                     // the storage type (to_f16 keeps the compiler from
                     // fusing the last multiply-add with the conversion)
                     if constexpr (PT<P>::scaled) {
-                        lk[K][2 * i][lane] = to_f16(u[i].re);
-                        lk[K][2 * i + 1][lane] = to_f16(u[i].im);
+                        lk[K][i][lane][0] = to_f16(u[i].re);
+                        lk[K][i][lane][1] = to_f16(u[i].im);
                     } else {
-                        lk[K][2 * i][lane] = (S)u[i].re;
-                        lk[K][2 * i + 1][lane] = (S)u[i].im;
+                        lk[K][i][lane][0] = (S)u[i].re;
+                        lk[K][i][lane][1] = (S)u[i].im;
                     }
                 }
             }
@@ -695,11 +697,11 @@ __device__ __forceinline__ void prologue_sp(const HopArgs &a, const char *__rest
 // (links read from LDS as 18 reals, whatever the storage format)
 template <int P, bool DAG, int PF, int K>
 __device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__restrict__ in, int lane, int cb,
-                                            const int c[4], typename PT<P>::S (*lk)[18][64],
+                                            const int c[4], typename PT<P>::S (*lk)[9][64][2],
                                             HalfRaw<P, 18, 1> (&slot)[PF], cx<typename PT<P>::R> (&acc)[1][12])
 {
     if constexpr (K < 8) {
-        consume_link<P, 18, DAG, 1, K, 64>(a, &lk[K][0][lane], slot[K % PF], acc);
+        consume_link<P, 18, DAG, 1, K, 64, 1>(a, &lk[K][0][lane][0], slot[K % PF], acc);
         if constexpr (K + PF < 8) gather<P, 18, 1, K + PF, false, false>(a, in, 1, cb, c, slot[K % PF]);
         pipeline_sp<P, DAG, PF, K + 1>(a, in, lane, cb, c, lk, slot, acc);
     }
@@ -709,8 +711,8 @@ __device__ __forceinline__ void pipeline_sp(const HopArgs &a, const char *__rest
 // sides) with the links and clover blocks in the LDS arrays lk and lc.
 template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R, int PF = Prefetch<P, 1>::value,
           int CACHE = CachePolicy<P, CLOV>::value>
-__device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, typename PT<P>::S (*lk)[18][64],
-                                                typename PT<P>::S (*lc)[64])
+__device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, typename PT<P>::S (*lk)[9][64][2],
+                                                typename PT<P>::S (*lc)[64][2])
 {
     using Rt = typename PT<P>::R;
     using S = typename PT<P>::S;
@@ -753,7 +755,7 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
                 S raw[72];
                 load_planes<S, 72, true>(a.clov, cb, a.g.vh, raw);
 #pragma unroll
-                for (int i = 0; i < 72; ++i) lc[i][lane] = raw[i];
+                for (int i = 0; i < 72; ++i) lc[i / 2][lane][i % 2] = raw[i];
             }
         }
     }
@@ -767,7 +769,7 @@ __device__ __forceinline__ void hop_shared_body(const HopArgs &a, const int id, 
         S craw[has_block<CLOV>() ? 72 : 1];
         if constexpr (stage_block<P, CLOV>()) {
 #pragma unroll
-            for (int i = 0; i < 72; ++i) craw[i] = lc[i][lane];
+            for (int i = 0; i < 72; ++i) craw[i] = lc[i / 2][lane][i % 2];
         } else if constexpr (has_block<CLOV>()) {
             load_planes<S, 72, true>(a.clov, cb, a.g.vh, craw);
         }
@@ -782,8 +784,8 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
 __global__ __launch_bounds__(64 * R) void hop_shared_kernel(HopArgs a)
 {
     using S = typename PT<P>::S;
-    __shared__ S lk[8][18][64];
-    __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
+    __shared__ S lk[8][9][64][2];
+    __shared__ S lc[stage_block<P, CLOV>() ? 36 : 1][64][2];
     hop_shared_body<P, NL, DAG, CLOV, XPAY, RED, R>(a, blockIdx.x, lk, lc);
 }
 
@@ -793,8 +795,8 @@ template <int P, int NL, bool DAG, int CLOV, bool XPAY, int RED, int R>
 __global__ __launch_bounds__(64 * R) void hop_shared_batch_kernel(HopBatch b)
 {
     using S = typename PT<P>::S;
-    __shared__ S lk[8][18][64];
-    __shared__ S lc[stage_block<P, CLOV>() ? 72 : 1][64];
+    __shared__ S lk[8][9][64][2];
+    __shared__ S lc[stage_block<P, CLOV>() ? 36 : 1][64][2];
     const int t = blockIdx.x;
     int i = 0;
     while (i + 1 < b.nlat && t >= b.tile_off[i + 1]) ++i;
