@@ -130,7 +130,7 @@ void batch_schur(SolveCtx &c, int prec, const FieldView &out, const FieldView &i
     // setting takes them for the fewest right-hand sides of the batch
     int minr = bt->nrhs[0];
     for (int g = 1; g < n; ++g) minr = std::min(minr, bt->nrhs[g]);
-    const int R = (prec != F64 && minr >= 4 && !bt->ops[0]->has_twist && eff_nr(bt->ops[0], prec, minr) == 4) ? 4 : 1;
+    const int R = (prec != F64 && minr >= 4 && eff_nr(bt->ops[0], prec, minr) == 4) ? 4 : 1;
     for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
         HopBatch k1{}, k2{};
         const int nl = std::min(kMaxBatch, n - g0);

@@ -843,21 +843,21 @@ static hipError_t launch_nr(const HopArgs &a, int nr, int block, hipStream_t s)
 // The epilogue combinations the operators use:
 //   (clov, xpay, red) in {(0,0,0) plain hop, (2,0,0) C H x, (1,1,*) C y + c H x,
 //                         (0,1,*) y + c H x, (2,1,0) C (y + c H x), (3,1,*) y + C (c H x)}
-// The twisted-mass epilogues (clov | kTwist), one right-hand side per thread.
+// The twisted-mass epilogues (clov | kTwist).
 template <int P, int NL, bool DAG>
-static hipError_t launch_epi_tw(const HopArgs &a, int clov, bool xpay, int red, int block, hipStream_t s)
+static hipError_t launch_epi_tw(const HopArgs &a, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
     constexpr int T = kTwist;
-    if (!xpay && red == 0 && clov == 2) return launch_nt<P, NL, DAG, T | 2, false, 0, 1>(a, block, s);
+    if (!xpay && red == 0 && clov == 2) return launch_nr<P, NL, DAG, T | 2, false, 0>(a, nr, block, s);
     if (xpay) {
-        if (clov == 1 && red == 0) return launch_nt<P, NL, DAG, T | 1, true, 0, 1>(a, block, s);
-        if (clov == 1 && red == 2) return launch_nt<P, NL, DAG, T | 1, true, 2, 1>(a, block, s);
-        if (clov == 1 && red == 3) return launch_nt<P, NL, DAG, T | 1, true, 3, 1>(a, block, s);
-        if (clov == 2 && red == 0) return launch_nt<P, NL, DAG, T | 2, true, 0, 1>(a, block, s);
+        if (clov == 1 && red == 0) return launch_nr<P, NL, DAG, T | 1, true, 0>(a, nr, block, s);
+        if (clov == 1 && red == 2) return launch_nr<P, NL, DAG, T | 1, true, 2>(a, nr, block, s);
+        if (clov == 1 && red == 3) return launch_nr<P, NL, DAG, T | 1, true, 3>(a, nr, block, s);
+        if (clov == 2 && red == 0) return launch_nr<P, NL, DAG, T | 2, true, 0>(a, nr, block, s);
         if constexpr (!DAG) {
-            if (clov == 3 && red == 0) return launch_nt<P, NL, DAG, T | 3, true, 0, 1>(a, block, s);
-            if (clov == 3 && red == 2) return launch_nt<P, NL, DAG, T | 3, true, 2, 1>(a, block, s);
-            if (clov == 3 && red == 3) return launch_nt<P, NL, DAG, T | 3, true, 3, 1>(a, block, s);
+            if (clov == 3 && red == 0) return launch_nr<P, NL, DAG, T | 3, true, 0>(a, nr, block, s);
+            if (clov == 3 && red == 2) return launch_nr<P, NL, DAG, T | 3, true, 2>(a, nr, block, s);
+            if (clov == 3 && red == 3) return launch_nr<P, NL, DAG, T | 3, true, 3>(a, nr, block, s);
         }
     }
     return hipErrorInvalidValue;
@@ -866,7 +866,7 @@ static hipError_t launch_epi_tw(const HopArgs &a, int clov, bool xpay, int red, 
 template <int P, int NL, bool DAG>
 static hipError_t launch_epi(const HopArgs &a, int clov, bool xpay, int red, int nr, int block, hipStream_t s)
 {
-    if (clov & kTwist) return launch_epi_tw<P, NL, DAG>(a, clov & 3, xpay, red, block, s);
+    if (clov & kTwist) return launch_epi_tw<P, NL, DAG>(a, clov & 3, xpay, red, nr, block, s);
     if (!xpay && red == 0) {
         if (clov == 0) return launch_nr<P, NL, DAG, 0, false, 0>(a, nr, block, s);
         if (clov == 2) return launch_nr<P, NL, DAG, 2, false, 0>(a, nr, block, s);

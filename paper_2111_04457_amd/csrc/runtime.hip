@@ -133,7 +133,7 @@ void hop(lq_op *op, int prec, const FieldView &out, const FieldView &in, int p_o
     // right-hand sides per thread (2, no reductions), or 4 per workgroup
     // sharing the links in LDS (at least 4 right-hand sides)
     int nr = 1;
-    if (in.nrhs > 1 && !(clov_mode & kTwist)) {
+    if (in.nrhs > 1) {
         const int want = eff_nr(op, prec, in.nrhs);
         if (want == 2 && red == 0) nr = 2;
         else if (want == 4 && in.nrhs >= 4) nr = 4;

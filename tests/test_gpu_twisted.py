@@ -178,6 +178,38 @@ def test_twisted_trajectory_reversible_and_second_order(lq):
     assert 3.5 < abs(dh8 / dh16) < 4.5
 
 
+def test_twisted_multi_rhs_shapes_bitwise(lq, case):
+    """Several right-hand sides of a twisted operator: two per thread and
+    four per workgroup (links in LDS) give the bits of one per thread, in
+    every kind and precision, and so does a multi-RHS solve."""
+    U, ref = case
+    op = lq.Operator(DIMS, KAPPA, 0.0, BC, link_recon=12, twist=TAU)
+    op.set_gauge(to_dev(U))
+    nrhs = 5
+    xe = to_dev(np.stack([gaussian_parity_spinor(DIMS, 2640 + i) for i in range(nrhs)]))
+    for p in ("f16", "f32", "f64"):
+        for kind in ("schur", "schur_dag", "schur_left", "schur_normal", "clover_inv_o"):
+            outs = {}
+            for nr in (1, 2, 4):
+                op.set_option("rhs_per_thread_" + p, nr)
+                outs[nr] = to_host(op.apply(kind, xe, p))
+            assert np.array_equal(outs[1], outs[2]) and np.array_equal(outs[1], outs[4]), (p, kind)
+    b = to_dev(gaussian_spinor(DIMS, 2650, nrhs))
+    prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, check_every=4, left_precond=True)
+    res = {}
+    for nr in (1, 4):
+        op.set_option("rhs_per_thread", nr)
+        x, st = op.solve(b, "D", prm)
+        res[nr] = (to_host(x), [s.nconv for s in st])
+    assert np.array_equal(res[1][0], res[4][0]) and res[1][1] == res[4][1]
+    x = res[4][0]
+    bh = to_host(b)
+    for r in range(nrhs):
+        assert oracle.true_residual(ref, x[r], bh[r]) <= 1.01e-10
+    announce("twisted multi-RHS: iterations %s" % res[4][1])
+    op.close()
+
+
 def test_twisted_batch_and_argument_checks(lq):
     dims_list = [(4, 4, 4, 4), (6, 6, 4, 4), (8, 4, 4, 8)]
     prm = lq.SolverParams(tol=1e-10, inner="f16", inner_tol=5e-3, left_precond=True)
