@@ -902,30 +902,55 @@ lq_status lq_mg_create(lq_op *op, const lq_mg_params *p, const void *v0, lq_mg *
         mg->osc.ensure(sizeof(double) * 2 * NSC);
         LQ_HIP(hipMemsetAsync(mg->osc.ptr, 0, sizeof(double) * 2 * NSC, s));
         // near-null vectors: v0, improved by inverse iterations with the
-        // operator's own solver, normalised, in FP32
-        const FieldView b64 = full64(mg, fine64(mg, 0)), x64 = full64(mg, fine64(mg, 1));
+        // operator's own solver, normalised, in FP32; the vectors are solved
+        // together as one multi-RHS solve (in groups that fit an operator
+        // bound to a workspace of fewer right-hand sides)
         lq_solver_params sp;
         lq_solver_params_default(&sp);
         sp.tol = p->setup_tol;
         sp.inner = LQ_F32;
         sp.inner_tol = std::max(1e-5, p->setup_tol * 0.1);
         const long vlex = (long)m.g.vh * 2 * 12 * 2;  // doubles of one complex128 full field
-        double *osc = reinterpret_cast<double *>(mg->osc.ptr);
-        for (int k = 0; k < m.nv; ++k) {
-            for (int par = 0; par < 2; ++par)
-                LQ_HIP(launch_pack_spinor(m.g, par, 0, static_cast<const double *>(v0) + k * vlex,
-                                          full_parity_view(b64.base, F64, m.g, 1, par), s));
-            for (int it = 0; it < p->setup_iters; ++it) {
-                lq_solve_stats st;
-                const lq_status rc = solve_packed(op, sp, 1, x64.base, b64.base, false, &st, s);
-                if (rc < 0) throw Failure{rc, std::string("lq_mg_create: setup solve: ") + get_error()};
-                // b = x / |x|
-                LQ_HIP(launch_reduce(x64, x64, RED_NORM, reinterpret_cast<double *>(mg->part.ptr), s));
-                LQ_HIP(launch_finish(reinterpret_cast<double *>(mg->part.ptr), 1, 2, blas_blocks(m.g.vh), 1, FIN_NORM,
-                                     osc, 0, s));
-                LQ_HIP(launch_copy(b64, x64, osc, 2, true, s));
+        const int grp = op->bound_nrhs ? std::min(m.nv, op->bound_nrhs) : m.nv;
+        const size_t ffb = 2 * (size_t)fb(F64, m.g);  // bytes of one packed FP64 full field
+        Buf sws, ssc, spart;                          // freed when the set-up ends
+        if (p->setup_iters > 0) {
+            sws.ensure(2 * ffb * grp);
+            ssc.ensure(sizeof(double) * NSC * grp);
+            spart.ensure(sizeof(double) * 2 * (size_t)grp * blas_blocks(m.g.vh));
+            LQ_HIP(hipMemsetAsync(ssc.ptr, 0, sizeof(double) * NSC * grp, s));
+        }
+        double *osc = reinterpret_cast<double *>(ssc.ptr);
+        for (int k0 = 0; k0 < m.nv; k0 += grp) {
+            const int n = std::min(grp, m.nv - k0);
+            char *bp = p->setup_iters > 0 ? sws.ptr : fine64(mg, 0);
+            char *xp = p->setup_iters > 0 ? sws.ptr + ffb * grp : fine64(mg, 1);
+            const int nb_ = p->setup_iters > 0 ? n : 1;
+            for (int k = k0; k < k0 + n; ++k) {
+                char *dst = p->setup_iters > 0 ? bp + ffb * (k - k0) : bp;
+                for (int par = 0; par < 2; ++par)
+                    LQ_HIP(launch_pack_spinor(m.g, par, 0, static_cast<const double *>(v0) + k * vlex,
+                                              full_parity_view(dst, F64, m.g, 1, par), s));
+                if (p->setup_iters == 0)
+                    LQ_HIP(launch_copy(full32(mg, mg->vecs.ptr + k * m.vstride), full64(mg, dst), nullptr, 2, false,
+                                       s));
             }
-            LQ_HIP(launch_copy(full32(mg, mg->vecs.ptr + k * m.vstride), b64, osc, 2, false, s));
+            if (p->setup_iters == 0) continue;
+            const FieldView bs{bp, F64, (long)m.g.vh, fb(F64, m.g), 2 * nb_};
+            const FieldView xs{xp, F64, (long)m.g.vh, fb(F64, m.g), 2 * nb_};
+            for (int it = 0; it < p->setup_iters; ++it) {
+                std::vector<lq_solve_stats> st(n);
+                const lq_status rc = solve_packed(op, sp, n, xp, bp, false, st.data(), s);
+                if (rc < 0) throw Failure{rc, std::string("lq_mg_create: setup solve: ") + get_error()};
+                // b = x / |x|, per vector
+                LQ_HIP(launch_reduce(xs, xs, RED_NORM, reinterpret_cast<double *>(spart.ptr), s));
+                LQ_HIP(launch_finish(reinterpret_cast<double *>(spart.ptr), n, 2, blas_blocks(m.g.vh), 1, FIN_NORM,
+                                     osc, 0, s));
+                LQ_HIP(launch_copy(bs, xs, osc, 2, true, s));
+            }
+            for (int k = k0; k < k0 + n; ++k)
+                LQ_HIP(launch_copy(full32(mg, mg->vecs.ptr + k * m.vstride), full64(mg, bp + ffb * (k - k0)), osc, 2,
+                                   false, s));
         }
         mg_orth_kernel<<<m.nagg, MT, 0, s>>>(m, mg->vecs.ptr);
         LQ_HIP(hipGetLastError());
