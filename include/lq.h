@@ -390,7 +390,9 @@ void lq_batch_destroy(lq_batch *batch);
  * nrhs >= 4 in FP16 / FP32, four right-hand sides per workgroup sharing
  * links in LDS; requires every candidate's output to be bitwise equal to
  * the first's, and keeps the fastest on the operator unless the shape the
- * operator had is within 2 % of it.  Results are cached in the JSON file
+ * operator had is within 2 % of it (a shape that beats it in the sweep is
+ * timed against it again, in turn, before it replaces it).  Results are
+ * cached in the JSON file
  * cache_path (or $LQ_TUNE_CACHE; NULL and unset: no cache), keyed by
  * operator form, precision, lattice, link format, nrhs and architecture;
  * cached entries are applied without timing.  report (may be NULL)

@@ -16,7 +16,7 @@
 // every candidate must be bitwise equal to the first candidate's (each
 // site's sum is formed in the same order whatever the launch shape).  The
 // fastest candidate is kept on the operator, unless the shape the operator
-// had before is within 2 % of it.  Results are cached in a JSON file keyed
+// had before is within 2 % of it (checked again by timing the two in turn).  Results are cached in a JSON file keyed
 // by operator form, precision, lattice, link format, right-hand sides and
 // architecture; a cached entry is applied without timing.
 #include <algorithm>
@@ -223,7 +223,8 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                     op->rhs_per_thread[prec] = save_nr;
                     op->halo[prec] = save_halo;
                 };
-                for (const Cand &cd : cands) {
+                // median time of one iteration in shape cd (leaves the shape set)
+                const auto time_shape = [&](const Cand &cd) {
                     op->hop_block[prec] = cd.block;
                     op->xcd_remap[prec] = cd.remap;
                     op->rhs_per_thread[prec] = cd.nr;
@@ -239,7 +240,10 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         LQ_HIP(hipEventElapsedTime(&t[k], e0, e1));
                     }
                     std::sort(t.begin(), t.end());
-                    const double us = 1e3 * t[reps / 2];
+                    return 1e3 * t[reps / 2];
+                };
+                for (const Cand &cd : cands) {
+                    const double us = time_shape(cd);
                     LQ_HIP(hipMemcpyAsync(cur_host.data(), out.base, b, hipMemcpyDeviceToHost, s));
                     LQ_HIP(hipStreamSynchronize(s));
                     if (first) {
@@ -263,7 +267,26 @@ extern "C" lq_status lq_tune(lq_op *op, int nrhs, const char *cache_path, char *
                         default_us = us;
                 }
                 // the shape the operator had unless another is faster by more
-                // than 2 %: closer times are within run-to-run noise
+                // than 2 %: closer times are within run-to-run noise.  A sweep
+                // times each shape once, in sequence; before leaving the
+                // default, the two are timed again in turn (three rounds each,
+                // the medians compared), so that a drift of the clocks during
+                // the sweep does not decide
+                const Cand def{def_nr, save_block, def_remap, save_halo};
+                const bool is_def = best.nr == def.nr && best.block == def.block && best.xcd == def.remap &&
+                                    best.halo == def.halo;
+                if (!is_def && default_us < 1e30 && default_us > 1.02 * best_us) {
+                    const Cand bc{best.nr, best.block, best.xcd, best.halo};
+                    std::vector<double> td, tb;
+                    for (int rnd = 0; rnd < 3; ++rnd) {
+                        td.push_back(time_shape(def));
+                        tb.push_back(time_shape(bc));
+                    }
+                    std::sort(td.begin(), td.end());
+                    std::sort(tb.begin(), tb.end());
+                    default_us = td[1];
+                    best_us = tb[1];
+                }
                 if (default_us <= 1.02 * best_us) {
                     best_us = default_us;
                     best.block = save_block;
